@@ -1,0 +1,195 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does; it
+shares no code with it.  The arithmetic lives in ``oracle.c`` (plain C, FP64,
+OpenMP over targets); this module only builds and marshals.
+
+Functions follow the paper (arXiv 2406.16091):
+  * :func:`bin_particles` -- Sec. 2 binning (cell id, counts, exclusive prefix
+    sum of Fig. 1, stable scatter into cell-sorted order);
+  * :func:`sweep` -- the 27-neighbour-cell sweep of Sec. 2 / Algorithm 1 with
+    the cubic B-spline kernel, over all targets or a subset;
+  * :func:`brute` -- the plain O(N^2) definition of Sec. 2 (all pairs i != j
+    with r_ij < r_c), no grid;
+  * :func:`kernel` -- the B-spline W(r) and dW/dr.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ERANGE = 0, -1, -3
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no fast-math, no FMA
+    contraction: float32 decisions must round exactly as written)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.oracle_kernel.argtypes = [ctypes.c_double, ctypes.c_double, P, P]
+        lib.oracle_kernel.restype = None
+        lib.oracle_cells.argtypes = [I64, P, P, P, P, P, ctypes.c_float, P]
+        lib.oracle_cells.restype = ctypes.c_int
+        lib.oracle_bin.argtypes = [I64, P, P, P, P, P, P, ctypes.c_float, ctypes.c_float,
+                                   P, P, P, P, P, P, P, P, P]
+        lib.oracle_bin.restype = ctypes.c_int
+        lib.oracle_sweep.argtypes = [I64, P, P, P, P, P, ctypes.c_float, P, P, P,
+                                     I64, P, P, P, P, P, P, P, P, ctypes.c_int]
+        lib.oracle_sweep.restype = ctypes.c_int
+        lib.oracle_brute.argtypes = [I64, P, P, P, P, ctypes.c_float, I64, P,
+                                     P, P, P, P, P, P, ctypes.c_int]
+        lib.oracle_brute.restype = ctypes.c_int
+        lib.oracle_max_threads.argtypes = []
+        lib.oracle_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status):
+        super().__init__(f"oracle status {status}")
+        self.status = status
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def kernel(r: float, h: float):
+    """(W(r), dW/dr) of the cubic B-spline with support h."""
+    W = ctypes.c_double()
+    dW = ctypes.c_double()
+    _load().oracle_kernel(float(r), float(h), ctypes.byref(W), ctypes.byref(dW))
+    return W.value, dW.value
+
+
+def cells(x, y, z, origin, dims, cell_w):
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.shape[0]
+    o = _f32(origin)
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    out = np.empty(n, dtype=np.int32)
+    st = _load().oracle_cells(n, _p(x), _p(y), _p(z), _p(o), _p(d), float(cell_w), _p(out))
+    return st, out
+
+
+@dataclass
+class Binned:
+    cell: np.ndarray      # int32 [n]  cell of each particle (original order)
+    counts: np.ndarray    # int32 [n_cells]
+    offsets: np.ndarray   # int32 [n_cells + 1], exclusive, last = n
+    perm: np.ndarray      # int32 [n]  original index of the k-th sorted particle
+    xs: np.ndarray        # float32 [n] cell-relative, sorted order
+    ys: np.ndarray
+    zs: np.ndarray
+    ws: np.ndarray
+    max_per_cell: int
+
+
+def bin_particles(x, y, z, w, origin, dims, cell_w, rc) -> Binned:
+    x, y, z, w = _f32(x), _f32(y), _f32(z), _f32(w)
+    n = x.shape[0]
+    o = _f32(origin)
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    nc = int(d[0]) * int(d[1]) * int(d[2])
+    cell = np.empty(n, np.int32)
+    counts = np.empty(max(nc, 0), np.int32)
+    offsets = np.empty(max(nc, 0) + 1, np.int32)
+    perm = np.empty(n, np.int32)
+    xs, ys, zs, ws = (np.empty(n, np.float32) for _ in range(4))
+    mc = ctypes.c_int32(0)
+    st = _load().oracle_bin(n, _p(x), _p(y), _p(z), _p(w), _p(o), _p(d),
+                            float(cell_w), float(rc), _p(cell), _p(counts), _p(offsets),
+                            _p(perm), _p(xs), _p(ys), _p(zs), _p(ws), ctypes.byref(mc))
+    if st != OK:
+        raise OracleError(st)
+    return Binned(cell, counts, offsets, perm, xs, ys, zs, ws, int(mc.value))
+
+
+@dataclass
+class SweepOut:
+    rho: np.ndarray     # float64 [t]
+    gx: np.ndarray
+    gy: np.ndarray
+    gz: np.ndarray
+    ascale: np.ndarray  # float64 [t]  sum_j w_j |W'(r_ij)|
+    count: np.ndarray   # int64 [t]
+    cand: np.ndarray | None  # int64 [t] candidates in the clipped 27-cell stencil
+
+
+def sweep(x, y, z, w, dims, rc, binned: Binned, targets=None, nthreads: int = 0) -> SweepOut:
+    x, y, z, w = _f32(x), _f32(y), _f32(z), _f32(w)
+    n = x.shape[0]
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    rho, gx, gy, gz, a = (np.empty(nt, np.float64) for _ in range(5))
+    cnt = np.empty(nt, np.int64)
+    cand = np.empty(nt, np.int64)
+    st = _load().oracle_sweep(n, _p(x), _p(y), _p(z), _p(w), _p(d), float(rc),
+                              _p(binned.cell), _p(binned.offsets), _p(binned.perm),
+                              nt, _p(tg), _p(rho), _p(gx), _p(gy), _p(gz), _p(a),
+                              _p(cnt), _p(cand), int(nthreads))
+    if st != OK:
+        raise OracleError(st)
+    return SweepOut(rho, gx, gy, gz, a, cnt, cand)
+
+
+def brute(x, y, z, w, rc, targets=None, nthreads: int = 0) -> SweepOut:
+    x, y, z, w = _f32(x), _f32(y), _f32(z), _f32(w)
+    n = x.shape[0]
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    rho, gx, gy, gz, a = (np.empty(nt, np.float64) for _ in range(5))
+    cnt = np.empty(nt, np.int64)
+    st = _load().oracle_brute(n, _p(x), _p(y), _p(z), _p(w), float(rc), nt, _p(tg),
+                              _p(rho), _p(gx), _p(gy), _p(gz), _p(a), _p(cnt), int(nthreads))
+    if st != OK:
+        raise OracleError(st)
+    return SweepOut(rho, gx, gy, gz, a, cnt, None)
+
+
+def invariants(w, out: SweepOut):
+    """Global invariants of a full sweep (targets in original order):
+    P = sum_i count_i, F = sum_i w_i G_i (zero by Newton's third law on the
+    antisymmetric pair terms), S = sum_i w_i A_i (scale for F)."""
+    w = np.asarray(w, dtype=np.float64)
+    P = int(out.count.sum())
+    F = np.array([(w * out.gx).sum(), (w * out.gy).sum(), (w * out.gz).sum()])
+    S = float((w * out.ascale).sum())
+    return P, F, S

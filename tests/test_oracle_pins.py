@@ -1,0 +1,414 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle itself.
+
+Each test names what fixes the expected value: the paper's worked examples
+(Fig. 1, the Sec. 6 scan example, Table 1's first column), closed forms of the
+B-spline, its unit integral, exact integer arithmetic on the input lattice,
+Newton's third law, brute force, and statistical means of uniform systems.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from paper_2406_16091_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split(":", 1) if ":" in line else (None, line)
+            if k is None:
+                out.setdefault("rows", []).append([float(t) for t in v.split()])
+            else:
+                out.setdefault(k.strip(), []).append([float(t) for t in v.split()])
+    return out
+
+
+# ---------------------------------------------------------------- Fig. 1
+
+def test_fig1_counts_and_offsets(oracle_lib):
+    g = _read_golden("fig1_binning.txt")
+    pts = np.array(g["particle"], dtype=np.float32)
+    origin = g["origin"][0]
+    dims = [int(v) for v in g["dims"][0]]
+    cw = g["cell_w"][0][0]
+    b = oracle.bin_particles(pts[:, 0], pts[:, 1], pts[:, 2], np.ones(len(pts)),
+                             origin, dims, cw, cw)
+    assert b.counts.tolist() == [int(v) for v in g["counts"][0]]
+    assert b.offsets.tolist() == [int(v) for v in g["offsets"][0]]
+    assert b.max_per_cell == 3
+    # stable order inside each cell: ascending index of the figure's drawing order
+    assert b.perm.tolist() == [0, 1, 2, 3, 4, 5, 7, 8, 6]
+
+
+# ---------------------------------------------------------------- Sec. 6 scan
+
+def _paper_tree_scan(a, downward_init_div):
+    """The in-place upward/downward tree scan of Sec. 6, sequential form.
+    downward_init_div = 2 is the appendix listing's restart of the downward
+    pass, 4 the algorithm box's.  Returns (final, states)."""
+    p = list(a)
+    n = len(p)
+    states = []
+    js = 2
+    while js <= n:
+        h = js // 2
+        for i in range(js - 1, n, js):
+            p[i] += p[i - h]
+        states.append(list(p))
+        js *= 2
+    js = max(4, js // downward_init_div)
+    while js > 1:
+        h = js // 2
+        for i in range(js + h - 1, n, js):
+            p[i] += p[i - h]
+        states.append(list(p))
+        js = h
+    return p, states
+
+
+def test_scan_worked_example():
+    g = _read_golden("scan_vectors.txt")
+    final, states = _paper_tree_scan([int(v) for v in g["input"][0]], 2)
+    want = [g[k][0] for k in ("up1", "up2", "up3")]
+    assert [s for s in states[:3]] == [[int(v) for v in w] for w in want]
+    # the downward pass of the listing visits the 4-step level first; it is a
+    # no-op on 8 entries (index 5 is the first updated), matching down1
+    assert states[-2] == [int(v) for v in g["down1"][0]]
+    assert final == [int(v) for v in g["down2"][0]]
+
+
+def test_scan_erratum_algorithm_box():
+    """The algorithm box restarts the downward pass at js/4 and leaves the
+    last entry wrong for 12 ones (it stays 4); the listing (js/2) is right."""
+    ones = [1] * 12
+    good, _ = _paper_tree_scan(ones, 2)
+    bad, _ = _paper_tree_scan(ones, 4)
+    assert good == list(range(1, 13))
+    assert bad[-1] == 4
+
+
+def test_oracle_offsets_equal_paper_scan(oracle_lib):
+    """The oracle's exclusive offsets equal the listing's inclusive tree scan
+    shifted by one, for many lengths and count vectors."""
+    rng = np.random.default_rng(7)
+    for ncell in list(range(1, 40)) + [63, 64, 65, 127, 128, 200, 1000]:
+        counts = rng.integers(0, 4, size=ncell)
+        # one particle row per cell along x, cell width 1, rc = 1
+        xs = np.repeat(np.arange(ncell), counts).astype(np.float64) + 0.5
+        n = xs.size
+        b = oracle.bin_particles(xs, np.full(n, 0.5), np.full(n, 0.5), np.ones(n),
+                                 (0, 0, 0), (ncell, 1, 1), 1.0, 1.0)
+        incl, _ = _paper_tree_scan(counts.tolist(), 2)
+        assert b.counts.tolist() == counts.tolist()
+        assert b.offsets.tolist() == [0] + incl
+
+
+# ---------------------------------------------------------------- Table 1
+
+def _table1_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_candidates.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                d, p, v = line.split()
+                rows.append((int(d), int(p), float(v)))
+    return rows
+
+
+@pytest.mark.parametrize("d,p,printed", [r for r in _table1_rows() if r[0] ** 3 * r[1] <= 500_000])
+def test_table1_candidates(oracle_lib, d, p, printed):
+    n = d ** 3 * p
+    rng = np.random.default_rng(1000 + d * 7 + p)
+    m = rng.integers(0, 1 << 24, size=(3, n))
+    x, y, z = (m.astype(np.float64) * 2.0 ** -24).astype(np.float32)
+    w = np.ones(n, np.float32)
+    rc = 1.0 / d
+    b = oracle.bin_particles(x, y, z, w, (0, 0, 0), (d, d, d), rc, rc)
+    s = oracle.sweep(x, y, z, w, (d, d, d), rc, b)
+    mean = s.cand.mean()
+    if d == 2:
+        # every particle's clipped stencil covers the whole 2x2x2 grid
+        assert (s.cand == n - 1).all() and int(round(printed)) == n - 1
+    else:
+        expect = (n - 1) * ((3 * d - 2) / d ** 2) ** 3   # non-periodic clipping
+        tol = 0.02 if n >= 4096 else 0.15
+        assert abs(mean - printed) / printed < tol
+        assert abs(mean - expect) / expect < tol
+
+
+# ---------------------------------------------------------------- kernel
+
+SIG = 8.0 / math.pi  # sigma at h = 1
+
+
+@pytest.mark.parametrize("q,w_over_sigma,dw_h_over_sigma", [
+    (0.0, 1.0, 0.0), (0.25, 0.71875, -1.875), (0.5, 0.25, -1.5),
+    (0.75, 1.0 / 32.0, -0.375), (1.0, 0.0, 0.0), (1.5, 0.0, 0.0)])
+def test_kernel_closed_forms(oracle_lib, q, w_over_sigma, dw_h_over_sigma):
+    for h in (1.0, 2.0 ** -5, 3.0):
+        sigma = 8.0 / (math.pi * h ** 3)
+        W, dW = oracle.kernel(q * h, h)
+        assert W == pytest.approx(sigma * w_over_sigma, rel=1e-14, abs=1e-300)
+        assert dW == pytest.approx(sigma / h * dw_h_over_sigma, rel=1e-14, abs=1e-300)
+
+
+def test_kernel_unit_integral(oracle_lib):
+    for h in (1.0, 2.0 ** -5, 0.37):
+        val, err = integrate.quad(lambda r: 4.0 * math.pi * r * r * oracle.kernel(r, h)[0],
+                                  0.0, h, points=[0.5 * h], epsabs=0, epsrel=1e-13)
+        assert val == pytest.approx(1.0, rel=1e-11)
+
+
+def test_kernel_derivative_matches_finite_difference(oracle_lib):
+    h = 1.0
+    for r in np.linspace(0.01, 0.99, 97):
+        if abs(r - 0.5) < 1e-3:
+            continue
+        e = 1e-6
+        fd = (oracle.kernel(r + e, h)[0] - oracle.kernel(r - e, h)[0]) / (2 * e)
+        assert oracle.kernel(r, h)[1] == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+def test_kernel_continuous_at_half(oracle_lib):
+    a = oracle.kernel(0.5 - 1e-12, 1.0)
+    b = oracle.kernel(0.5 + 1e-12, 1.0)
+    assert a[0] == pytest.approx(b[0], rel=1e-9)
+    assert a[1] == pytest.approx(b[1], rel=1e-9)
+
+
+# ---------------------------------------------------------------- closed-form systems
+
+def _run(x, y, z, w, dims, cw, rc, origin=(0, 0, 0)):
+    b = oracle.bin_particles(x, y, z, w, origin, dims, cw, rc)
+    return b, oracle.sweep(x, y, z, w, dims, rc, b)
+
+
+def test_two_particles_quarter_support(oracle_lib):
+    # r = h/4 along x; h = rc = 1, unit cells, box [0,4)^3
+    x = np.array([1.5, 1.75], np.float32)
+    y = np.array([2.0, 2.0], np.float32)
+    z = np.array([2.0, 2.0], np.float32)
+    w = np.array([0.75, 1.25], np.float32)
+    _, s = _run(x, y, z, w, (4, 4, 4), 1.0, 1.0)
+    assert s.count.tolist() == [1, 1]
+    assert s.rho[0] == pytest.approx(1.25 * SIG * 0.71875, rel=1e-14)
+    assert s.rho[1] == pytest.approx(0.75 * SIG * 0.71875, rel=1e-14)
+    # gradient of particle 0 points toward particle 1 (+x): -w1 W'(h/4)
+    assert s.gx[0] == pytest.approx(1.25 * SIG * 1.875, rel=1e-14)
+    assert s.gx[1] == pytest.approx(-0.75 * SIG * 1.875, rel=1e-14)
+    assert s.gy.tolist() == [0.0, 0.0] and s.gz.tolist() == [0.0, 0.0]
+    assert s.ascale[0] == pytest.approx(1.25 * SIG * 1.875, rel=1e-14)
+
+
+def test_two_particles_diagonal_three_quarter(oracle_lib):
+    # separation (0.375, 0.5, 0) * 1.2 -> r = 0.75 with h = 1
+    x = np.array([1.0, 1.45], np.float32)
+    y = np.array([1.0, 1.6], np.float32)
+    z = np.array([1.0, 1.0], np.float32)
+    dx, dy = float(x[0]) - float(x[1]), float(y[0]) - float(y[1])
+    r = math.hypot(dx, dy)
+    w = np.array([1.0, 1.0], np.float32)
+    _, s = _run(x, y, z, w, (3, 3, 3), 1.0, 1.0)
+    q = r
+    W = 2 * SIG * (1 - q) ** 3
+    dW = -6 * SIG * (1 - q) ** 2
+    assert s.rho[0] == pytest.approx(W, rel=1e-12)
+    assert s.gx[0] == pytest.approx(dW * dx / r, rel=1e-12)
+    assert s.gy[0] == pytest.approx(dW * dy / r, rel=1e-12)
+
+
+def test_coincident_particles(oracle_lib):
+    x = np.array([0.5, 0.5, 2.5], np.float32)
+    w = np.array([1.0, 2.0, 1.0], np.float32)
+    _, s = _run(x, x, x, w, (3, 3, 3), 1.0, 1.0)
+    assert s.count.tolist() == [1, 1, 0]
+    assert s.rho[0] == pytest.approx(2.0 * SIG, rel=1e-15)
+    assert s.rho[1] == pytest.approx(1.0 * SIG, rel=1e-15)
+    assert s.rho[2] == 0.0
+    assert s.gx.tolist() == [0.0, 0.0, 0.0]
+
+
+def test_cutoff_is_strict_exact(oracle_lib):
+    # rc = 0.625 = 5/8; (0.375, 0.5) is a 3-4-5 triangle with r == rc exactly
+    rc = 0.625
+    x = np.array([1.0, 1.375, 1.0, 1.625, 1.0], np.float32)
+    y = np.array([1.0, 1.5, 2.5, 2.5, 3.75], np.float32)
+    z = np.array([1.0, 1.0, 1.0, 1.0, 1.0], np.float32)
+    # pairs: (0,1) r = rc exactly -> excluded; (2,3) r = rc on axis -> excluded
+    w = np.ones(5, np.float32)
+    _, s = _run(x, y, z, w, (8, 8, 8), rc, rc)
+    assert s.count.tolist() == [0, 0, 0, 0, 0]
+    # one lattice step closer on each: included
+    u = 2.0 ** -20
+    x2 = x.copy()
+    x2[1] = np.float32(1.375 - u)
+    x2[3] = np.float32(1.625 - u)
+    _, s2 = _run(x2, y, z, w, (8, 8, 8), rc, rc)
+    assert s2.count.tolist() == [1, 1, 1, 1, 0]
+
+
+def test_predicate_exact_on_lattice(oracle_lib):
+    """Near-shell pairs: the oracle's FP64 test equals exact integer
+    arithmetic on the lattice indices (no rounding decides a count)."""
+    rng = np.random.default_rng(11)
+    p = 24
+    rc = 2.0 ** -5
+    k_rc = int(rc * 2 ** p)
+    n = 3000
+    base = rng.integers(4 * k_rc, (1 << p) - 4 * k_rc, size=(n, 3))
+    # partner at distance ~rc along a random direction, jittered by a few units
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    off = np.round(d * k_rc).astype(np.int64) + rng.integers(-2, 3, size=(n, 3))
+    m = np.concatenate([base, base + off])
+    m = np.clip(m, 0, (1 << p) - 1)
+    x, y, z = (m.T.astype(np.float64) * 2.0 ** -p).astype(np.float32)
+    w = np.ones(2 * n, np.float32)
+    s = oracle.brute(x, y, z, w, rc)
+    mi = np.stack([(np.float64(v) * 2 ** p).astype(np.int64) for v in (x, y, z)], 1)
+    want = np.zeros(2 * n, np.int64)
+    for i in range(2 * n):
+        dd = mi - mi[i]
+        d2 = (dd * dd).sum(1)
+        d2[i] = k_rc * k_rc  # exclude self
+        want[i] = int((d2 < k_rc * k_rc).sum())
+    assert (s.count == want).all()
+
+
+# ---------------------------------------------------------------- brute vs cells
+
+@pytest.mark.parametrize("case", ["uniform", "clustered", "wide_cells", "offset_origin", "flat"])
+def test_cells_match_brute(oracle_lib, case):
+    if case == "uniform":
+        s = synth.uniform_unit_cube(4096, -4, seed=3)
+        sysx = (s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    elif case == "clustered":
+        s = synth.clustered(n=3000, n_blobs=4, rc_log2=-4, seed=9)
+        sysx = (s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    elif case == "wide_cells":
+        s = synth.box_system(2500, 6, seed=5, lattice_log2=18)
+        sysx = (s.x, s.y, s.z, s.w, s.origin, s.dims, 1.0, 0.8)
+    elif case == "offset_origin":
+        s = synth.box_system(2000, 7, seed=6, lattice_log2=18)
+        sh = np.float32(-3.0)
+        sysx = (s.x + sh, s.y + sh, s.z + sh, s.w, (-3.0, -3.0, -3.0), s.dims, 1.0, 1.0)
+    else:
+        s = synth.box_system(2000, 12, seed=8, lattice_log2=18)
+        sysx = (s.x, s.y, (s.z * np.float32(1 / 12.0)).astype(np.float32) * 0,
+                s.w, s.origin, (12, 12, 1), 1.0, 1.0)
+    x, y, z, w, origin, dims, cw, rc = sysx
+    b = oracle.bin_particles(x, y, z, w, origin, dims, cw, rc)
+    c = oracle.sweep(x, y, z, w, dims, rc, b)
+    r = oracle.brute(x, y, z, w, rc)
+    assert (c.count == r.count).all()
+    assert c.count.sum() > 0
+    for a, bb, sc in ((c.rho, r.rho, r.rho), (c.gx, r.gx, r.ascale),
+                      (c.gy, r.gy, r.ascale), (c.gz, r.gz, r.ascale)):
+        assert np.all(np.abs(a - bb) <= 1e-12 * sc + 1e-300)
+
+
+# ---------------------------------------------------------------- definitions
+
+def test_binning_matches_independent_definition(oracle_lib):
+    s = synth.box_system(5000, 9, seed=12, lattice_log2=18)
+    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    # cell: float32 floor((x - o) / w), X fastest
+    ix, iy, iz = (np.floor((v - np.float32(0)) / np.float32(s.cell_w)).astype(np.int64)
+                  for v in (s.x, s.y, s.z))
+    cell = ix + s.dims[0] * (iy + s.dims[1] * iz)
+    assert (b.cell == cell).all()
+    counts = np.bincount(cell, minlength=s.n_cells)
+    assert (b.counts == counts).all()
+    assert (b.offsets == np.concatenate([[0], np.cumsum(counts)])).all()
+    perm = np.argsort(cell, kind="stable")
+    assert (b.perm == perm).all()
+    assert b.max_per_cell == counts.max()
+    for rel, v, i in ((b.xs, s.x, ix), (b.ys, s.y, iy), (b.zs, s.z, iz)):
+        want = (v.astype(np.float64) - i * float(s.cell_w))[perm].astype(np.float32)
+        assert (rel == want).all()
+    assert (b.ws == s.w[perm]).all()
+
+
+def test_out_of_box_and_bad_grid(oracle_lib):
+    x = np.array([0.5, 1.0], np.float32)  # 1.0 is on the far face: outside [0, 1)
+    y = np.array([0.5, 0.5], np.float32)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bin_particles(x, y, y, y, (0, 0, 0), (2, 2, 2), 0.5, 0.5)
+    assert e.value.status == oracle.ERANGE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bin_particles(np.array([np.nan], np.float32), y[:1], y[:1], y[:1],
+                             (0, 0, 0), (2, 2, 2), 0.5, 0.5)
+    assert e.value.status == oracle.ERANGE
+    with pytest.raises(oracle.OracleError) as e:  # cell width below the cutoff
+        oracle.bin_particles(x[:1], y[:1], y[:1], y[:1], (0, 0, 0), (2, 2, 2), 0.5, 0.6)
+    assert e.value.status == oracle.EINVAL
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bin_particles(x[:1], y[:1], y[:1], y[:1], (0, 0, 0), (0, 2, 2), 0.5, 0.5)
+    assert e.value.status == oracle.EINVAL
+
+
+def test_empty_system(oracle_lib):
+    e = np.zeros(0, np.float32)
+    b = oracle.bin_particles(e, e, e, e, (0, 0, 0), (3, 2, 1), 1.0, 1.0)
+    assert b.counts.tolist() == [0] * 6 and b.offsets.tolist() == [0] * 7
+    s = oracle.sweep(e, e, e, e, (3, 2, 1), 1.0, b)
+    assert s.count.size == 0
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_newton_third_law_and_symmetry(oracle_lib):
+    s = synth.clustered(n=20000, n_blobs=8, rc_log2=-5, seed=21)
+    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    o = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b)
+    P, F, S = oracle.invariants(s.w, o)
+    assert P % 2 == 0 and P > 0
+    assert np.all(np.abs(F) <= 1e-13 * S)
+
+
+def test_translation_and_permutation_invariance(oracle_lib):
+    s = synth.box_system(3000, 8, seed=22, lattice_log2=18)
+    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, 1.0, 1.0)
+    o = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, 1.0, b)
+    # shift by whole cells into a larger box
+    sh = np.float32(2.0)
+    b2 = oracle.bin_particles(s.x + sh, s.y, s.z + sh, s.w, (0, 0, 0), (11, 8, 12), 1.0, 1.0)
+    o2 = oracle.sweep(s.x + sh, s.y, s.z + sh, s.w, (11, 8, 12), 1.0, b2)
+    assert (o.count == o2.count).all()
+    assert np.all(np.abs(o.rho - o2.rho) <= 1e-13 * o.rho)
+    # permute the input order
+    pi = np.random.default_rng(1).permutation(s.n)
+    b3 = oracle.bin_particles(s.x[pi], s.y[pi], s.z[pi], s.w[pi], s.origin, s.dims, 1.0, 1.0)
+    o3 = oracle.sweep(s.x[pi], s.y[pi], s.z[pi], s.w[pi], s.dims, 1.0, b3)
+    assert (o3.count == o.count[pi]).all()
+    assert (b3.offsets == b.offsets).all()
+    assert np.all(np.abs(o3.gx - o.gx[pi]) <= 1e-13 * o.ascale[pi] + 1e-300)
+
+
+# ---------------------------------------------------------------- statistics
+
+def test_uniform_statistics_tiny(oracle_lib):
+    """Uniform unit cube, 32^3 cells, r_c = 1/32: interior particles see on
+    average (N-1)(4 pi/3) r_c^3 neighbours and rho = (N-1) E[w] (unit
+    integral of W); the total ordered pair count is about 1.325e5."""
+    s = synth.tiny()
+    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    o = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b)
+    rc = s.rc
+    inner = ((s.x >= rc) & (s.x < 1 - rc) & (s.y >= rc) & (s.y < 1 - rc)
+             & (s.z >= rc) & (s.z < 1 - rc))
+    n = s.n
+    assert o.count[inner].mean() == pytest.approx((n - 1) * 4 * math.pi / 3 * rc ** 3, rel=0.02)
+    assert o.rho[inner].mean() == pytest.approx((n - 1) * 1.0, rel=0.02)
+    assert o.count.sum() == pytest.approx(1.325e5, rel=0.02)
+    assert o.cand.mean() == pytest.approx((n - 1) * ((3 * 32 - 2) / 32 ** 2) ** 3, rel=0.01)
