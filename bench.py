@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the hot path on one MI355X: cutoff pair-interactions/s.
+
+One step = pi_bin (cell ids, counts, prefix sum, stable scatter) followed by
+pi_interact (27-cell sweep, compensated FP32, with the FP64 invariant
+reductions) over a system already resident in HBM.  The default workload is
+2^24 uniform particles in the unit cube, r_c = 1/256, 256^3 cells (one
+particle per cell).  value = ordered cutoff pairs per step / step time.
+
+    python bench.py [--steps K] [--warmup W] [--workload scale_1ppc]
+
+Prints one JSON line.  Per-kernel device times come from the library's own
+hipEvent timing (pi_timing_*), recorded on the launch stream over the timed
+region.  The CPU baseline is the FP64 oracle (oracle/) timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cutoff pair-interactions/s at 1 ppc (16.8M particles); p99 latency at fixed QPS"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+# Algorithmic FLOPs of the sweep (FMA = 2, other arithmetic = 1; compares,
+# integer work not counted): every candidate pays 3 sub + 1 mul + 2 FMA = 8;
+# every accepted pair of the compensated path pays 72 on average (see the
+# accounting in the design notes).
+FLOP_PER_CANDIDATE = 8.0
+FLOP_PER_PAIR_COMPENSATED = 72.0
+
+WORKLOADS = {
+    "scale_1ppc": ("uniform 2^24 particles, unit cube, r_c=1/256, 256^3 cells (1 ppc)", "scale_1ppc"),
+    "scale_8ppc": ("uniform 2^24 particles, unit cube, r_c=1/128, 128^3 cells (8 ppc)", "scale_8ppc"),
+    "clustered": ("2^23 particles, 64 Gaussian blobs + 10% uniform, r_c=1/128, 128^3 cells", "clustered"),
+    "tiny": ("uniform 32768 particles, unit cube, r_c=1/32, 32^3 cells", "tiny"),
+}
+
+
+def algorithmic_bytes(name: str, n: int, nc: int, orig_order: bool) -> float:
+    """Compulsory HBM bytes of one launch: every input read once, every output
+    written once, at 4 bytes per int32/float32 element."""
+    if name == "k_fill_i32":
+        return 4.0 * nc
+    if name == "k_bin_count":
+        return 12.0 * n + 8.0 * n + 8.0 * nc          # x,y,z in; cell,slot out; counts RMW
+    if name in ("k_scan_reduce",):
+        return 4.0 * nc
+    if name == "k_scan_down":
+        return 8.0 * nc                               # counts in, offsets out
+    if name == "k_bin_scatter":
+        return 12.0 * n + 4.0 * nc                    # cell,slot in, perm_u out; offsets
+    if name == "k_bin_finalize":
+        return 48.0 * n + 4.0 * nc                    # perm_u,cell_in,x,y,z,w in; 6 arrays out
+    if name.startswith("k_sweep"):
+        return 40.0 * n + 4.0 * nc + (4.0 * n if orig_order else 0.0)
+    return 0.0
+
+
+def candidates_from_counts(counts: np.ndarray, dims) -> int:
+    """Sum over targets of sources in the clipped 27-cell stencil, minus self
+    (measurement bookkeeping for the FLOP count)."""
+    from scipy import ndimage
+    c = counts.reshape(dims[2], dims[1], dims[0]).astype(np.int64)
+    nb = ndimage.convolve(c, np.ones((3, 3, 3), np.int64), mode="constant", cval=0)
+    return int((c * nb).sum() - c.sum())
+
+
+def cpu_baseline(system, budget_s: float = 30.0):
+    import oracle
+    t0 = time.perf_counter()
+    b = oracle.bin_particles(system.x, system.y, system.z, system.w, system.origin, system.dims,
+                             system.cell_w, system.rc)
+    t_bin = time.perf_counter() - t0
+    n = system.n
+    # sweep over all targets if the estimate fits the budget, else a subsample
+    from paper_2406_16091_amd import synth
+    probe = synth.subsample(n, min(n, 200_000), seed=20)
+    t0 = time.perf_counter()
+    oracle.sweep(system.x, system.y, system.z, system.w, system.dims, system.rc, b, targets=probe)
+    t_probe = time.perf_counter() - t0
+    est = t_probe * n / max(len(probe), 1)
+    if t_bin + est <= budget_s:
+        targets, label = None, f"full workload: bin + sweep of all {n} targets"
+    else:
+        m = int(len(probe) * (budget_s - t_bin) / max(t_probe, 1e-9))
+        m = max(10_000, min(n, m))
+        targets = synth.subsample(n, m, seed=20)
+        label = f"bin all {n} + sweep of {m} sampled targets (pairs scaled by {n}/{m})"
+    t0 = time.perf_counter()
+    o = oracle.sweep(system.x, system.y, system.z, system.w, system.dims, system.rc, b, targets=targets)
+    t_sweep = time.perf_counter() - t0
+    pairs = float(o.count.sum())
+    if targets is not None:
+        # time per full step = bin + sweep scaled to all targets
+        frac = len(targets) / n
+        t_sweep /= frac
+        pairs /= frac
+    value = pairs / (t_bin + t_sweep)
+    return {"value": value, "unit": "pairs/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": label, "bin_s": round(t_bin, 3), "sweep_s": round(t_sweep, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="scale_1ppc", choices=sorted(WORKLOADS))
+    ap.add_argument("--sweep", default="auto")
+    ap.add_argument("--tile", default="0,0,0")
+    ap.add_argument("--precision", default="compensated")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the library has no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    from paper_2406_16091_amd import device, pi, synth
+
+    desc, gen = WORKLOADS[args.workload]
+    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+    system = getattr(synth, gen)()
+    ds = device.DeviceSystem(system)
+    ctx = ds.ctx.handle
+    tile = tuple(int(v) for v in args.tile.split(","))
+
+    def step():
+        ds.bin()
+        ds.interact(precision=args.precision, sweep=args.sweep, tile=tile, invariants=True)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    ds.sync()
+    torch.cuda.synchronize()
+
+    pi.pi_timing_reset(ctx)
+    pi.pi_timing_enable(ctx, not args.no_timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pi.pi_timing_enable(ctx, False)
+    ds.sync()
+    kt = pi.pi_timing_read(ctx) if not args.no_timing else {}
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    inv = ds.invariants()
+    pairs = inv["pairs"]
+    b = ds.binned()
+    n, nc = system.n, system.n_cells
+    cand = candidates_from_counts(b["counts"], system.dims)
+    value = pairs / (ms_per_step * 1e-3)
+
+    kernels = {k: {"launches": v[0], "avg_us": round(v[1] * 1e3 / max(v[0], 1), 3)} for k, v in kt.items()}
+    roof = None
+    stages = {}
+    if kt:
+        dom = max(kt.items(), key=lambda kv: kv[1][1])
+        name, (launches, total_ms) = dom
+        avg_s = total_ms * 1e-3 / launches
+        by = algorithmic_bytes(name, n, nc, False)
+        if name.startswith("k_sweep"):
+            flops = FLOP_PER_CANDIDATE * cand + FLOP_PER_PAIR_COMPENSATED * pairs
+            t_hbm = by / (HBM_PEAK_GBS * 1e9)
+            t_alu = flops / (FP32_PEAK_TFLOPS * 1e12)
+            bound = "hbm" if t_hbm >= t_alu else "alu"
+        else:
+            flops, bound = 0.0, "hbm"
+        if bound == "hbm":
+            ach = by / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": by}
+        else:
+            ach = flops / avg_s / 1e12
+            roof = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None, "kernel": name,
+                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_flops": flops}
+        bin_us = sum(v[1] for k, v in kt.items() if not k.startswith(("k_sweep", "k_inv"))) * 1e3 / args.steps
+        sw = [(k, v) for k, v in kt.items() if k.startswith("k_sweep")]
+        sweep_us = sum(v[1] for _, v in sw) * 1e3 / args.steps
+        bin_bytes = 48.0 * n + 16.0 * nc
+        stages = {"bin_us": round(bin_us, 2), "sweep_us": round(sweep_us, 2),
+                  "bin_hbm_frac_algorithmic": round(bin_bytes / (bin_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                  "sweep_fp32_frac": round((FLOP_PER_CANDIDATE * cand + FLOP_PER_PAIR_COMPENSATED * pairs)
+                                           / (sweep_us * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 4)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "n_cells": nc, "rc": system.rc,
+                   "sweep": args.sweep, "precision": args.precision,
+                   "pairs_per_step": pairs, "candidate_pairs_per_step": cand,
+                   "candidate_pairs_per_s": round(cand / (ms_per_step * 1e-3), 1)},
+        "roofline": roof,
+        "stages": stages,
+        "kernels": kernels,
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(system)
+    if rank == 0:
+        print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

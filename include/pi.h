@@ -1,0 +1,221 @@
+/*
+ * pi.h -- C ABI of the MI355X (gfx950) library for grid-binned short-range
+ * pair interactions with a cutoff radius when each cell holds few particles.
+ *
+ * Method: Algis, Bramas, Darles, Aveneau, "Efficient GPU Implementation of
+ * Particle Interactions with Cutoff Radius and Few Particles per Cell"
+ * (arXiv 2406.16091).  The library implements the paper's GPU pipeline of
+ * Sec. 2 ("Background"): per-particle cell index, per-cell counts, exclusive
+ * prefix sum, scatter into a cell-sorted particle order, then the
+ * 27-neighbour-cell interaction sweep over every pair i != j with
+ * r_ij < r_c, with the sweep organisations of Sec. 4 (one thread per
+ * particle, no shared memory) and Sec. 5 (X-pencil and full sub-box tiles
+ * staged in LDS).
+ *
+ * Conventions for every entry point:
+ *   - All particle arrays are structure-of-arrays, float32 or int32, in
+ *     DEVICE memory, owned by the caller, and must stay valid until the work
+ *     queued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as an opaque pointer (NULL = the null
+ *     stream).  Every call only queues work on it and returns; nothing
+ *     blocks except pi_sync and pi_timing_read.
+ *   - Errors the host can see (bad pointers, sizes, grid) are returned at
+ *     once and nothing is queued.  Errors only the device can see (a particle
+ *     outside the box) are latched in the pi_cells object and returned by the
+ *     next pi_sync on it; the outputs of the failing call are unspecified but
+ *     every kernel stays inside its buffers.
+ *   - No call throws; every call is safe to make from any host thread as
+ *     long as one pi_cells object is not used by two calls at once.
+ */
+#ifndef PI_H
+#define PI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pi_status;
+#define PI_OK          0
+#define PI_EINVAL     (-1)  /* bad argument: pointer, size, grid, option */
+#define PI_ENOMEM     (-2)  /* device allocation failed / budget exceeded */
+#define PI_ERANGE     (-3)  /* a particle lies outside the grid's box */
+#define PI_EDEVICE    (-4)  /* a HIP runtime call failed */
+#define PI_EAGAIN     (-5)  /* try again later (queue or slots full) */
+#define PI_ENOTFOUND  (-6)  /* unknown handle or ticket */
+#define PI_ESTATE     (-7)  /* call out of order (e.g. interact before bin) */
+
+typedef void *pi_stream; /* hipStream_t */
+
+/*
+ * Regular grid over the box [origin, origin + dims * cell_w) (Sec. 2: the
+ * domain is divided into a regular grid; Sec. 3: the cell width is at least
+ * the cutoff, so every neighbour of a particle lies in its cell or one of
+ * the 26 cells around it).  The grid is not periodic: the 27-cell stencil is
+ * clipped at its faces.
+ *   dims[a] >= 1, each <= 2^24, dims[0]*dims[1]*dims[2] < 2^31;
+ *   0 < rc <= cell_w, both finite.
+ * Cells are numbered X fastest: c = ix + dims[0] * (iy + dims[1] * iz)
+ * (Fig. 1).  Particle axis index: t = (x - origin) / cell_w evaluated in
+ * float32 with IEEE rounding, inside iff 0 <= t < dims, index floor(t).
+ */
+typedef struct pi_grid {
+    float origin[3];
+    int32_t dims[3];
+    float cell_w;
+    float rc;
+} pi_grid;
+
+typedef struct pi_ctx pi_ctx;     /* one per device */
+typedef struct pi_cells pi_cells; /* a binned system, resident in HBM */
+
+/* Create a context on HIP device `device` (made current for the calling
+ * thread).  *out receives the handle.  PI_EDEVICE if the device is absent. */
+pi_status pi_ctx_create(int32_t device, pi_ctx **out);
+/* Destroy a context.  All pi_cells made from it must be destroyed first. */
+pi_status pi_ctx_destroy(pi_ctx *ctx);
+
+/* Create an empty cell structure.  Device buffers are allocated by pi_bin
+ * and grown when a later pi_bin needs more; they are freed by
+ * pi_cells_destroy.  The object is owned by the caller. */
+pi_status pi_cells_create(pi_ctx *ctx, pi_cells **out);
+/* Free a cell structure and its device buffers (synchronises its last
+ * stream first). */
+pi_status pi_cells_destroy(pi_cells *cells);
+
+/*
+ * Binning (Sec. 2; Fig. 1).  For the n particles (x, y, z, w) on the grid:
+ *   1. cell of every particle (float32 decision, see pi_grid);
+ *   2. counts[c] = particles in cell c, and max_per_cell (the paper's M_C,
+ *      Sec. 5.1);
+ *   3. offsets[c] = exclusive prefix sum of counts, n_cells + 1 entries,
+ *      offsets[n_cells] = n (Fig. 1);
+ *   4. the cell-sorted order: perm[k] = original index of the k-th particle,
+ *      ascending original index inside each cell (a stable counting sort:
+ *      the paper places particles inside a cell with atomics, in any order;
+ *      this library fixes the order so that results are reproducible);
+ *   5. sorted, cell-relative float32 coordinates
+ *      xs[k] = fma(-ix, cell_w, x[perm[k]] - origin[0]) (one rounding; exact
+ *      when positions lie on a power-of-two lattice), same for ys, zs, and
+ *      ws[k] = w[perm[k]].
+ * n may be 0.  n < 2^31.  Out-of-box particles set PI_ERANGE on the object
+ * (returned by pi_sync) and are left out of the counts.
+ * Buffers may be (re)allocated here; when they grow, the call first waits
+ * for the object's previous stream.
+ */
+pi_status pi_bin(pi_ctx *ctx, pi_cells *cells,
+                 const float *x, const float *y, const float *z, const float *w,
+                 int64_t n, const pi_grid *grid, pi_stream stream);
+
+/* Device pointers into a binned system (valid until the next pi_bin or
+ * pi_cells_destroy on it).  All arrays are int32/float32 in device memory. */
+typedef struct pi_cells_view {
+    int64_t n;                /* particles binned by the last pi_bin */
+    int64_t n_cells;
+    pi_grid grid;
+    const int32_t *counts;    /* [n_cells] */
+    const int32_t *offsets;   /* [n_cells + 1] */
+    const int32_t *perm;      /* [n] original index of sorted slot k */
+    const int32_t *cell;      /* [n] cell of sorted slot k */
+    const float *xs, *ys, *zs, *ws; /* [n] sorted, cell-relative */
+    const int32_t *max_per_cell;    /* [1] */
+} pi_cells_view;
+
+pi_status pi_cells_get_view(const pi_cells *cells, pi_cells_view *out);
+
+/* Accumulation precision of the sweep. */
+#define PI_PREC_COMPENSATED 0 /* FP32 terms with an error-free h^2 - r^2 for
+                                 q > 1/2, FP32 TwoSum-compensated sums */
+#define PI_PREC_PLAIN       1 /* FP32 terms (1 - q from q), plain FP32 sums */
+#define PI_PREC_FP64ACC     2 /* compensated FP32 terms, FP64 sums */
+
+/* Organisation of the sweep. */
+#define PI_SWEEP_AUTO   0 /* chosen by the library's tuner */
+#define PI_SWEEP_NOLDS  1 /* one thread per target, sources read through the
+                             caches (Sec. 4.1, Par-Part-NoLoop, Algorithm 1) */
+#define PI_SWEEP_PENCIL 2 /* a workgroup owns an X-run of target cells; the 9
+                             neighbour X-runs are staged in LDS (Sec. 5.2,
+                             X-pencil, Algorithm 5) */
+#define PI_SWEEP_SUBBOX 3 /* a workgroup owns a 3-D sub-box of target cells;
+                             the sub-box and its ghost shell are staged in LDS
+                             (Sec. 5.1, All-in-SM, Algorithm 4) */
+
+/* Order of the per-particle outputs. */
+#define PI_ORDER_SORTED   0 /* output[k] belongs to sorted slot k */
+#define PI_ORDER_ORIGINAL 1 /* output[i] belongs to input particle i */
+
+typedef struct pi_interact_opts {
+    int32_t precision; /* PI_PREC_* */
+    int32_t sweep;     /* PI_SWEEP_* */
+    int32_t order;     /* PI_ORDER_* */
+    int32_t tile[3];   /* target cells per tile for PENCIL/SUBBOX; 0 = tuned */
+} pi_interact_opts;
+
+/* Global invariants, reduced in FP64 on the device. */
+typedef struct pi_invariants {
+    int64_t pairs;   /* sum_i count_i (ordered pairs; always even) */
+    double net[3];   /* sum_i w_i G_i: zero up to rounding, since the pair
+                        terms are antisymmetric (Newton's third law) */
+    double scale;    /* sum_i w_i A_i, A_i = sum_j w_j |W'(r_ij)| */
+    double rho_sum;  /* sum_i rho_i */
+} pi_invariants;
+
+/*
+ * Interaction sweep (Sec. 2; Algorithms 1, 4, 5).  For every binned particle
+ * i (target), over the 27 neighbour cells of its cell clipped at the grid
+ * faces, and over every source j != i there with r_ij < rc (exact real
+ * predicate for lattice inputs):
+ *   count[i] = number of such j                                 (int32)
+ *   rho[i]   = sum_j w_j W(r_ij)                                (float32)
+ *   g*[i]    = sum_j w_j W'(r_ij) (x_i - x_j) / r_ij, 0 at r=0  (float32)
+ * with the cubic B-spline of support h = rc, q = r/h, sigma = 8/(pi h^3):
+ *   W = sigma (6q^3 - 6q^2 + 1) for q <= 1/2, 2 sigma (1-q)^3 for q < 1.
+ * Terms are accumulated in a fixed canonical order (neighbour cells in
+ * (dz, dy, dx) lexicographic order, sources in sorted order), so every sweep
+ * organisation gives bit-identical outputs.
+ * Outputs are caller-owned device arrays of n entries (n of the last
+ * pi_bin); any of rho, gx, gy, gz, count may be NULL only if all the float
+ * outputs are NULL together (count-only sweep).  `inv` (optional, device
+ * memory) receives the invariants.  opts may be NULL (defaults: compensated,
+ * auto, sorted).
+ */
+pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts *opts,
+                      float *rho, float *gx, float *gy, float *gz, int32_t *count,
+                      pi_invariants *inv, pi_stream stream);
+
+/* Wait for `stream` and return the first device-detected error latched on
+ * `cells` (PI_ERANGE for out-of-box particles), then clear it.  cells may be
+ * NULL (only waits). */
+pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream);
+
+/*
+ * Kernel timing (instrumentation for measurement).  While enabled on a
+ * context, every kernel the library launches is bracketed by two hipEvents
+ * recorded on the stream it is launched on; pi_timing_read waits for the
+ * recorded events and returns, per kernel name, the number of launches and
+ * the summed device time since the last reset.  Off by default (no events
+ * are recorded).  Not for use inside graph capture.
+ */
+typedef struct pi_kernel_time {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} pi_kernel_time;
+
+pi_status pi_timing_enable(pi_ctx *ctx, int32_t on);
+/* Fill out[0 .. *n_out) (at most `max` records, in first-launch order). */
+pi_status pi_timing_read(pi_ctx *ctx, pi_kernel_time *out, int32_t max, int32_t *n_out);
+pi_status pi_timing_reset(pi_ctx *ctx);
+
+/* Human-readable name of a status code (static string). */
+const char *pi_status_str(pi_status status);
+
+/* Library version string (static). */
+const char *pi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PI_H */

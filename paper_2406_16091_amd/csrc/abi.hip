@@ -1,0 +1,340 @@
+// Context, cell-object lifetime, status reporting: the non-kernel part of the
+// C ABI declared in include/pi.h.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pi_internal.h"
+
+// ------------------------------------------------------------- kernel timing
+
+struct pi_timing {
+    struct Pending {
+        int slot;
+        hipEvent_t a, b;
+    };
+    std::mutex mu;
+    std::vector<std::string> names;  // first-launch order
+    std::vector<int64_t> launches;
+    std::vector<double> total_ms;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+
+    int slot_of(const char *name)
+    {
+        for (size_t i = 0; i < names.size(); ++i)
+            if (names[i] == name) return (int)i;
+        names.emplace_back(name);
+        launches.push_back(0);
+        total_ms.push_back(0.0);
+        return (int)names.size() - 1;
+    }
+    hipEvent_t get_event()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // Fold every pending pair into the totals (waits for the events).
+    void drain()
+    {
+        for (Pending &p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                launches[p.slot] += 1;
+                total_ms[p.slot] += (double)ms;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+};
+
+// A launch's event pair lives on the heap between begin and end, and joins
+// the pending list only once both events are recorded, so a concurrent drain
+// never waits on a half-recorded pair.
+void *pi_timer_begin(pi_ctx *ctx, hipStream_t s, const char *name)
+{
+    pi_timing *t = ctx->timing;
+    if (!t) return nullptr;
+    pi_timing::Pending *p = new (std::nothrow) pi_timing::Pending();
+    if (!p) return nullptr;
+    {
+        std::lock_guard<std::mutex> g(t->mu);
+        if (t->pending.size() > 4096) t->drain();
+        p->slot = t->slot_of(name);
+        p->a = t->get_event();
+        p->b = t->get_event();
+    }
+    if (!p->a || !p->b || hipEventRecord(p->a, s) != hipSuccess) {
+        std::lock_guard<std::mutex> g(t->mu);
+        if (p->a) t->pool.push_back(p->a);
+        if (p->b) t->pool.push_back(p->b);
+        delete p;
+        return nullptr;
+    }
+    return p;
+}
+
+void pi_timer_end(pi_ctx *ctx, hipStream_t s, void *tok)
+{
+    pi_timing *t = ctx->timing;
+    if (!t || !tok) return;
+    pi_timing::Pending *p = (pi_timing::Pending *)tok;
+    const bool ok = hipEventRecord(p->b, s) == hipSuccess;
+    std::lock_guard<std::mutex> g(t->mu);
+    if (ok) {
+        t->pending.push_back(*p);
+    } else {
+        t->pool.push_back(p->a);
+        t->pool.push_back(p->b);
+    }
+    delete p;
+}
+
+extern "C" pi_status pi_timing_enable(pi_ctx *ctx, int32_t on)
+{
+    if (!ctx || !ctx->timing) return PI_EINVAL;
+    ctx->timing_on = on ? 1 : 0;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_timing_reset(pi_ctx *ctx)
+{
+    if (!ctx || !ctx->timing) return PI_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->timing->mu);
+    ctx->timing->drain();
+    for (auto &v : ctx->timing->launches) v = 0;
+    for (auto &v : ctx->timing->total_ms) v = 0.0;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_timing_read(pi_ctx *ctx, pi_kernel_time *out, int32_t max, int32_t *n_out)
+{
+    if (!ctx || !ctx->timing || !n_out || max < 0 || (max > 0 && !out)) return PI_EINVAL;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> g(ctx->timing->mu);
+    pi_timing *t = ctx->timing;
+    t->drain();
+    int32_t k = 0;
+    for (size_t i = 0; i < t->names.size() && k < max; ++i) {
+        if (t->launches[i] == 0) continue;
+        memset(out[k].name, 0, sizeof(out[k].name));
+        strncpy(out[k].name, t->names[i].c_str(), sizeof(out[k].name) - 1);
+        out[k].launches = t->launches[i];
+        out[k].total_ms = t->total_ms[i];
+        ++k;
+    }
+    *n_out = k;
+    return PI_OK;
+}
+
+pi_status pi_hip_fail(hipError_t e, const char *what)
+{
+    if (getenv("PI_DEBUG")) fprintf(stderr, "pi: %s failed: %s\n", what, hipGetErrorString(e));
+    (void)hipGetLastError(); // clear the sticky-less error state
+    return e == hipErrorOutOfMemory ? PI_ENOMEM : PI_EDEVICE;
+}
+
+extern "C" const char *pi_status_str(pi_status s)
+{
+    switch (s) {
+    case PI_OK: return "PI_OK";
+    case PI_EINVAL: return "PI_EINVAL: invalid argument";
+    case PI_ENOMEM: return "PI_ENOMEM: out of device memory or budget";
+    case PI_ERANGE: return "PI_ERANGE: particle outside the grid box";
+    case PI_EDEVICE: return "PI_EDEVICE: HIP runtime error";
+    case PI_EAGAIN: return "PI_EAGAIN: try again";
+    case PI_ENOTFOUND: return "PI_ENOTFOUND: unknown handle";
+    case PI_ESTATE: return "PI_ESTATE: call out of order";
+    default: return "unknown pi_status";
+    }
+}
+
+extern "C" const char *pi_version(void) { return "pi 0.1 (gfx950)"; }
+
+extern "C" pi_status pi_ctx_create(int32_t device, pi_ctx **out)
+{
+    if (!out) return PI_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    PI_CHECK_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return PI_EINVAL;
+    PI_CHECK_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    PI_CHECK_HIP(hipGetDeviceProperties(&prop, device));
+    pi_ctx *c = (pi_ctx *)calloc(1, sizeof(pi_ctx));
+    if (!c) return PI_ENOMEM;
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    c->num_xcd = 8;
+    c->lds_per_block = prop.sharedMemPerBlock;
+    c->timing_on = 0;
+    c->timing = new (std::nothrow) pi_timing();
+    if (!c->timing) {
+        free(c);
+        return PI_ENOMEM;
+    }
+    *out = c;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_ctx_destroy(pi_ctx *ctx)
+{
+    if (!ctx) return PI_EINVAL;
+    if (ctx->timing) {
+        {
+            std::lock_guard<std::mutex> g(ctx->timing->mu);
+            ctx->timing->drain();
+            for (hipEvent_t e : ctx->timing->pool) (void)hipEventDestroy(e);
+        }
+        delete ctx->timing;
+    }
+    free(ctx);
+    return PI_OK;
+}
+
+extern "C" pi_status pi_cells_create(pi_ctx *ctx, pi_cells **out)
+{
+    if (!ctx || !out) return PI_EINVAL;
+    pi_cells *c = (pi_cells *)calloc(1, sizeof(pi_cells));
+    if (!c) return PI_ENOMEM;
+    c->ctx = ctx;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    if (hipMalloc((void **)&c->d_err, 256) != hipSuccess) { free(c); return PI_ENOMEM; }
+    if (hipMemset(c->d_err, 0, 256) != hipSuccess) { (void)hipFree(c->d_err); free(c); return PI_EDEVICE; }
+    c->max_per_cell = (int32_t *)((char *)c->d_err + 64);
+    *out = c;
+    return PI_OK;
+}
+
+static void free_buffers(pi_cells *c)
+{
+    void **bufs[] = {(void **)&c->counts, (void **)&c->offsets, (void **)&c->cell_in,
+                     (void **)&c->slot_in, (void **)&c->perm_u, (void **)&c->perm,
+                     (void **)&c->cell, (void **)&c->xs, (void **)&c->ys, (void **)&c->zs,
+                     (void **)&c->ws, (void **)&c->tile_sum, (void **)&c->tile_max,
+                     (void **)&c->partials};
+    for (void **b : bufs) {
+        if (*b) (void)hipFree(*b);
+        *b = nullptr;
+    }
+}
+
+extern "C" pi_status pi_cells_destroy(pi_cells *c)
+{
+    if (!c) return PI_EINVAL;
+    (void)hipSetDevice(c->ctx->device);
+    if (c->last_stream || c->binned) (void)hipStreamSynchronize(c->last_stream);
+    free_buffers(c);
+    if (c->d_err) (void)hipFree(c->d_err);
+    free(c);
+    return PI_OK;
+}
+
+static int64_t grow(int64_t need, int64_t have)
+{
+    if (need <= have) return have;
+    int64_t g = have + have / 4;
+    return need > g ? need : g;
+}
+
+// Grow the per-particle / per-cell buffers to hold n particles on n_cells
+// cells.  Growing waits for the object's previous stream, since the old
+// buffers may still be in use there.
+pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_t stream)
+{
+    const int64_t tiles = (n_cells + 4095) / 4096 + 1;
+    const bool grow_n = n > c->cap_n || !c->perm;
+    const bool grow_c = n_cells > c->cap_cells || !c->counts;
+    if (!grow_n && !grow_c) return PI_OK;
+    if (c->binned) PI_CHECK_HIP(hipStreamSynchronize(c->last_stream));
+    (void)stream;
+    if (grow_n) {
+        int64_t cap = grow(n < 64 ? 64 : n, c->cap_n);
+        void **bufs[] = {(void **)&c->cell_in, (void **)&c->slot_in, (void **)&c->perm_u,
+                         (void **)&c->perm, (void **)&c->cell, (void **)&c->xs,
+                         (void **)&c->ys, (void **)&c->zs, (void **)&c->ws};
+        for (void **b : bufs) {
+            if (*b) (void)hipFree(*b);
+            *b = nullptr;
+        }
+        for (void **b : bufs)
+            if (hipMalloc(b, (size_t)cap * 4) != hipSuccess) { c->cap_n = 0; return PI_ENOMEM; }
+        c->cap_n = cap;
+        // invariant partials: one record per 256-target block
+        const int64_t parts = cap / 64 + 64;
+        if (c->partials) (void)hipFree(c->partials);
+        c->partials = nullptr;
+        if (hipMalloc(&c->partials, (size_t)parts * 64) != hipSuccess) { c->cap_n = 0; return PI_ENOMEM; }
+        c->cap_partials = parts;
+    }
+    if (grow_c) {
+        int64_t cap = grow(n_cells < 64 ? 64 : n_cells, c->cap_cells);
+        int64_t capt = (cap + 4095) / 4096 + 1;
+        void **bufs[] = {(void **)&c->counts, (void **)&c->offsets, (void **)&c->tile_sum,
+                         (void **)&c->tile_max};
+        for (void **b : bufs) {
+            if (*b) (void)hipFree(*b);
+            *b = nullptr;
+        }
+        if (hipMalloc((void **)&c->counts, (size_t)cap * 4) != hipSuccess ||
+            hipMalloc((void **)&c->offsets, (size_t)(cap + 1) * 4) != hipSuccess ||
+            hipMalloc((void **)&c->tile_sum, (size_t)capt * 4) != hipSuccess ||
+            hipMalloc((void **)&c->tile_max, (size_t)capt * 4) != hipSuccess) {
+            c->cap_cells = 0;
+            return PI_ENOMEM;
+        }
+        c->cap_cells = cap;
+        c->cap_tiles = capt;
+    }
+    (void)tiles;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_cells_get_view(const pi_cells *c, pi_cells_view *v)
+{
+    if (!c || !v) return PI_EINVAL;
+    if (!c->binned) return PI_ESTATE;
+    v->n = c->n;
+    v->n_cells = c->n_cells;
+    v->grid = c->grid;
+    v->counts = c->counts;
+    v->offsets = c->offsets;
+    v->perm = c->perm;
+    v->cell = c->cell;
+    v->xs = c->xs;
+    v->ys = c->ys;
+    v->zs = c->zs;
+    v->ws = c->ws;
+    v->max_per_cell = c->max_per_cell;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream)
+{
+    if (!ctx) return PI_EINVAL;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    PI_CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+    if (!cells) return PI_OK;
+    uint32_t err = 0;
+    PI_CHECK_HIP(hipMemcpy(&err, cells->d_err, 4, hipMemcpyDeviceToHost));
+    if (err) {
+        uint32_t zero = 0;
+        PI_CHECK_HIP(hipMemcpy(cells->d_err, &zero, 4, hipMemcpyHostToDevice));
+        if (err & PI_DERR_RANGE) return PI_ERANGE;
+        return PI_EDEVICE;
+    }
+    return PI_OK;
+}

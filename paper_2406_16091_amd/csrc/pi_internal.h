@@ -1,0 +1,137 @@
+// Internal declarations of the gfx950 library: context and cell objects,
+// launch helpers, wave64 primitives and the B-spline pair term.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pi.h"
+
+#define PI_CHECK_HIP(expr)                                  \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return pi_hip_fail(_e, #expr); \
+    } while (0)
+
+pi_status pi_hip_fail(hipError_t e, const char *what);
+
+// Device-side error bits latched in pi_cells::d_err.
+#define PI_DERR_RANGE 1u
+
+struct pi_timing; // per-context kernel timing state (abi.hip)
+
+struct pi_ctx {
+    int device;
+    int num_cu;
+    int num_xcd;
+    size_t lds_per_block;
+    volatile int timing_on;
+    pi_timing *timing;
+};
+
+// Kernel timing: bracket one launch with events on its stream when enabled.
+void *pi_timer_begin(pi_ctx *ctx, hipStream_t s, const char *name);
+void pi_timer_end(pi_ctx *ctx, hipStream_t s, void *tok);
+
+#define PI_LAUNCH(ctx, name, kern, grid, block, shmem, stream, ...)                 \
+    do {                                                                          \
+        void *_tok = (ctx)->timing_on ? pi_timer_begin((ctx), (stream), (name)) : nullptr; \
+        hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);         \
+        if (_tok) pi_timer_end((ctx), (stream), _tok);                             \
+    } while (0)
+
+// Device buffers of one binned system.  Capacities grow, never shrink.
+struct pi_cells {
+    pi_ctx *ctx;
+    int64_t n;          // particles of the last pi_bin
+    int64_t n_cells;
+    pi_grid grid;
+    int64_t cap_n;      // capacity in particles
+    int64_t cap_cells;  // capacity in cells
+    int64_t cap_tiles;  // scan tile partials
+    hipStream_t last_stream;
+    bool binned;
+    // per cell
+    int32_t *counts;    // [cap_cells]
+    int32_t *offsets;   // [cap_cells + 1]
+    // per particle, input order
+    int32_t *cell_in;   // [cap_n] cell of input particle i (-1 outside)
+    int32_t *slot_in;   // [cap_n] arrival slot inside the cell (atomic)
+    // per particle, sorted order
+    int32_t *perm_u;    // [cap_n] unstable sorted order (arrival order)
+    int32_t *perm;      // [cap_n] stable sorted order
+    int32_t *cell;      // [cap_n] cell of sorted slot
+    float *xs, *ys, *zs, *ws;   // [cap_n]
+    // scan scratch
+    int32_t *tile_sum;  // [cap_tiles]
+    int32_t *tile_max;  // [cap_tiles]
+    int32_t *max_per_cell; // [1]
+    uint32_t *d_err;       // [1]
+    // invariant partials
+    int64_t cap_partials;
+    void *partials;
+};
+
+// ------------------------------------------------------------- launch helpers
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup g runs on
+// XCD g % 8).  Remap so that each XCD processes one contiguous range of
+// logical tiles: neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t g, uint32_t ng)
+{
+    constexpr uint32_t X = 8;
+    const uint32_t q = ng / X, r = ng % X;
+    const uint32_t xcd = g % X, idx = g / X;
+    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// ------------------------------------------------------------- wave64 scan
+
+// Inclusive prefix sum over the 64 lanes of a wavefront: four row_shr DPP
+// steps scan each 16-lane row, then row_bcast:15 / row_bcast:31 carry the row
+// totals into the rows above (GFX9 DPP controls, available on gfx950).
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v)
+{
+    int32_t t;
+    t = __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false); v += t; // row_shr:1
+    t = __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false); v += t; // row_shr:2
+    t = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false); v += t; // row_shr:4
+    t = __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false); v += t; // row_shr:8
+    t = __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false); v += t; // row_bcast:15
+    t = __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false); v += t; // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_max(int32_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int32_t wave_sum(int32_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------- geometry
+
+struct GridDev {
+    float ox, oy, oz;
+    float w;        // cell width
+    int32_t nx, ny, nz;
+    int32_t pad;
+};
+
+// One axis of the cell decision: t = (x - o) / w in float32 (IEEE), inside
+// iff 0 <= t < n, index floor(t).  NaN fails the test.
+__device__ __forceinline__ bool axis_index(float x, float o, float w, int32_t n, int32_t &out)
+{
+    const float u = x - o;
+    const float t = u / w;
+    if (!(t >= 0.0f && t < (float)n)) return false;
+    out = (int32_t)t; // t >= 0: truncation is floor
+    return true;
+}
+
+pi_status pi_ensure_capacity(pi_cells *cells, int64_t n, int64_t n_cells, hipStream_t stream);

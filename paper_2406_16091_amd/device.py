@@ -1,0 +1,131 @@
+"""Device-side plumbing around the C ABI: upload a system into torch CUDA
+tensors, call pi_bin / pi_interact on a stream, read results back.
+Marshalling only -- no arithmetic of the method happens here."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import pi
+
+
+class Context:
+    """A pi_ctx on one device (created once per process and device)."""
+    _cache: dict = {}
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self.handle = pi.pi_ctx_create(device)
+
+    @classmethod
+    def get(cls, device: int = 0) -> "Context":
+        if device not in cls._cache:
+            cls._cache[device] = Context(device)
+        return cls._cache[device]
+
+
+class DeviceSystem:
+    """One particle system resident on the GPU with its pi_cells object."""
+
+    def __init__(self, system, device: int = 0, ctx: Context | None = None):
+        self.sys = system
+        self.ctx = ctx or Context.get(device)
+        self.dev = torch.device("cuda", device)
+        self.x = torch.from_numpy(np.ascontiguousarray(system.x)).to(self.dev)
+        self.y = torch.from_numpy(np.ascontiguousarray(system.y)).to(self.dev)
+        self.z = torch.from_numpy(np.ascontiguousarray(system.z)).to(self.dev)
+        self.w = torch.from_numpy(np.ascontiguousarray(system.w)).to(self.dev)
+        self.grid = pi.make_grid(system.origin, system.dims, system.cell_w, system.rc)
+        self.cells = pi.pi_cells_create(self.ctx.handle)
+        n = system.n
+        f = dict(dtype=torch.float32, device=self.dev)
+        self.rho = torch.empty(max(n, 1), **f)
+        self.gx = torch.empty(max(n, 1), **f)
+        self.gy = torch.empty(max(n, 1), **f)
+        self.gz = torch.empty(max(n, 1), **f)
+        self.count = torch.empty(max(n, 1), dtype=torch.int32, device=self.dev)
+        self.inv = torch.zeros(pi.INV_BYTES, dtype=torch.uint8, device=self.dev)
+
+    def close(self):
+        if self.cells is not None:
+            pi.pi_cells_destroy(self.cells)
+            self.cells = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bin(self, stream=None):
+        pi.pi_bin(self.ctx.handle, self.cells, self.x, self.y, self.z, self.w, self.sys.n,
+                  self.grid, stream)
+
+    def interact(self, precision="compensated", sweep="auto", order="sorted", tile=(0, 0, 0),
+                 invariants=True, stream=None, floats=True):
+        opts = pi.make_opts(precision, sweep, order, tile)
+        pi.pi_interact(self.ctx.handle, self.cells, opts,
+                       self.rho if floats else None, self.gx if floats else None,
+                       self.gy if floats else None, self.gz if floats else None,
+                       self.count, self.inv if invariants else None, stream)
+
+    def sync(self, stream=None):
+        pi.pi_sync(self.ctx.handle, self.cells, stream)
+
+    def results(self):
+        n = self.sys.n
+        return {k: getattr(self, k)[:n].cpu().numpy() for k in ("rho", "gx", "gy", "gz", "count")}
+
+    def invariants(self):
+        return pi.read_invariants(self.inv)
+
+    def binned(self):
+        """Copies of the binned arrays (counts, offsets, perm, cell, xs, ys,
+        zs, ws, max_per_cell) as numpy."""
+        v = pi.pi_cells_get_view(self.cells)
+        n, nc = int(v.n), int(v.n_cells)
+        out = {}
+        for name, cnt, dt in (("counts", nc, torch.int32), ("offsets", nc + 1, torch.int32),
+                              ("perm", n, torch.int32), ("cell", n, torch.int32),
+                              ("xs", n, torch.float32), ("ys", n, torch.float32),
+                              ("zs", n, torch.float32), ("ws", n, torch.float32),
+                              ("max_per_cell", 1, torch.int32)):
+            t = torch.empty(max(cnt, 1), dtype=dt, device=self.dev)
+            ptr = getattr(v, name)
+            if cnt > 0:
+                nbytes = cnt * 4
+                # device-to-device copy through the HIP runtime torch uses
+                torch.cuda.synchronize(self.dev)
+                _copy_d2d(t.data_ptr(), ptr, nbytes)
+            out[name] = t[:cnt].cpu().numpy()
+        out["max_per_cell"] = int(out["max_per_cell"][0])
+        return out
+
+
+_hip = None
+
+
+def _copy_d2d(dst: int, src: int, nbytes: int):
+    """hipMemcpy device-to-device between two raw pointers (the view's
+    buffers belong to the library, not to torch)."""
+    global _hip
+    if _hip is None:
+        import os
+        lib = None
+        for cand in ("libamdhip64.so.7", "libamdhip64.so"):
+            try:
+                lib = ctypes.CDLL(cand)
+                break
+            except OSError:
+                continue
+        if lib is None:
+            tl = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+            lib = ctypes.CDLL(tl)
+        lib.hipMemcpy.restype = ctypes.c_int
+        lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip = lib
+    st = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes), 3)
+    if st != 0:
+        raise RuntimeError(f"hipMemcpy failed: {st}")

@@ -96,17 +96,43 @@ def scale_8ppc(seed=2):
     return uniform_unit_cube(1 << 24, -7, seed, "uniform-16.8M-128^3-8ppc")
 
 
-def clustered(n=1 << 23, n_blobs=64, bg_frac=0.10, rc_log2=-7, seed=3, name=None):
-    """Gaussian blobs (centres uniform in [0,1)^3, sigma ~ U(0.01, 0.05), blob
-    chosen uniformly) plus a uniform background fraction; clipped to the unit
-    cube and quantized to the 2^-24 lattice."""
+def _blob_sigmas(rng, n_blobs, n_blob_pts, g, lo, hi, peak_ppc):
+    """Blob widths in cells: drawn from U(lo, hi) * g, raised where needed so
+    that no blob's centre holds more than about peak_ppc particles per cell
+    (density of an isotropic Gaussian at its centre: n / ((2 pi)^1.5 s^3))."""
+    sig = rng.uniform(lo, hi, size=n_blobs) * g
+    floor = (n_blob_pts / ((2.0 * math.pi) ** 1.5 * peak_ppc)) ** (1.0 / 3.0)
+    return np.maximum(sig, floor)
+
+
+def _blob_points(rng, centres, sig, which, extent):
+    """Gaussian points around centres[which]; a point that falls outside
+    [0, extent)^3 is drawn again (truncated Gaussians), so no mass piles up
+    on the faces of the box."""
+    pts = centres[which] + sig[which, None] * rng.standard_normal((which.size, 3))
+    bad = np.nonzero(((pts < 0) | (pts >= extent)).any(axis=1))[0]
+    while bad.size:
+        w = which[bad]
+        pts[bad] = centres[w] + sig[w, None] * rng.standard_normal((bad.size, 3))
+        bad = bad[((pts[bad] < 0) | (pts[bad] >= extent)).any(axis=1)]
+    return pts
+
+
+def clustered(n=1 << 23, n_blobs=64, bg_frac=0.10, rc_log2=-7, seed=3, name=None,
+              sigma=(0.04, 0.08), peak_ppc=60.0):
+    """Gaussian blobs (centres uniform in [0,1)^3, blob chosen uniformly,
+    width U(sigma) in box units, raised so that blob centres stay near
+    peak_ppc particles per cell, truncated to the unit cube) plus a uniform
+    background fraction, quantized to the 2^-24 lattice."""
     rng = np.random.default_rng(seed)
-    centres = rng.random((n_blobs, 3))
-    sig = rng.uniform(0.01, 0.05, size=n_blobs)
+    rc = 2.0 ** rc_log2
+    d = int(round(1.0 / rc))
     n_bg = int(round(bg_frac * n))
     n_bl = n - n_bg
+    centres = rng.random((n_blobs, 3))
+    sig = _blob_sigmas(rng, n_blobs, n_bl / n_blobs, d, sigma[0], sigma[1], peak_ppc) / d
     which = rng.integers(0, n_blobs, size=n_bl)
-    pts = centres[which] + sig[which, None] * rng.standard_normal((n_bl, 3))
+    pts = _blob_points(rng, centres, sig, which, 1.0)
     bg = rng.random((n_bg, 3))
     allp = np.concatenate([pts, bg], axis=0)
     order = rng.permutation(n)          # interleave blob and background points
@@ -115,27 +141,28 @@ def clustered(n=1 << 23, n_blobs=64, bg_frac=0.10, rc_log2=-7, seed=3, name=None
     y = _lattice_quantize(allp[:, 1], 1, 24)
     z = _lattice_quantize(allp[:, 2], 1, 24)
     w = _weights(rng, n)
-    rc = 2.0 ** rc_log2
-    d = int(round(1.0 / rc))
     return System(name or f"clustered-{n}-{d}^3", x, y, z, w, (0.0, 0.0, 0.0),
                   (d, d, d), rc, rc, {"seed": seed, "blobs": n_blobs, "lattice": 2.0 ** -24})
 
 
-def box_system(n, g, seed, lattice_log2, clustered_blobs=0, name=None):
+def box_system(n, g, seed, lattice_log2, clustered_blobs=0, name=None,
+               sigma=(0.04, 0.08), peak_ppc=60.0):
     """n particles in the box [0, g)^3 of unit cells (cell width = r_c = 1),
     on the 2^-lattice_log2 lattice; uniform, or `clustered_blobs` Gaussian
-    blobs (sigma ~ U(0.01, 0.05) * g) with a 10% uniform background."""
+    blobs (width U(sigma) * g, raised so that blob centres stay near
+    peak_ppc particles per cell) with a 10% uniform background."""
     rng = np.random.default_rng(seed)
     p = lattice_log2
     if clustered_blobs <= 0:
         x, y, z = _lattice_uniform(rng, n, g, p)
         kind = "uniform"
     else:
-        centres = rng.random((clustered_blobs, 3)) * g
-        sig = rng.uniform(0.01, 0.05, size=clustered_blobs) * g
         n_bg = int(round(0.1 * n))
+        centres = rng.random((clustered_blobs, 3)) * g
+        sig = _blob_sigmas(rng, clustered_blobs, (n - n_bg) / clustered_blobs, g,
+                           sigma[0], sigma[1], peak_ppc)
         which = rng.integers(0, clustered_blobs, size=n - n_bg)
-        pts = centres[which] + sig[which, None] * rng.standard_normal((n - n_bg, 3))
+        pts = _blob_points(rng, centres, sig, which, float(g))
         allp = np.concatenate([pts, rng.random((n_bg, 3)) * g], axis=0)[rng.permutation(n)]
         x = _lattice_quantize(allp[:, 0], g, p)
         y = _lattice_quantize(allp[:, 1], g, p)

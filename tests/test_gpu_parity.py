@@ -1,0 +1,308 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Integer outputs (cells, counts, offsets, sorted order, neighbour counts,
+total pair count) must match bit for bit.  Float outputs must be within the
+tolerance stated for the compensated FP32 path:
+  rho: |rho - rho*| <= 1e-5 * rho*            (exactly 0 when rho* = 0)
+  G:   |G_a - G_a*| <= 1e-5 * A*,  A* = sum_j w_j |W'(r_ij)|
+where starred values are the oracle's.  A is the condition scale of the
+gradient sums, so the bound is relative to the size of the terms summed.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_16091_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+SWEEPS = [("nolds", (0, 0, 0)), ("pencil", (254, 1, 1)), ("pencil", (62, 1, 1)),
+          ("pencil", (30, 1, 1)), ("subbox", (8, 8, 4)), ("subbox", (4, 4, 4)), ("subbox", (4, 4, 2))]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_16091_amd import device, pi
+    pi.load()
+    return device
+
+
+def _oracle_bin(s):
+    return oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+
+
+def _check_bin(ds, s, b):
+    g = ds.binned()
+    assert g["counts"].tolist() == b.counts.tolist() or (g["counts"] == b.counts).all()
+    assert (g["offsets"] == b.offsets).all()
+    assert (g["perm"] == b.perm).all()
+    assert (g["cell"] == b.cell[b.perm]).all()
+    for k in ("xs", "ys", "zs", "ws"):
+        assert (g[k].view(np.uint32) == getattr(b, k).view(np.uint32)).all(), k
+    assert g["max_per_cell"] == b.max_per_cell
+
+
+def _check_floats(res, ref, idx=None, tol=TOL):
+    """res: GPU outputs in original order; ref: oracle SweepOut for targets idx."""
+    sel = (lambda a: a) if idx is None else (lambda a: a[idx])
+    cnt = sel(res["count"]).astype(np.int64)
+    assert (cnt == ref.count).all(), f"count mismatch at {np.nonzero(cnt != ref.count)[0][:10]}"
+    rho = sel(res["rho"]).astype(np.float64)
+    assert np.all(np.abs(rho - ref.rho) <= tol * ref.rho), \
+        f"rho max rel err {np.max(np.abs(rho - ref.rho) / np.maximum(ref.rho, 1e-300))}"
+    assert np.all(rho[ref.rho == 0] == 0)
+    for k in ("gx", "gy", "gz"):
+        g = sel(res[k]).astype(np.float64)
+        e = np.abs(g - getattr(ref, k))
+        assert np.all(e <= tol * ref.ascale), f"{k} max scaled err {np.max(e / np.maximum(ref.ascale, 1e-300))}"
+
+
+def _err_stats(res, ref, idx=None):
+    sel = (lambda a: a) if idx is None else (lambda a: a[idx])
+    rho = sel(res["rho"]).astype(np.float64)
+    er = np.abs(rho - ref.rho) / np.where(ref.rho > 0, ref.rho, 1.0)
+    eg = max(np.max(np.abs(sel(res[k]).astype(np.float64) - getattr(ref, k))
+                    / np.where(ref.ascale > 0, ref.ascale, 1.0)) for k in ("gx", "gy", "gz"))
+    return float(er.max()), float(eg), float((er > TOL).mean())
+
+
+SMALL = {
+    "tiny": lambda: synth.tiny(),
+    "ragged": lambda: synth.box_system(3001, 7, seed=31, lattice_log2=18),
+    "clustered": lambda: synth.clustered(n=20000, n_blobs=6, rc_log2=-5, seed=32),
+    "one_cell": lambda: synth.box_system(300, 1, seed=33, lattice_log2=18),
+    "flat": lambda: synth.System("flat", *(lambda b: (b.x, b.y, (b.z * 0).astype(np.float32), b.w))(
+        synth.box_system(4000, 40, seed=34, lattice_log2=18)), (0.0, 0.0, 0.0), (40, 40, 1), 1.0, 1.0),
+    "wide_cells": lambda: synth.System("wide", *(lambda b: (b.x, b.y, b.z, b.w))(
+        synth.box_system(5000, 9, seed=35, lattice_log2=18)), (0.0, 0.0, 0.0), (9, 9, 9), 1.0, 0.75),
+    "offset_origin": lambda: synth.System("off", *(lambda b: (b.x - np.float32(4), b.y + np.float32(2),
+                                                              b.z - np.float32(1), b.w))(
+        synth.box_system(4000, 8, seed=36, lattice_log2=18)), (-4.0, 2.0, -1.0), (8, 8, 8), 1.0, 1.0),
+    "single": lambda: synth.box_system(1, 3, seed=37, lattice_log2=18),
+    "dense_8ppc": lambda: synth.uniform_unit_cube(8 * 16 ** 3, -4, seed=38),
+}
+
+
+@pytest.mark.parametrize("case", list(SMALL))
+def test_bin_parity(dev, case):
+    s = SMALL[case]()
+    _say(f"[bin] {case} n={s.n} dims={s.dims}")
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.sync()
+    _check_bin(ds, s, _oracle_bin(s))
+
+
+def test_bin_fig1(dev):
+    from test_oracle_pins import _read_golden
+    g = _read_golden("fig1_binning.txt")
+    pts = np.array(g["particle"], dtype=np.float32)
+    s = synth.System("fig1", pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(),
+                     np.ones(len(pts), np.float32), tuple(g["origin"][0]),
+                     tuple(int(v) for v in g["dims"][0]), g["cell_w"][0][0], g["cell_w"][0][0])
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.sync()
+    out = ds.binned()
+    assert out["counts"].tolist() == [2, 1, 3, 0, 2, 1]
+    assert out["offsets"].tolist() == [0, 2, 3, 6, 6, 8, 9]
+    assert out["perm"].tolist() == [0, 1, 2, 3, 4, 5, 7, 8, 6]
+
+
+def test_bin_float_decision_non_power_of_two(dev):
+    """Cell width 0.1 (not a power of two): the float32 cell decision of
+    the kernel and the oracle must agree bit for bit, including points that
+    sit on rounded cell faces."""
+    rng = np.random.default_rng(40)
+    n = 200000
+    x = (rng.random(n) * 3.0).astype(np.float32)
+    y = (np.floor(rng.random(n) * 30) * np.float32(0.1)).astype(np.float32)  # on faces
+    z = (rng.random(n) * 3.0).astype(np.float32)
+    w = np.ones(n, np.float32)
+    y = np.minimum(y, np.float32(2.9))
+    s = synth.System("p2", x, y, z, w, (0.0, 0.0, 0.0), (30, 30, 30), 0.1, 0.1)
+    st, cells = oracle.cells(x, y, z, s.origin, s.dims, s.cell_w)
+    keep = cells >= 0
+    s = synth.System("p2", x[keep], y[keep], z[keep], w[keep], (0.0, 0.0, 0.0), (30, 30, 30), 0.1, 0.1)
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.sync()
+    _check_bin(ds, s, _oracle_bin(s))
+
+
+@pytest.mark.parametrize("case", list(SMALL))
+@pytest.mark.parametrize("sweep,tile", SWEEPS)
+def test_sweep_parity(dev, case, sweep, tile):
+    s = SMALL[case]()
+    _say(f"[sweep] {case} n={s.n} {sweep} {tile}")
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.interact(sweep=sweep, tile=tile, order="original")
+    ds.sync()
+    b = _oracle_bin(s)
+    ref = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b)
+    res = ds.results()
+    _check_floats(res, ref)
+    inv = ds.invariants()
+    P, F, S = oracle.invariants(s.w, ref)
+    assert inv["pairs"] == P
+    assert inv["scale"] == pytest.approx(S, rel=1e-5, abs=1e-30)
+    assert np.all(np.abs(np.array(inv["net"])) <= 1e-5 * max(S, 1e-30))
+    assert inv["rho_sum"] == pytest.approx(ref.rho.sum(), rel=1e-5, abs=1e-30)
+
+
+def test_sorted_order_matches_original(dev):
+    s = SMALL["ragged"]()
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.interact(order="original")
+    a = ds.results()
+    ds.interact(order="sorted")
+    bsort = ds.results()
+    perm = ds.binned()["perm"]
+    for k in ("rho", "gx", "gy", "gz", "count"):
+        assert (a[k][perm].view(np.uint32) == bsort[k].view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("case", ["tiny", "clustered", "dense_8ppc", "ragged"])
+def test_sweep_organisations_bitwise_equal(dev, case):
+    s = SMALL[case]()
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    outs = []
+    for sweep, tile in SWEEPS:
+        ds.interact(sweep=sweep, tile=tile, order="sorted")
+        outs.append(ds.results())
+    for o in outs[1:]:
+        for k in ("rho", "gx", "gy", "gz", "count"):
+            assert (o[k].view(np.uint32) == outs[0][k].view(np.uint32)).all(), k
+
+
+@pytest.mark.parametrize("precision", ["plain", "fp64acc"])
+def test_precision_variants(dev, precision):
+    s = SMALL["tiny"]()
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.interact(precision=precision, order="original")
+    ds.sync()
+    ref = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, _oracle_bin(s))
+    res = ds.results()
+    assert (res["count"].astype(np.int64) == ref.count).all()
+    er, eg, frac = _err_stats(res, ref)
+    _say(f"[{precision}] max rel rho err {er:.3e}, max scaled G err {eg:.3e}, frac rho > tol {frac:.2e}")
+    if precision == "fp64acc":
+        _check_floats(res, ref)
+    else:
+        assert er < 1e-3 and eg < 1e-4
+
+
+def test_overflowing_tile_falls_back(dev):
+    """5000 particles in a 3x3x3 grid: every tile's halo exceeds the LDS
+    capacity and is read from global memory instead -- same results."""
+    s = synth.box_system(5000, 3, seed=41, lattice_log2=18)
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ref = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, _oracle_bin(s))
+    for sweep, tile in SWEEPS:
+        ds.interact(sweep=sweep, tile=tile, order="original")
+        ds.sync()
+        _check_floats(ds.results(), ref)
+
+
+def test_empty_system(dev):
+    e = np.zeros(0, np.float32)
+    s = synth.System("empty", e, e, e, e, (0.0, 0.0, 0.0), (4, 3, 2), 1.0, 1.0)
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.interact()
+    ds.sync()
+    out = ds.binned()
+    assert out["counts"].tolist() == [0] * 24 and out["offsets"].tolist() == [0] * 25
+    assert ds.invariants()["pairs"] == 0
+
+
+def test_out_of_box_reports_erange(dev):
+    from paper_2406_16091_amd import pi
+    s = synth.box_system(1000, 4, seed=42, lattice_log2=18)
+    x = s.x.copy()
+    x[17] = np.float32(4.0)      # on the far face: outside [0, 4)
+    x[500] = np.float32(np.nan)
+    bad = synth.System("bad", x, s.y, s.z, s.w, s.origin, s.dims, 1.0, 1.0)
+    ds = dev.DeviceSystem(bad)
+    ds.bin()
+    ds.interact()
+    with pytest.raises(pi.PiError) as e:
+        ds.sync()
+    assert e.value.status == pi.PI_ERANGE
+    ds.sync()  # the error is cleared once reported
+    # the object is usable again with valid input
+    good = dev.DeviceSystem(s)
+    good.bin()
+    good.interact(order="original")
+    good.sync()
+
+
+def test_host_argument_errors(dev):
+    from paper_2406_16091_amd import pi
+    s = SMALL["single"]()
+    ds = dev.DeviceSystem(s)
+    bad = pi.make_grid((0, 0, 0), (3, 3, 3), 1.0, 1.5)  # cell narrower than the cutoff
+    with pytest.raises(pi.PiError) as e:
+        pi.pi_bin(ds.ctx.handle, ds.cells, ds.x, ds.y, ds.z, ds.w, 1, bad)
+    assert e.value.status == pi.PI_EINVAL
+    fresh = pi.pi_cells_create(ds.ctx.handle)
+    with pytest.raises(pi.PiError) as e:   # interact before bin
+        pi.pi_interact(ds.ctx.handle, fresh, pi.make_opts(), ds.rho, ds.gx, ds.gy, ds.gz, ds.count)
+    assert e.value.status == pi.PI_ESTATE
+    pi.pi_cells_destroy(fresh)
+    with pytest.raises(pi.PiError):
+        pi.pi_bin(ds.ctx.handle, ds.cells, ds.x, ds.y, ds.z, ds.w, -1, ds.grid)
+
+
+# ---------------------------------------------------------------- full sizes
+
+_BIG = {}
+
+
+def _big(name):
+    if name not in _BIG:
+        _BIG.clear()
+        _BIG[name] = {"scale_1ppc": synth.scale_1ppc, "scale_8ppc": synth.scale_8ppc,
+                      "clustered": synth.clustered}[name]()
+    return _BIG[name]
+
+
+@pytest.mark.parametrize("name", ["scale_1ppc", "scale_8ppc", "clustered"])
+def test_full_size_parity(dev, name):
+    s = _big(name)
+    _say(f"[full] {name} n={s.n} dims={s.dims}")
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.interact(order="original")
+    ds.sync()
+    b = _oracle_bin(s)
+    _check_bin(ds, s, b)
+    idx = synth.subsample(s.n, 20000, seed=20)
+    ref = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b, targets=idx)
+    res = ds.results()
+    _check_floats(res, ref, idx)
+    if name == "scale_1ppc":
+        # every particle's neighbour count and the total pair count
+        full = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b)
+        assert ds.invariants()["pairs"] == int(full.count.sum())
+        assert (res["count"].astype(np.int64) == full.count).all()
+    else:
+        assert ds.invariants()["pairs"] == int(res["count"].astype(np.int64).sum())
+    ds.close()
