@@ -149,6 +149,139 @@ def cpu_baseline(system, budget_s: float = 30.0):
             "sample": label, "bin_s": round(t_bin, 3), "sweep_s": round(t_sweep, 3)}
 
 
+def bench_batch(steps: int, warmup: int, sweep: str = "auto"):
+    """512 independent systems (N log-uniform in [1e3, 2e5], 1-4 per cell):
+    one pi_batch_run (one captured hipGraph launch per step) against the
+    plain path of pi_bin + pi_interact per system on the same stream."""
+    import torch
+    from paper_2406_16091_amd import device, pi, synth
+
+    systems = synth.batch_systems()
+    n_total = sum(s.n for s in systems)
+    stream = torch.cuda.Stream()
+    # plain path: one resident system object per system
+    singles = [device.DeviceSystem(s) for s in systems]
+    torch.cuda.synchronize()
+
+    def plain_step():
+        for d in singles:
+            d.bin(stream=stream)
+            d.interact(sweep=sweep, invariants=True, stream=stream)
+
+    for _ in range(warmup):
+        plain_step()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain_step()
+    stream.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    pairs_plain = sum(d.invariants()["pairs"] for d in singles)
+    del singles
+
+    db = device.DeviceBatch(systems)
+    torch.cuda.synchronize()
+    stream.wait_stream(torch.cuda.current_stream())
+    for _ in range(max(warmup, 1)):
+        db.run(sweep=sweep, stream=stream)   # the first call captures the graph
+    stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        db.run(sweep=sweep, stream=stream)
+    stream.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    db.sync(stream)
+    pairs = sum(v["pairs"] for v in db.invariants())
+    assert pairs == pairs_plain, "batched and per-system pair totals differ"
+    return {"systems": len(systems), "particles": n_total, "pairs_per_step": pairs,
+            "batched_ms_per_step": round(t_batch * 1e3, 4),
+            "batched_pairs_per_s": round(pairs / t_batch, 1),
+            "one_system_per_launch_ms_per_step": round(t_plain * 1e3, 4),
+            "one_system_per_launch_pairs_per_s": round(pairs / t_plain, 1),
+            "speedup": round(t_plain / t_batch, 2)}
+
+
+def bench_serve(n_pool: int = 16, sweeps: int = 8, seconds: float = 3.0, loads=(0.5, 0.8), seed: int = 5):
+    """Serving: requests of N log-uniform in [1e4, 4e6] particles (uniform or
+    8-blob clustered, 1/2/4/8 per cell), each swept `sweeps` times with
+    Gaussian displacements of 0.1 r_c between sweeps.  Measures the
+    saturation rate (all requests submitted at once), the one-request-at-a-
+    time rate, and p50/p99 latency (submit to results in host memory) under
+    Poisson arrivals at fractions of the saturation rate."""
+    import numpy as np
+    import torch
+    from paper_2406_16091_amd import device, pi, synth
+
+    pool = synth.serve_requests(n_pool, seed=seed)
+    ctx = device.Context.get(0).handle
+    reqs = [pi.make_request(s, n_sweeps=sweeps, jitter_sigma=0.1 * s.rc, lattice=2.0 ** -16, seed=1000 + k)
+            for k, s in enumerate(pool)]
+    torch.cuda.synchronize()
+
+    def run_all(server, order):
+        t0 = time.perf_counter()
+        tickets = [pi.pi_submit(server, reqs[i]) for i in order]
+        pairs = 0
+        for t in tickets:
+            r = pi.pi_wait(server, t, copy=False)
+            pairs += r["pairs_total"]
+            pi.pi_release(server, t)
+        return time.perf_counter() - t0, pairs
+
+    one = pi.pi_server_create(ctx, max_slots=1, n_streams=1)
+    run_all(one, range(len(reqs)))               # warm: buffers, tuner classes
+    t_seq, pairs_seq = run_all(one, range(len(reqs)))
+    pi.pi_server_destroy(one)
+
+    server = pi.pi_server_create(ctx, max_slots=8, n_streams=4)
+    run_all(server, range(len(reqs)))
+    t_sat, pairs_sat = run_all(server, range(len(reqs)))
+    rate_sat = len(reqs) / t_sat
+    out = {"requests_in_pool": len(reqs), "sweeps_per_request": sweeps,
+           "mean_particles": float(np.mean([s.n for s in pool])),
+           "saturation_requests_per_s": round(rate_sat, 2),
+           "saturation_pairs_per_s": round(pairs_sat / t_sat, 1),
+           "one_at_a_time_requests_per_s": round(len(reqs) / t_seq, 2),
+           "one_at_a_time_pairs_per_s": round(pairs_seq / t_seq, 1),
+           "speedup_over_one_at_a_time": round(t_seq / t_sat, 2), "loads": []}
+    rng = np.random.default_rng(seed)
+    for f in loads:
+        lam = f * rate_sat
+        t_start = time.perf_counter()
+        next_t = t_start
+        k = 0
+        pending = {}
+        lat, pairs = [], 0
+        while True:
+            now = time.perf_counter()
+            if now - t_start < seconds and now >= next_t:
+                i = k % len(reqs)
+                t_client = time.perf_counter()
+                st, tk = pi.pi_submit_status(server, reqs[i])
+                if st == pi.PI_OK:
+                    pending[tk] = t_client
+                k += 1
+                next_t += rng.exponential(1.0 / lam)
+                continue
+            for tk in list(pending):
+                r = pi.pi_poll(server, tk, copy=False)
+                if r["done"]:
+                    lat.append(time.perf_counter() - pending.pop(tk))
+                    pairs += r["pairs_total"]
+                    pi.pi_release(server, tk)
+            if now - t_start >= seconds and not pending:
+                break
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t_start
+        lat_ms = np.array(lat) * 1e3
+        out["loads"].append({"load": f, "offered_requests_per_s": round(lam, 2), "completed": len(lat),
+                             "p50_ms": round(float(np.percentile(lat_ms, 50)), 3) if len(lat) else None,
+                             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3) if len(lat) else None,
+                             "pairs_per_s": round(pairs / wall, 1)})
+    pi.pi_server_destroy(server)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +293,10 @@ def main():
     ap.add_argument("--precision", default="compensated")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--serve", action="store_true",
+                    help="also measure the request server (saturation, one-at-a-time, Poisson p50/p99)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also measure the 512-system batch (graph launch vs one launch per system)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times "
                          "(reference kernel for scaling HBM traffic counters), then exit")
@@ -277,6 +414,12 @@ def main():
         "stages": stages,
         "kernels": kernels,
     }
+    if args.serve:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serve"] = bench_serve()
+    if args.batch:
+        print("[bench] batch of 512 systems", file=sys.stderr, flush=True)
+        out["batch"] = bench_batch(max(3, args.steps // 10), 2)
     if rank == 0 and not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(system)

@@ -99,8 +99,9 @@ pi_status pi_cells_destroy(pi_cells *cells);
  *      xs[k] = fma(-ix, cell_w, x[perm[k]] - origin[0]) (one rounding; exact
  *      when positions lie on a power-of-two lattice), same for ys, zs, and
  *      ws[k] = w[perm[k]].
- * n may be 0.  n < 2^31.  Out-of-box particles set PI_ERANGE on the object
- * (returned by pi_sync) and are left out of the counts.
+ * n may be 0.  n < 2^31.  An out-of-box particle sets PI_ERANGE on the object
+ * (returned by pi_sync); the results of that call are then unspecified (the
+ * particle is put in the last cell so that every kernel stays in bounds).
  * Buffers may be (re)allocated here; when they grow, the call first waits
  * for the object's previous stream.
  */
@@ -188,6 +189,141 @@ pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts
  * `cells` (PI_ERANGE for out-of-box particles), then clear it.  cells may be
  * NULL (only waits). */
 pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream);
+
+/*
+ * Tuner.  The paper concludes that which organisation is fastest is hard to
+ * predict and needs a profiling step per configuration (Sec. 8).  With
+ * PI_SWEEP_AUTO the library times every compiled organisation (no-LDS and
+ * each pencil / sub-box tile) once per size and occupancy class -- buckets
+ * of log2(n) and of the mean particles per cell -- on the caller's stream,
+ * and reuses the fastest for that class afterwards (per context).  Tuning
+ * runs the sweep once per candidate and waits for the stream.  In
+ * PI_TUNE_STATIC mode (or with PI_AUTOTUNE=off in the environment) AUTO uses
+ * a fixed rule on the mean occupancy instead.
+ */
+#define PI_TUNE_STATIC 0
+#define PI_TUNE_TIMED  1
+pi_status pi_tuner_mode(pi_ctx *ctx, int32_t mode);
+/* The organisation AUTO uses for this binned system and precision (tuning
+ * it now if the class is new and the mode is timed).  out->sweep is
+ * PI_SWEEP_NOLDS, _PENCIL or _SUBBOX and out->tile its shape. */
+pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t precision, pi_interact_opts *out,
+                          pi_stream stream);
+
+/*
+ * Batches: many independent systems binned and swept together (the
+ * pipeline of Sec. 2 applied to a set of systems).  The systems' particles
+ * are concatenated in the caller's arrays, system s occupying
+ * [offset, offset + n) with offset = sum of the previous systems' n; each
+ * system has its own grid and cutoff.  One radix sort over global cell ids
+ * and one work-list sweep cover all systems; the launch sequence is
+ * captured into a hipGraph the first time a layout (systems, pointers,
+ * options, stream) is seen and replayed by later calls with the same
+ * layout.  On the null stream nothing is captured.
+ */
+typedef struct pi_batch pi_batch;
+
+typedef struct pi_system_desc {
+    int64_t offset;   /* first particle of the system in the concatenated arrays */
+    int64_t n;        /* particles of the system (>= 0) */
+    pi_grid grid;     /* the system's grid and cutoff */
+} pi_system_desc;
+
+pi_status pi_batch_create(pi_ctx *ctx, pi_batch **out);
+pi_status pi_batch_destroy(pi_batch *batch);
+/*
+ * Bin and sweep nsys >= 1 systems (descriptions in host memory).  x, y, z, w
+ * and the outputs are concatenated device arrays of sum(n) entries; with
+ * PI_ORDER_ORIGINAL output i belongs to input particle i, with
+ * PI_ORDER_SORTED to sorted slot i (systems stay in order either way).  inv,
+ * if not NULL, receives nsys records (device memory).  Same precision and
+ * organisation options as pi_interact; AUTO picks one tile shape for the
+ * batch from its mean occupancy.  Sum(n) and the total cell count must stay
+ * below 2^31.  Errors as pi_bin / pi_interact; device errors surface through
+ * pi_batch_sync.
+ */
+pi_status pi_batch_run(pi_ctx *ctx, pi_batch *batch, int32_t nsys, const pi_system_desc *sys,
+                       const float *x, const float *y, const float *z, const float *w,
+                       const pi_interact_opts *opts, float *rho, float *gx, float *gy, float *gz,
+                       int32_t *count, pi_invariants *inv, pi_stream stream);
+/* View of the concatenated binned arrays of the last run (cell ids in
+ * `cell` are local to their system; counts/offsets are indexed by global
+ * cell = cell_base[s] + local cell).  cell_base (host, max_sys entries) may
+ * be NULL. */
+pi_status pi_batch_get_view(const pi_batch *batch, pi_cells_view *out, int64_t *cell_base, int32_t max_sys);
+/* pi_sync for a batch. */
+pi_status pi_batch_sync(pi_ctx *ctx, pi_batch *batch, pi_stream stream);
+
+/*
+ * Serving.  Particle systems submitted over time, each swept n_sweeps
+ * times; before every sweep after the first, each particle is displaced by
+ * a Gaussian step (counter-based RNG, reflected at the box faces, rounded to
+ * a lattice) and the system is re-binned in place: its cell list stays
+ * resident on the GPU for the whole request.  A scheduler thread admits
+ * queued requests first-in first-out as soon as a slot is free and the
+ * request's device-memory footprint fits the budget, and queues the whole
+ * request on one of the server's streams, so requests run concurrently and
+ * new ones are admitted while older ones are in flight.  Results stay in
+ * pinned host memory owned by the server until pi_release.  All calls are
+ * thread-safe.
+ */
+typedef struct pi_server pi_server;
+
+typedef struct pi_server_opts {
+    int64_t hbm_budget;      /* device bytes the admitted requests may hold together */
+    int32_t max_slots;       /* requests in flight at once (1..256) */
+    int32_t n_streams;       /* HIP streams the slots are spread over (1..16) */
+    int32_t queue_capacity;  /* requests waiting for admission; beyond -> PI_EAGAIN */
+    int32_t pad;
+} pi_server_opts;
+
+typedef struct pi_request {
+    const float *x, *y, *z, *w; /* host arrays of n entries, copied by pi_submit */
+    int64_t n;
+    pi_grid grid;
+    int32_t n_sweeps;           /* >= 1 */
+    int32_t precision;          /* PI_PREC_* */
+    int32_t sweep;              /* PI_SWEEP_* */
+    float jitter_sigma;         /* per-axis standard deviation of a displacement (0: none) */
+    float lattice;              /* displaced positions rounded down to multiples of this (0: no rounding) */
+    int32_t pad;
+    uint64_t seed;              /* RNG seed of the displacements */
+} pi_request;
+
+typedef struct pi_result {
+    int32_t done;               /* 1 once the request has finished */
+    int32_t status;             /* PI_OK or the error that ended it */
+    int64_t n;
+    int32_t sweeps;
+    int32_t pad;
+    int64_t pairs_total;        /* ordered pairs summed over all sweeps */
+    double t_submit, t_start, t_done; /* seconds (CLOCK_MONOTONIC): submitted, admitted, finished */
+    const float *rho, *gx, *gy, *gz;  /* last sweep, input order (pinned host memory) */
+    const int32_t *count;
+    const float *x, *y, *z;     /* positions of the last sweep */
+    const pi_invariants *invariants; /* [sweeps] */
+} pi_result;
+
+typedef struct pi_server_stats_t {
+    int32_t queued;
+    int32_t running;
+    int64_t hbm_in_use;
+} pi_server_stats_t;
+
+/* opts may be NULL (64 GiB budget, 8 slots, 4 streams, queue of 1024). */
+pi_status pi_server_create(pi_ctx *ctx, const pi_server_opts *opts, pi_server **out);
+/* Admitted requests finish first; queued ones end with PI_EAGAIN. */
+pi_status pi_server_destroy(pi_server *server);
+/* PI_EAGAIN if the queue is full, PI_ENOMEM if the request alone exceeds the
+ * budget, PI_EINVAL for a bad request.  *ticket identifies the request. */
+pi_status pi_submit(pi_server *server, const pi_request *req, uint64_t *ticket);
+/* Non-blocking: out->done tells whether the request has finished. */
+pi_status pi_poll(pi_server *server, uint64_t ticket, pi_result *out);
+/* Blocks until the request has finished. */
+pi_status pi_wait(pi_server *server, uint64_t ticket, pi_result *out);
+/* Frees a finished request's results (PI_EAGAIN while it is running). */
+pi_status pi_release(pi_server *server, uint64_t ticket);
+pi_status pi_server_stats(pi_server *server, pi_server_stats_t *out);
 
 /*
  * Kernel timing (instrumentation for measurement).  While enabled on a

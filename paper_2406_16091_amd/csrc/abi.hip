@@ -182,9 +182,15 @@ extern "C" pi_status pi_ctx_create(int32_t device, pi_ctx **out)
     c->lds_per_block = prop.sharedMemPerBlock;
     c->timing_on = 0;
     c->timing = new (std::nothrow) pi_timing();
-    if (!c->timing) {
+    c->tuner = new (std::nothrow) pi_tuner();
+    if (!c->timing || !c->tuner) {
+        delete c->timing;
+        delete c->tuner;
         free(c);
         return PI_ENOMEM;
+    }
+    if (const char *m = getenv("PI_AUTOTUNE")) {
+        if (!strcmp(m, "off") || !strcmp(m, "0")) c->tuner->mode = PI_TUNE_STATIC;
     }
     *out = c;
     return PI_OK;
@@ -201,6 +207,7 @@ extern "C" pi_status pi_ctx_destroy(pi_ctx *ctx)
         }
         delete ctx->timing;
     }
+    delete ctx->tuner;
     free(ctx);
     return PI_OK;
 }
@@ -215,20 +222,57 @@ extern "C" pi_status pi_cells_create(pi_ctx *ctx, pi_cells **out)
     if (hipMalloc((void **)&c->d_err, 256) != hipSuccess) { free(c); return PI_ENOMEM; }
     if (hipMemset(c->d_err, 0, 256) != hipSuccess) { (void)hipFree(c->d_err); free(c); return PI_EDEVICE; }
     c->max_per_cell = (int32_t *)((char *)c->d_err + 64);
+    c->hist_total = (int32_t *)((char *)c->d_err + 128);
     *out = c;
     return PI_OK;
 }
 
+// Every device buffer of a pi_cells object except the error word, with the
+// capacity class it is sized by.
+enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_TILES, BUF_HIST, BUF_HIST_TILES, BUF_PARTIALS };
+
+struct BufRef {
+    void **ptr;
+    BufClass cls;
+    size_t elem;
+};
+
+static int list_buffers(pi_cells *c, BufRef *out)
+{
+    int k = 0;
+    auto add = [&](void **p, BufClass cls, size_t elem) { out[k++] = BufRef{p, cls, elem}; };
+    add((void **)&c->counts, BUF_CELLS, 4);
+    add((void **)&c->offsets, BUF_CELLS1, 4);
+    add((void **)&c->perm, BUF_N, 4);
+    add((void **)&c->cell, BUF_N, 4);
+    add((void **)&c->xs, BUF_N, 4);
+    add((void **)&c->ys, BUF_N, 4);
+    add((void **)&c->zs, BUF_N, 4);
+    add((void **)&c->ws, BUF_N, 4);
+    for (int b = 0; b < 2; ++b) {
+        add((void **)&c->skey[b], BUF_N, 4);
+        add((void **)&c->sidx[b], BUF_N, 4);
+        add((void **)&c->sx[b], BUF_N, 4);
+        add((void **)&c->sy[b], BUF_N, 4);
+        add((void **)&c->sz[b], BUF_N, 4);
+        add((void **)&c->sw[b], BUF_N, 4);
+    }
+    add((void **)&c->hist, BUF_HIST, 4);
+    add((void **)&c->hist_tsum, BUF_HIST_TILES, 4);
+    add((void **)&c->hist_tmax, BUF_HIST_TILES, 4);
+    add((void **)&c->tile_sum, BUF_TILES, 4);
+    add((void **)&c->tile_max, BUF_TILES, 4);
+    add((void **)&c->partials, BUF_PARTIALS, 64);
+    return k;
+}
+
 static void free_buffers(pi_cells *c)
 {
-    void **bufs[] = {(void **)&c->counts, (void **)&c->offsets, (void **)&c->cell_in,
-                     (void **)&c->slot_in, (void **)&c->perm_u, (void **)&c->perm,
-                     (void **)&c->cell, (void **)&c->xs, (void **)&c->ys, (void **)&c->zs,
-                     (void **)&c->ws, (void **)&c->tile_sum, (void **)&c->tile_max,
-                     (void **)&c->partials};
-    for (void **b : bufs) {
-        if (*b) (void)hipFree(*b);
-        *b = nullptr;
+    BufRef b[40];
+    const int nb = list_buffers(c, b);
+    for (int i = 0; i < nb; ++i) {
+        if (*b[i].ptr) (void)hipFree(*b[i].ptr);
+        *b[i].ptr = nullptr;
     }
 }
 
@@ -255,51 +299,46 @@ static int64_t grow(int64_t need, int64_t have)
 // buffers may still be in use there.
 pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_t stream)
 {
-    const int64_t tiles = (n_cells + 4095) / 4096 + 1;
+    (void)stream;
     const bool grow_n = n > c->cap_n || !c->perm;
     const bool grow_c = n_cells > c->cap_cells || !c->counts;
     if (!grow_n && !grow_c) return PI_OK;
     if (c->binned) PI_CHECK_HIP(hipStreamSynchronize(c->last_stream));
-    (void)stream;
-    if (grow_n) {
-        int64_t cap = grow(n < 64 ? 64 : n, c->cap_n);
-        void **bufs[] = {(void **)&c->cell_in, (void **)&c->slot_in, (void **)&c->perm_u,
-                         (void **)&c->perm, (void **)&c->cell, (void **)&c->xs,
-                         (void **)&c->ys, (void **)&c->zs, (void **)&c->ws};
-        for (void **b : bufs) {
-            if (*b) (void)hipFree(*b);
-            *b = nullptr;
+    const int64_t cap_n = grow_n ? grow(n < 64 ? 64 : n, c->cap_n) : c->cap_n;
+    const int64_t cap_c = grow_c ? grow(n_cells < 64 ? 64 : n_cells, c->cap_cells) : c->cap_cells;
+    const int64_t sort_tiles = (cap_n + 4095) / 4096 + 1;
+    const int64_t cap_hist = 256 * sort_tiles;
+    const int64_t cap_hist_tiles = cap_hist / 4096 + 2;
+    const int64_t cap_tiles = (cap_c + 4095) / 4096 + 1;
+    const int64_t cap_parts = 2 * (cap_c + cap_n / 64) + 64;
+    BufRef b[40];
+    const int nb = list_buffers(c, b);
+    for (int i = 0; i < nb; ++i) {
+        int64_t count = 0;
+        bool redo = false;
+        switch (b[i].cls) {
+        case BUF_N: count = cap_n; redo = grow_n; break;
+        case BUF_HIST: count = cap_hist; redo = grow_n; break;
+        case BUF_HIST_TILES: count = cap_hist_tiles; redo = grow_n; break;
+        case BUF_CELLS: count = cap_c; redo = grow_c; break;
+        case BUF_CELLS1: count = cap_c + 1; redo = grow_c; break;
+        case BUF_TILES: count = cap_tiles; redo = grow_c; break;
+        case BUF_PARTIALS: count = cap_parts; redo = grow_n || grow_c; break;
         }
-        for (void **b : bufs)
-            if (hipMalloc(b, (size_t)cap * 4) != hipSuccess) { c->cap_n = 0; return PI_ENOMEM; }
-        c->cap_n = cap;
-        // invariant partials: one record per 256-target block
-        const int64_t parts = cap / 64 + 64;
-        if (c->partials) (void)hipFree(c->partials);
-        c->partials = nullptr;
-        if (hipMalloc(&c->partials, (size_t)parts * 64) != hipSuccess) { c->cap_n = 0; return PI_ENOMEM; }
-        c->cap_partials = parts;
-    }
-    if (grow_c) {
-        int64_t cap = grow(n_cells < 64 ? 64 : n_cells, c->cap_cells);
-        int64_t capt = (cap + 4095) / 4096 + 1;
-        void **bufs[] = {(void **)&c->counts, (void **)&c->offsets, (void **)&c->tile_sum,
-                         (void **)&c->tile_max};
-        for (void **b : bufs) {
-            if (*b) (void)hipFree(*b);
-            *b = nullptr;
-        }
-        if (hipMalloc((void **)&c->counts, (size_t)cap * 4) != hipSuccess ||
-            hipMalloc((void **)&c->offsets, (size_t)(cap + 1) * 4) != hipSuccess ||
-            hipMalloc((void **)&c->tile_sum, (size_t)capt * 4) != hipSuccess ||
-            hipMalloc((void **)&c->tile_max, (size_t)capt * 4) != hipSuccess) {
-            c->cap_cells = 0;
+        if (!redo && *b[i].ptr) continue;
+        if (*b[i].ptr) (void)hipFree(*b[i].ptr);
+        *b[i].ptr = nullptr;
+        if (hipMalloc(b[i].ptr, (size_t)count * b[i].elem) != hipSuccess) {
+            free_buffers(c);
+            c->cap_n = c->cap_cells = 0;
             return PI_ENOMEM;
         }
-        c->cap_cells = cap;
-        c->cap_tiles = capt;
     }
-    (void)tiles;
+    c->cap_n = cap_n;
+    c->cap_cells = cap_c;
+    c->cap_tiles = cap_tiles;
+    c->cap_hist = cap_hist;
+    c->cap_partials = cap_parts;
     return PI_OK;
 }
 

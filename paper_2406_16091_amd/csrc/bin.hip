@@ -1,26 +1,41 @@
-// Binning (paper Sec. 2 and Fig. 1): cell of every particle, per-cell counts
-// with atomics, exclusive prefix sum (n_cells + 1 entries, last = n) and the
-// scatter into a cell-sorted order, made stable (ascending original index
-// inside each cell) so that every later result is reproducible.
+// Binning (paper Sec. 2 and Fig. 1): the cell of every particle, per-cell
+// counts, the exclusive prefix sum of the counts (n_cells + 1 entries, last =
+// n) and the particles moved into a cell-sorted order.  The order inside a
+// cell is ascending original index: the paper places particles inside their
+// cell with atomics in any order; fixing the order makes every later result
+// reproducible.
 //
-// Kernels, in launch order on the caller's stream:
-//   k_fill_i32      counts = 0 (a kernel, not a memset, so the sequence can
-//                   be captured into a graph)
-//   k_bin_count     cell id (float32 decision), atomicAdd on counts -> the
-//                   particle's arrival slot inside its cell
-//   k_scan_reduce   per 4096-cell tile: sum and max of counts
-//   k_scan_tiles    one workgroup: exclusive scan of tile sums, M_C, total
-//   k_scan_down     per tile: wave64 DPP scan, writes offsets
-//   k_bin_scatter   perm_u[offsets[c] + slot] = i (arrival order)
-//   k_bin_finalize  per sorted slot: stable rank inside the cell, gathers
-//                   the particle, writes perm, cell, xs, ys, zs, ws
+// On MI355X the move is a least-significant-digit radix sort of the cell ids,
+// 8 bits per pass, which is stable by construction and keeps every HBM access
+// coalesced (the input order is a random permutation of the cells, so a
+// scatter by per-particle atomics costs a whole cache line per 4-byte access).
+// Per pass, in launch order on the caller's stream:
+//   k_radix_hist     per 4096-key tile: LDS histogram of the pass's digit,
+//                    stored digit-major (digit * tiles + tile)
+//   k_scan_*         exclusive scan of the histogram -> where each
+//                    (digit, tile) run starts in the pass's output
+//   k_radix_scatter  per tile: stable rank of every key among the tile's
+//                    keys with the same digit (wave64 ballots + per-wave
+//                    counters), the tile reordered by digit in LDS, then
+//                    written out in runs (key, index, x, y, z, w)
+// The first pass computes the cell id from the position (float32 decision,
+// see axis_index); the last pass writes the final arrays perm, cell and the
+// cell-relative coordinates.  Counts then come from atomics on the sorted
+// cell ids (consecutive threads hit consecutive counters) and the offsets
+// and M_C from the same DPP scan.
+#include <string.h>
+
 #include "pi_internal.h"
 
 namespace {
 
 constexpr int kBlock = 256;
 constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems; // 4096 cells per scan tile
+constexpr int kScanTile = kBlock * kScanItems; // 4096 entries per scan tile
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kBlock * kSortItems; // 4096 keys per sort tile
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
@@ -28,29 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int3
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_count(int32_t n, const float *__restrict__ x,
-                                                      const float *__restrict__ y,
-                                                      const float *__restrict__ z, GridDev g,
-                                                      int32_t *__restrict__ counts,
-                                                      int32_t *__restrict__ cell_in,
-                                                      int32_t *__restrict__ slot_in,
-                                                      uint32_t *__restrict__ err)
-{
-    const int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (i >= n) return;
-    int32_t ix, iy, iz;
-    const int ok = (int)axis_index(x[i], g.ox, g.w, g.nx, ix) & (int)axis_index(y[i], g.oy, g.w, g.ny, iy) &
-                   (int)axis_index(z[i], g.oz, g.w, g.nz, iz);
-    if (!ok) {
-        cell_in[i] = -1;
-        slot_in[i] = 0;
-        atomicOr(err, PI_DERR_RANGE);
-        return;
-    }
-    const int32_t c = ix + g.nx * (iy + g.ny * iz);
-    cell_in[i] = c;
-    slot_in[i] = atomicAdd(&counts[c], 1);
-}
+// ------------------------------------------------------------- scan (DPP)
 
 // Block-wide sum and max of one value per thread (256 threads, 4 waves).
 __device__ __forceinline__ void block_sum_max(int32_t &s, int32_t &m, int32_t *lds)
@@ -67,7 +60,7 @@ __device__ __forceinline__ void block_sum_max(int32_t &s, int32_t &m, int32_t *l
     m = max(max(lds[4], lds[5]), max(lds[6], lds[7]));
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ counts, int64_t nc,
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ in, int64_t nc,
                                                         int32_t *__restrict__ tile_sum,
                                                         int32_t *__restrict__ tile_max)
 {
@@ -78,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restric
     for (int j = 0; j < kScanItems; ++j) {
         const int64_t c = base + j * kBlock + threadIdx.x; // coalesced
         if (c < nc) {
-            const int32_t v = counts[c];
+            const int32_t v = in[c];
             s += v;
             m = max(m, v);
         }
@@ -113,8 +106,8 @@ __device__ __forceinline__ int32_t block_excl_scan_1024(int32_t v, int32_t *lds,
 
 __global__ __launch_bounds__(1024) void k_scan_tiles(int32_t *__restrict__ tile_sum,
                                                      const int32_t *__restrict__ tile_max, int32_t ntiles,
-                                                     int32_t *__restrict__ off_last,
-                                                     int32_t *__restrict__ mc_out)
+                                                     int32_t *__restrict__ total_out,
+                                                     int32_t *__restrict__ max_out)
 {
     __shared__ int32_t lds[40];
     __shared__ int32_t red[32];
@@ -128,27 +121,26 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int32_t *__restrict__ tile_
         if (t < ntiles) tile_sum[t] = carry + ex;
         carry += tot;
     }
-    // max over the block
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         int32_t mm = 0;
         for (int k = 0; k < 16; ++k) mm = max(mm, red[k]);
-        *mc_out = mm;
-        *off_last = carry;
+        if (max_out) *max_out = mm;
+        *total_out = carry;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t *__restrict__ counts, int64_t nc,
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t *in, int64_t nc,
                                                       const int32_t *__restrict__ tile_off,
-                                                      int32_t *__restrict__ off)
+                                                      int32_t *out) // may alias `in`
 {
     __shared__ int32_t lds[8];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t v[kScanItems];
     if (base + kScanItems <= nc) {
-        const int4 *p = reinterpret_cast<const int4 *>(counts + base);
+        const int4 *p = reinterpret_cast<const int4 *>(in + base);
 #pragma unroll
         for (int q = 0; q < kScanItems / 4; ++q) {
             const int4 t = p[q];
@@ -159,12 +151,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t *__restrict_
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < kScanItems; ++j) v[j] = (base + j < nc) ? counts[base + j] : 0;
+        for (int j = 0; j < kScanItems; ++j) v[j] = (base + j < nc) ? in[base + j] : 0;
     }
     int32_t tsum = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) tsum += v[j];
-    // block exclusive scan of per-thread sums (4 waves)
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int32_t inc = wave_incl_scan(tsum);
     if (lane == 63) lds[wid] = inc;
@@ -179,60 +170,294 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t *__restrict_
         run += v[j];
     }
     if (base + kScanItems <= nc) {
-        int4 *p = reinterpret_cast<int4 *>(off + base);
+        int4 *p = reinterpret_cast<int4 *>(out + base);
 #pragma unroll
         for (int q = 0; q < kScanItems / 4; ++q) p[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
     } else {
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j)
-            if (base + j < nc) off[base + j] = o[j];
+            if (base + j < nc) out[base + j] = o[j];
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_scatter(int32_t n, const int32_t *__restrict__ cell_in,
-                                                        const int32_t *__restrict__ slot_in,
-                                                        const int32_t *__restrict__ off,
-                                                        int32_t *__restrict__ perm_u)
+// ------------------------------------------------------------- radix sort
+
+// Cell id of a position (X fastest, Fig. 1).  A particle outside the box
+// raises the error bit and is put in the last cell, so that every kernel
+// stays inside its buffers; the results of that call are then unspecified.
+__device__ __forceinline__ uint32_t cell_key(float x, float y, float z, const GridDev &g, uint32_t *err)
 {
-    const int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (i >= n) return;
-    const int32_t c = cell_in[i];
-    if (c < 0) return;
-    perm_u[off[c] + slot_in[i]] = i;
+    int32_t ix, iy, iz;
+    const int ok = (int)axis_index(x, g.ox, g.w, g.nx, ix) & (int)axis_index(y, g.oy, g.w, g.ny, iy) &
+                   (int)axis_index(z, g.oz, g.w, g.nz, iz);
+    if (!ok) {
+        atomicOr(err, PI_DERR_RANGE);
+        return (uint32_t)g.nx * (uint32_t)g.ny * (uint32_t)g.nz - 1u;
+    }
+    return (uint32_t)(ix + g.nx * (iy + g.ny * iz));
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_finalize(
-    int32_t n, int64_t nc, const int32_t *__restrict__ perm_u, const int32_t *__restrict__ cell_in,
-    const int32_t *__restrict__ off, const float *__restrict__ x, const float *__restrict__ y,
-    const float *__restrict__ z, const float *__restrict__ w, GridDev g, int32_t *__restrict__ perm,
-    int32_t *__restrict__ cell, float *__restrict__ xs, float *__restrict__ ys, float *__restrict__ zs,
-    float *__restrict__ ws)
+// System owning global particle e (systems concatenated in order).
+__device__ __forceinline__ int sys_of_particle(const SysDev *sys, int nsys, int64_t e)
+{
+    int lo = 0, hi = nsys; // sys[lo].first <= e < sys[hi].first
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sys[mid].first <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// System owning global cell key.
+__device__ __forceinline__ int sys_of_cell(const SysDev *sys, int nsys, uint32_t key)
+{
+    int lo = 0, hi = nsys;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((uint32_t)sys[mid].cell_base <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+struct SortArgs {
+    int32_t n;
+    int32_t ntiles;
+    int32_t shift;
+    GridDev g;
+    const SysDev *sys; // batch mode: system table (nsys entries), else null
+    int32_t nsys;
+    // first pass reads the caller's arrays
+    const float *x, *y, *z, *w;
+    // later passes read the previous pass's output
+    const uint32_t *key_in;
+    const int32_t *idx_in;
+    const float *x_in, *y_in, *z_in, *w_in;
+    // outputs (ping-pong buffer, or the final arrays on the last pass)
+    uint32_t *key_out;
+    int32_t *idx_out;
+    float *x_out, *y_out, *z_out, *w_out;
+    const int32_t *gbase; // scanned histogram, digit-major
+    int32_t *hist;
+    uint32_t *err;
+};
+
+// Global cell key of caller particle e.
+template <bool BATCH>
+__device__ __forceinline__ uint32_t first_key(const SortArgs &a, int64_t e)
+{
+    if (!BATCH) return cell_key(a.x[e], a.y[e], a.z[e], a.g, a.err);
+    const SysDev &s = a.sys[sys_of_particle(a.sys, a.nsys, e)];
+    return (uint32_t)s.cell_base + cell_key(a.x[e], a.y[e], a.z[e], s.g, a.err);
+}
+
+template <bool FIRST, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_radix_hist(SortArgs a)
+{
+    __shared__ int32_t h[kRadix];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int q = 0; q < kSortItems; ++q) {
+        const int64_t e = base + q * kBlock + threadIdx.x;
+        if (e < a.n) {
+            const uint32_t key = FIRST ? first_key<BATCH>(a, e) : a.key_in[e];
+            atomicAdd(&h[(key >> a.shift) & (kRadix - 1)], 1);
+        }
+    }
+    __syncthreads();
+    a.hist[(int64_t)threadIdx.x * a.ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Lanes of the wavefront whose digit equals this lane's (among `valid`).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid)
+{
+    uint64_t m = valid;
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const uint64_t bal = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    return m;
+}
+
+template <bool FIRST, bool LAST, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(SortArgs a)
+{
+    __shared__ int32_t wcnt[4][kRadix];  // per-wave digit counters, then wave bases
+    __shared__ int32_t lstart[kRadix];   // tile-local start of each digit
+    __shared__ int32_t gdst[kRadix];     // global start of each digit's run
+    __shared__ int32_t scan_tmp[8];
+    __shared__ int32_t lds_dst[kSortTile];
+    __shared__ uint32_t lds_buf[kSortTile];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t tile_base = (int64_t)blockIdx.x * kSortTile;
+    for (int i = tid; i < 4 * kRadix; i += kBlock) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    // 1. stable rank of each key among the keys of its wavefront's 1024-key
+    //    chunk with the same digit (rounds in key order, lanes in key order)
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t key[kSortItems];
+    int32_t rank[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t e = tile_base + wid * (kSortItems * 64) + r * 64 + lane;
+        const bool valid = e < a.n;
+        uint32_t k = 0;
+        if (valid) k = FIRST ? first_key<BATCH>(a, e) : a.key_in[e];
+        key[r] = k;
+        const uint32_t d = (k >> a.shift) & (kRadix - 1);
+        const uint64_t vmask = __ballot(valid);
+        const uint64_t peers = match_digit(d, vmask);
+        int32_t rk = -1;
+        if (valid) {
+            const int32_t before = __popcll(peers & lt);
+            const int32_t base = wcnt[wid][d];
+            rk = base + before;
+            if (before == 0) wcnt[wid][d] = base + __popcll(peers);
+        }
+        rank[r] = rk;
+    }
+    __syncthreads();
+
+    // 2. per digit: bases of the waves, tile total, tile-local start (scan)
+    {
+        const int d = tid;
+        const int32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+        const int32_t tot = c0 + c1 + c2 + c3;
+        const int32_t inc = wave_incl_scan(tot);
+        if (lane == 63) scan_tmp[wid] = inc;
+        __syncthreads();
+        int32_t wofs = 0;
+        for (int k = 0; k < wid; ++k) wofs += scan_tmp[k];
+        lstart[d] = wofs + inc - tot;
+        gdst[d] = a.gbase[(int64_t)d * a.ntiles + blockIdx.x];
+        wcnt[0][d] = 0;
+        wcnt[1][d] = c0;
+        wcnt[2][d] = c0 + c1;
+        wcnt[3][d] = c0 + c1 + c2;
+    }
+    __syncthreads();
+
+    // 3. tile-local position of every key and the global destination of that
+    //    position (consecutive positions of one digit go to consecutive
+    //    addresses, so the copies below are coalesced runs)
+    int32_t pos[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        pos[r] = -1;
+        if (rank[r] >= 0) {
+            const uint32_t d = (key[r] >> a.shift) & (kRadix - 1);
+            const int32_t within = wcnt[wid][d] + rank[r];
+            pos[r] = lstart[d] + within;
+            lds_dst[pos[r]] = gdst[d] + within;
+        }
+    }
+    const int32_t nvalid = (int32_t)min((int64_t)kSortTile, (int64_t)a.n - tile_base);
+
+    // 4. reorder each array through LDS and write it out
+    auto pass_array = [&](auto value_of, auto store) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r)
+            if (pos[r] >= 0) lds_buf[pos[r]] = value_of(r);
+        __syncthreads();
+        for (int p = tid; p < nvalid; p += kBlock) store(lds_dst[p], lds_buf[p]);
+    };
+    auto elem = [&](int r) { return tile_base + wid * (kSortItems * 64) + r * 64 + lane; };
+
+    if (LAST) {
+        // final arrays: local cell ids, and the cell-relative coordinates
+        // fma(-i, w, x - o) of the original coordinate carried along
+        int32_t lcell[kSortItems];
+        const GridDev *gr[kSortItems];
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            lcell[r] = 0;
+            gr[r] = &a.g;
+            if (pos[r] >= 0 && BATCH) {
+                const SysDev &sd = a.sys[sys_of_cell(a.sys, a.nsys, key[r])];
+                lcell[r] = (int32_t)(key[r] - (uint32_t)sd.cell_base);
+                gr[r] = &sd.g;
+            } else {
+                lcell[r] = (int32_t)key[r];
+            }
+        }
+        pass_array([&](int r) { return (uint32_t)lcell[r]; }, [&](int32_t o, uint32_t v) { a.key_out[o] = v; });
+        pass_array([&](int r) { return FIRST ? (uint32_t)elem(r) : (uint32_t)a.idx_in[elem(r)]; },
+                   [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
+        pass_array(
+            [&](int r) {
+                const GridDev &g = *gr[r];
+                const float x = FIRST ? a.x[elem(r)] : a.x_in[elem(r)];
+                const int32_t ix = lcell[r] % g.nx;
+                return __float_as_uint(__builtin_fmaf(-(float)ix, g.w, x - g.ox));
+            },
+            [&](int32_t o, uint32_t v) { a.x_out[o] = __uint_as_float(v); });
+        pass_array(
+            [&](int r) {
+                const GridDev &g = *gr[r];
+                const float y = FIRST ? a.y[elem(r)] : a.y_in[elem(r)];
+                const int32_t iy = (lcell[r] / g.nx) % g.ny;
+                return __float_as_uint(__builtin_fmaf(-(float)iy, g.w, y - g.oy));
+            },
+            [&](int32_t o, uint32_t v) { a.y_out[o] = __uint_as_float(v); });
+        pass_array(
+            [&](int r) {
+                const GridDev &g = *gr[r];
+                const float z = FIRST ? a.z[elem(r)] : a.z_in[elem(r)];
+                const int32_t iz = lcell[r] / (g.nx * g.ny);
+                return __float_as_uint(__builtin_fmaf(-(float)iz, g.w, z - g.oz));
+            },
+            [&](int32_t o, uint32_t v) { a.z_out[o] = __uint_as_float(v); });
+    } else {
+        pass_array([&](int r) { return key[r]; }, [&](int32_t o, uint32_t v) { a.key_out[o] = v; });
+        pass_array([&](int r) { return FIRST ? (uint32_t)elem(r) : (uint32_t)a.idx_in[elem(r)]; },
+                   [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
+        pass_array([&](int r) { return __float_as_uint(FIRST ? a.x[elem(r)] : a.x_in[elem(r)]); },
+                   [&](int32_t o, uint32_t v) { a.x_out[o] = __uint_as_float(v); });
+        pass_array([&](int r) { return __float_as_uint(FIRST ? a.y[elem(r)] : a.y_in[elem(r)]); },
+                   [&](int32_t o, uint32_t v) { a.y_out[o] = __uint_as_float(v); });
+        pass_array([&](int r) { return __float_as_uint(FIRST ? a.z[elem(r)] : a.z_in[elem(r)]); },
+                   [&](int32_t o, uint32_t v) { a.z_out[o] = __uint_as_float(v); });
+    }
+    pass_array([&](int r) { return __float_as_uint(FIRST ? a.w[elem(r)] : a.w_in[elem(r)]); },
+               [&](int32_t o, uint32_t v) { a.w_out[o] = __uint_as_float(v); });
+}
+
+// counts[c] += 1 for every sorted cell id: consecutive threads touch
+// consecutive counters, so the atomics are coalesced.
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_count_sorted(int32_t n, const int32_t *__restrict__ cell,
+                                                         int32_t *__restrict__ counts, const SysDev *sys,
+                                                         int32_t nsys)
 {
     const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    const int32_t nb = off[nc]; // particles inside the box
-    if (k >= nb || k >= n) return;
-    const int32_t p = perm_u[k];
-    const int32_t c = cell_in[p];
-    const int32_t s = off[c], e = off[c + 1];
-    int32_t rank = 0;
-    for (int32_t q = s; q < e; ++q) rank += (perm_u[q] < p) ? 1 : 0;
-    const int32_t d = s + rank;
-    const int32_t ix = c % g.nx;
-    const int32_t iy = (c / g.nx) % g.ny;
-    const int32_t iz = c / (g.nx * g.ny);
-    perm[d] = p;
-    cell[d] = c;
-    xs[d] = __builtin_fmaf(-(float)ix, g.w, x[p] - g.ox);
-    ys[d] = __builtin_fmaf(-(float)iy, g.w, y[p] - g.oy);
-    zs[d] = __builtin_fmaf(-(float)iz, g.w, z[p] - g.oz);
-    ws[d] = w[p];
+    if (k >= n) return;
+    const int32_t base = BATCH ? sys[sys_of_particle(sys, nsys, k)].cell_base : 0;
+    atomicAdd(&counts[base + cell[k]], 1);
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Exclusive scan of in[0 .. len) into out[0 .. len); the total goes to
+// *total and the maximum to *maxv (optional).
+void launch_scan(pi_ctx *ctx, const int32_t *in, int64_t len, int32_t *out, int32_t *total, int32_t *maxv,
+                 int32_t *tsum, int32_t *tmax, hipStream_t s)
+{
+    const int32_t ntiles = (int32_t)((len + kScanTile - 1) / kScanTile);
+    PI_LAUNCH(ctx, "k_scan_reduce", k_scan_reduce, dim3(ntiles), dim3(kBlock), 0, s, in, len, tsum, tmax);
+    PI_LAUNCH(ctx, "k_scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, s, tsum, (const int32_t *)tmax, ntiles,
+              total, maxv);
+    PI_LAUNCH(ctx, "k_scan_down", k_scan_down, dim3(ntiles), dim3(kBlock), 0, s, in, len, (const int32_t *)tsum,
+              out);
+}
+
 } // namespace
 
-static bool grid_valid(const pi_grid *g)
+bool pi_grid_valid(const pi_grid *g)
 {
     if (!g) return false;
     for (int a = 0; a < 3; ++a) {
@@ -246,13 +471,104 @@ static bool grid_valid(const pi_grid *g)
     return true;
 }
 
+// Radix sort of n particles by global cell id, then counts and offsets.
+// nsys == 0: one system on grid g0; else d_sys describes nsys concatenated
+// systems with cells_total cells in all.
+pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const float *y, const float *z,
+                         const float *w, int64_t n, int64_t nc, int32_t nsys, const SysDev *d_sys,
+                         const GridDev &g0, hipStream_t stream)
+{
+    const bool batch = nsys > 0;
+    if (n > 0) {
+        // 8-bit digits needed to sort keys 0 .. nc-1
+        int bits = 1;
+        while (bits < 31 && ((int64_t)1 << bits) < nc) ++bits;
+        const int passes = (bits + kRadixBits - 1) / kRadixBits;
+        const int32_t ntiles = (int32_t)((n + kSortTile - 1) / kSortTile);
+        const int64_t hlen = (int64_t)kRadix * ntiles;
+        SortArgs a;
+        memset(&a, 0, sizeof(a));
+        a.n = (int32_t)n;
+        a.ntiles = ntiles;
+        a.g = g0;
+        a.sys = d_sys;
+        a.nsys = nsys;
+        a.x = x;
+        a.y = y;
+        a.z = z;
+        a.w = w;
+        a.hist = cells->hist;
+        a.gbase = cells->hist;
+        a.err = cells->d_err;
+        for (int p = 0; p < passes; ++p) {
+            const bool first = p == 0, last = p == passes - 1;
+            const int src = (p + 1) & 1, dst = p & 1;
+            a.shift = p * kRadixBits;
+            a.key_in = cells->skey[src];
+            a.idx_in = cells->sidx[src];
+            a.x_in = cells->sx[src];
+            a.y_in = cells->sy[src];
+            a.z_in = cells->sz[src];
+            a.w_in = cells->sw[src];
+            if (last) {
+                a.key_out = (uint32_t *)cells->cell;
+                a.idx_out = cells->perm;
+                a.x_out = cells->xs;
+                a.y_out = cells->ys;
+                a.z_out = cells->zs;
+                a.w_out = cells->ws;
+            } else {
+                a.key_out = cells->skey[dst];
+                a.idx_out = cells->sidx[dst];
+                a.x_out = cells->sx[dst];
+                a.y_out = cells->sy[dst];
+                a.z_out = cells->sz[dst];
+                a.w_out = cells->sw[dst];
+            }
+            const dim3 grid(ntiles), block(kBlock);
+            if (first && batch) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, true>), grid, block, 0, stream, a);
+            else if (first) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, false>), grid, block, 0, stream, a);
+            else PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<false, false>), grid, block, 0, stream, a);
+            launch_scan(ctx, cells->hist, hlen, cells->hist, cells->hist_total, nullptr, cells->hist_tsum,
+                        cells->hist_tmax, stream);
+#define PI_SCATTER(F, L, B) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<F, L, B>), grid, block, 0, stream, a)
+            if (batch) {
+                if (first && last) PI_SCATTER(true, true, true);
+                else if (first) PI_SCATTER(true, false, true);
+                else if (last) PI_SCATTER(false, true, true);
+                else PI_SCATTER(false, false, true);
+            } else {
+                if (first && last) PI_SCATTER(true, true, false);
+                else if (first) PI_SCATTER(true, false, false);
+                else if (last) PI_SCATTER(false, true, false);
+                else PI_SCATTER(false, false, false);
+            }
+#undef PI_SCATTER
+        }
+    }
+    PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks(nc, kBlock)), dim3(kBlock), 0, stream, cells->counts, nc,
+              0);
+    if (n > 0) {
+        if (batch)
+            PI_LAUNCH(ctx, "k_count_sorted", (k_count_sorted<true>), dim3(nblocks(n, kBlock)), dim3(kBlock), 0,
+                      stream, (int32_t)n, (const int32_t *)cells->cell, cells->counts, d_sys, nsys);
+        else
+            PI_LAUNCH(ctx, "k_count_sorted", (k_count_sorted<false>), dim3(nblocks(n, kBlock)), dim3(kBlock), 0,
+                      stream, (int32_t)n, (const int32_t *)cells->cell, cells->counts, d_sys, nsys);
+    }
+    launch_scan(ctx, cells->counts, nc, cells->offsets, cells->offsets + nc, cells->max_per_cell, cells->tile_sum,
+                cells->tile_max, stream);
+    PI_CHECK_HIP(hipGetLastError());
+    return PI_OK;
+}
+
 extern "C" pi_status pi_bin(pi_ctx *ctx, pi_cells *cells, const float *x, const float *y, const float *z,
                             const float *w, int64_t n, const pi_grid *grid, pi_stream stream_)
 {
     if (!ctx || !cells || cells->ctx != ctx) return PI_EINVAL;
     if (n < 0 || n >= ((int64_t)1 << 31)) return PI_EINVAL;
     if (n > 0 && (!x || !y || !z || !w)) return PI_EINVAL;
-    if (!grid_valid(grid)) return PI_EINVAL;
+    if (!pi_grid_valid(grid)) return PI_EINVAL;
     hipStream_t stream = (hipStream_t)stream_;
     PI_CHECK_HIP(hipSetDevice(ctx->device));
     const int64_t nc = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
@@ -274,25 +590,5 @@ extern "C" pi_status pi_bin(pi_ctx *ctx, pi_cells *cells, const float *x, const 
     g.nz = grid->dims[2];
     g.pad = 0;
 
-    const int32_t ntiles = (int32_t)((nc + kScanTile - 1) / kScanTile);
-    PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks(nc, kBlock)), dim3(kBlock), 0, stream, cells->counts, nc,
-              0);
-    if (n > 0)
-        PI_LAUNCH(ctx, "k_bin_count", k_bin_count, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, stream, (int32_t)n, x,
-                  y, z, g, cells->counts, cells->cell_in, cells->slot_in, cells->d_err);
-    PI_LAUNCH(ctx, "k_scan_reduce", k_scan_reduce, dim3(ntiles), dim3(kBlock), 0, stream, cells->counts, nc,
-              cells->tile_sum, cells->tile_max);
-    PI_LAUNCH(ctx, "k_scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, stream, cells->tile_sum, cells->tile_max,
-              ntiles, cells->offsets + nc, cells->max_per_cell);
-    PI_LAUNCH(ctx, "k_scan_down", k_scan_down, dim3(ntiles), dim3(kBlock), 0, stream, cells->counts, nc,
-              cells->tile_sum, cells->offsets);
-    if (n > 0) {
-        PI_LAUNCH(ctx, "k_bin_scatter", k_bin_scatter, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, stream,
-                  (int32_t)n, cells->cell_in, cells->slot_in, cells->offsets, cells->perm_u);
-        PI_LAUNCH(ctx, "k_bin_finalize", k_bin_finalize, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, stream,
-                  (int32_t)n, nc, cells->perm_u, cells->cell_in, cells->offsets, x, y, z, w, g, cells->perm,
-                  cells->cell, cells->xs, cells->ys, cells->zs, cells->ws);
-    }
-    PI_CHECK_HIP(hipGetLastError());
-    return PI_OK;
+    return pi_bin_systems(ctx, cells, x, y, z, w, n, nc, 0, nullptr, g, stream);
 }

@@ -7,6 +7,8 @@
 // Constants of one sweep, derived on the host from rc (= h, the support).
 struct KernelConst {
     float lo, hi;       // filter on fl(r^2): < lo surely inside, >= hi surely outside
+    float reach2;       // rc^2 (1 + 16 u) rounded up: a cell whose nearest face is at
+                        // fl(distance^2) >= reach2 surely holds no pair inside the cutoff
     float hh, eh;       // h*h rounded to float, and its residual: h^2 = hh + eh exactly
     float hh_quarter;   // hh / 4 (exact): r^2 <= hh/4  <=>  q <= 1/2
     float h, inv_h;

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "../../include/pi.h"
 
 #define PI_CHECK_HIP(expr)                                  \
@@ -20,6 +23,13 @@ pi_status pi_hip_fail(hipError_t e, const char *what);
 
 struct pi_timing; // per-context kernel timing state (abi.hip)
 
+// Sweep-organisation choices of the tuner, keyed by a size/occupancy class.
+struct pi_tuner {
+    std::mutex mu;
+    std::map<uint64_t, int> choice; // class -> tile id (0 = no LDS)
+    int mode = 1;                   // PI_TUNE_STATIC / PI_TUNE_TIMED
+};
+
 struct pi_ctx {
     int device;
     int num_cu;
@@ -27,6 +37,7 @@ struct pi_ctx {
     size_t lds_per_block;
     volatile int timing_on;
     pi_timing *timing;
+    pi_tuner *tuner;
 };
 
 // Kernel timing: bracket one launch with events on its stream when enabled.
@@ -48,21 +59,27 @@ struct pi_cells {
     pi_grid grid;
     int64_t cap_n;      // capacity in particles
     int64_t cap_cells;  // capacity in cells
-    int64_t cap_tiles;  // scan tile partials
+    int64_t cap_tiles;  // scan tile partials (cells)
+    int64_t cap_hist;   // radix histogram entries (256 per sort tile)
     hipStream_t last_stream;
     bool binned;
     // per cell
     int32_t *counts;    // [cap_cells]
     int32_t *offsets;   // [cap_cells + 1]
-    // per particle, input order
-    int32_t *cell_in;   // [cap_n] cell of input particle i (-1 outside)
-    int32_t *slot_in;   // [cap_n] arrival slot inside the cell (atomic)
-    // per particle, sorted order
-    int32_t *perm_u;    // [cap_n] unstable sorted order (arrival order)
+    // per particle, sorted order (the results of binning)
     int32_t *perm;      // [cap_n] stable sorted order
     int32_t *cell;      // [cap_n] cell of sorted slot
     float *xs, *ys, *zs, *ws;   // [cap_n]
-    // scan scratch
+    // radix-sort ping-pong buffers: key, original index, x, y, z, w
+    uint32_t *skey[2];
+    int32_t *sidx[2];
+    float *sx[2], *sy[2], *sz[2], *sw[2];
+    // radix histograms (digit-major, 256 x sort tiles) and their scan scratch
+    int32_t *hist;        // [cap_hist]
+    int32_t *hist_tsum;   // [cap_hist / 4096 + 1]
+    int32_t *hist_tmax;
+    int32_t *hist_total;  // [1]
+    // cell-scan scratch
     int32_t *tile_sum;  // [cap_tiles]
     int32_t *tile_max;  // [cap_tiles]
     int32_t *max_per_cell; // [1]
@@ -135,3 +152,34 @@ __device__ __forceinline__ bool axis_index(float x, float o, float w, int32_t n,
 }
 
 pi_status pi_ensure_capacity(pi_cells *cells, int64_t n, int64_t n_cells, hipStream_t stream);
+
+// One system of a batch, as the batched kernels see it.  Systems are
+// concatenated in order: system s owns input (and sorted) particles
+// [first, first + n) and global cells [cell_base, cell_base + nx ny nz).
+struct SysDev {
+    int64_t first;
+    int32_t n;
+    int32_t cell_base;
+    int32_t block_base; // first workgroup of this system in a sweep launch
+    int32_t ntx, nty;   // tiles per axis in that launch
+    int32_t pad;
+    GridDev g;
+};
+
+bool pi_grid_valid(const pi_grid *g);
+
+struct KernelConst;
+struct pi_interact_opts;
+KernelConst pi_make_kernel_const(float rc, float cell_w);
+bool pi_tile_shape(int tile_id, int *tx, int *ty, int *tz);
+int pi_pick_tile(const pi_interact_opts &o, double ppc);
+int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys);
+pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
+                         int64_t total_blocks, int tile_id, const pi_interact_opts &o, float *rho, float *gx,
+                         float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);
+
+// Host-side binning of a concatenated set of systems (bin.hip): one radix
+// sort over global cell ids; sorted arrays hold local cell ids.
+pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const float *y, const float *z,
+                         const float *w, int64_t n_total, int64_t cells_total, int32_t nsys,
+                         const SysDev *d_sys, const GridDev &g0, hipStream_t stream);

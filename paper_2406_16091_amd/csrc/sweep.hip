@@ -37,7 +37,30 @@ struct SweepArgs {
     int32_t *count;
     InvPartial *partials;
     KernelConst k;
+    // batch mode: system table, per-system kernel constants
+    const SysDev *sys;
+    const KernelConst *kcs;
+    int32_t nsys;
 };
+
+// Batch mode: the system owning logical workgroup lb; narrows the sweep
+// arguments to that system (its grid, cell offsets and kernel constants).
+__device__ __forceinline__ int enter_system(SweepArgs &a, uint32_t lb)
+{
+    int lo = 0, hi = a.nsys; // sys[lo].block_base <= lb < sys[hi].block_base
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((uint32_t)a.sys[mid].block_base <= lb) lo = mid; else hi = mid;
+    }
+    const SysDev &sd = a.sys[lo];
+    a.nx = sd.g.nx;
+    a.ny = sd.g.ny;
+    a.nz = sd.g.nz;
+    a.nc = (int64_t)sd.g.nx * sd.g.ny * sd.g.nz;
+    a.off += sd.cell_base;
+    a.k = a.kcs[lo];
+    return lo;
+}
 
 template <int PREC, bool INV>
 __device__ __forceinline__ void write_target(const SweepArgs &a, int32_t k, const Target<PREC, INV> &T)
@@ -105,13 +128,20 @@ __device__ __forceinline__ void target_invariants(const Target<PREC, INV> &T, fl
 // One thread per sorted target; sources read through L1/L2 (Algorithm 1,
 // Par-Part-NoLoop, with targets in cell-sorted order so that a wavefront's
 // neighbour rows overlap in cache).
-template <int PREC, bool INV>
+template <int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
 {
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int32_t k = (int32_t)(lb * kBlock + threadIdx.x);
-    const int32_t nb = a.off[a.nc];
-    const bool active = k < nb && k < a.n;
+    int32_t k, kend;
+    if (BATCH) {
+        const SysDev &sd = a.sys[enter_system(a, lb)];
+        k = (int32_t)sd.first + (int32_t)(lb - sd.block_base) * kBlock + (int32_t)threadIdx.x;
+        kend = (int32_t)sd.first + sd.n;
+    } else {
+        k = (int32_t)(lb * kBlock + threadIdx.x);
+        kend = min(a.off[a.nc], a.n);
+    }
+    const bool active = k < kend;
     Target<PREC, INV> T;
     float wi = 0.f;
     if (active) {
@@ -162,40 +192,107 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
 // of global offsets (the paper's local-offset construction, Sec. 5.1).
 // TY = TZ = 1 is the X-pencil (Sec. 5.2), with all nine neighbour pencils
 // resident at once instead of streamed; larger TY, TZ is the full sub-box
-// (Sec. 5.1).  A tile whose halo holds more than CAP particles reads its
-// sources from global memory instead (same order, same results).
-template <int TX, int TY, int TZ, int CAP, int PREC, bool INV>
+// (Sec. 5.1).
+//
+// Staged x coordinates are relative to the first cell of their halo row, so
+// the (up to) three cells a target needs from one row form a single range:
+// 9 row segments per target instead of 27 cells.  Each lane first writes its
+// target's non-empty segments, in canonical order, into an LDS table; a
+// neighbour cell whose nearest face is provably beyond the cutoff (a
+// conservative test in squared distances) is left out of its segment, which
+// removes about a quarter of the candidates without changing which pairs are
+// accepted or their order.
+//
+// Candidate testing and pair evaluation are decoupled: each lane walks its
+// segments in lockstep with the wavefront and pushes every accepted pair
+// (dx, dy, dz, w_j) into a private FIFO of Q entries in LDS; whenever some
+// lane's FIFO is full, the wavefront pops one entry per non-empty lane and
+// evaluates the kernel.  Otherwise the wavefront would run the long
+// evaluation on almost every candidate step (about one candidate in six is
+// accepted, so some lane of 64 nearly always accepts).  FIFO order keeps each
+// target's accumulation order canonical, so results stay bit-identical to the
+// other organisations.
+//
+// A tile whose halo holds more than CAP particles is swept from global
+// memory with the plain per-lane walk over 27 cells (same order, same
+// results).
+template <int PREC, bool INV>
+__device__ __forceinline__ void walk_cells_global(const SweepArgs &a, int32_t k, int32_t ix, int32_t iy, int32_t iz,
+                                                  float xi, float yi, float zi, Target<PREC, INV> &T)
+{
+    const float W = a.k.w;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int32_t cz = iz + dz;
+        if (cz < 0 || cz >= a.nz) continue;
+        const float tz = zi - (float)dz * W;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int32_t cy = iy + dy;
+            if (cy < 0 || cy >= a.ny) continue;
+            const float ty = yi - (float)dy * W;
+            const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz);
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int32_t cx = ix + dx;
+                if (cx < 0 || cx >= a.nx) continue;
+                const float tx = xi - (float)dx * W;
+                const int32_t j0 = a.off[rb + cx], j1 = a.off[rb + cx + 1];
+                for (int32_t j = j0; j < j1; ++j) {
+                    const float ddx = tx - a.xs[j], ddy = ty - a.ys[j], ddz = tz - a.zs[j];
+                    const float t = sq_dist(ddx, ddy, ddz);
+                    if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k))
+                        T.accept(ddx, ddy, ddz, t, a.ws[j], a.k);
+                }
+            }
+        }
+    }
+}
+
+template <int TX, int TY, int TZ, int CAP, int Q, int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx, int32_t nty)
 {
     constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
     constexpr int R = HY * HZ;   // halo rows
     constexpr int TR = TY * TZ;  // target rows
     static_assert(R <= 64 && TR <= 64, "row tables are scanned by one wavefront");
+    static_assert((Q & (Q - 1)) == 0, "FIFO depth must be a power of two");
+    static_assert(CAP <= 4096, "segment table packs LDS indices in 12 bits");
     __shared__ float4 sp[CAP];
+    __shared__ int32_t fifo[kBlock / 64][Q][64]; // accepted source: LDS index | (dy,dz) code << 12
+    __shared__ int32_t segtab[9][kBlock]; // start | len << 12 | (dy,dz) code << 25
     __shared__ int32_t cs[R][HX + 1];
     __shared__ int32_t rstart[R + 1];
     __shared__ int32_t gstart[R];
+    __shared__ int32_t rbase[R];
     __shared__ int32_t tstart[TR + 1];
     __shared__ int32_t tfirst[TR];
 
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int32_t bx = (int32_t)(lb % (uint32_t)ntx);
-    const int32_t by = (int32_t)((lb / (uint32_t)ntx) % (uint32_t)nty);
-    const int32_t bz = (int32_t)(lb / ((uint32_t)ntx * (uint32_t)nty));
+    uint32_t tl = lb; // tile index within its system
+    if (BATCH) {
+        const SysDev &sd = a.sys[enter_system(a, lb)];
+        tl = lb - (uint32_t)sd.block_base;
+        ntx = sd.ntx;
+        nty = sd.nty;
+    }
+    const int32_t bx = (int32_t)(tl % (uint32_t)ntx);
+    const int32_t by = (int32_t)((tl / (uint32_t)ntx) % (uint32_t)nty);
+    const int32_t bz = (int32_t)(tl / ((uint32_t)ntx * (uint32_t)nty));
     const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
     const int32_t cxlo = max(x0 - 1, 0);
     const int32_t cxhi = min(x0 + TX, a.nx - 1);
     const int32_t ncx = cxhi - cxlo + 1;
     const int32_t txhi = min(x0 + TX, a.nx); // exclusive end of target cells
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const float W = a.k.w;
 
     // 1. halo row ranges and their LDS starts; target row ranges
     if (tid < 64) {
-        int32_t cnt = 0, gs = 0;
+        int32_t cnt = 0, gs = 0, rb32 = 0;
         if (tid < R) {
             const int32_t y = y0 - 1 + tid % HY, z = z0 - 1 + tid / HY;
             if (y >= 0 && y < a.ny && z >= 0 && z < a.nz) {
                 const int64_t rb = (int64_t)a.nx * (y + (int64_t)a.ny * z);
+                rb32 = (int32_t)rb;
                 gs = a.off[rb + cxlo];
                 cnt = a.off[rb + cxhi + 1] - gs;
             }
@@ -204,6 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         if (tid < R) {
             rstart[tid] = inc - cnt;
             gstart[tid] = gs;
+            rbase[tid] = rb32;
         }
         if (tid == R - 1) rstart[R] = inc;
 
@@ -225,107 +323,161 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     }
     __syncthreads();
     const int32_t total = rstart[R];
-    const bool staged = total <= CAP;
+    const int32_t ntarget = tstart[TR];
+    long long icnt = 0;
+    double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
 
-    // 2. start of every halo cell in source space (LDS index when staged,
-    //    sorted global index otherwise)
+    if (total > CAP) {
+        // halo too large for LDS: sweep this tile from global memory
+        for (int32_t f = tid; f < ntarget; f += kBlock) {
+            int lo = 0, hi = TR;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (tstart[mid] <= f) lo = mid; else hi = mid;
+            }
+            const int32_t k = tfirst[lo] + (f - tstart[lo]);
+            const int32_t y = y0 + lo % TY, z = z0 + lo / TY;
+            const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
+            Target<PREC, INV> T;
+            walk_cells_global(a, k, ix, y, z, a.xs[k], a.ys[k], a.zs[k], T);
+            write_target(a, k, T);
+            if (INV) {
+                long long c1;
+                double a1, a2, a3, a4, a5;
+                target_invariants(T, a.ws[k], c1, a1, a2, a3, a4, a5);
+                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
+            }
+        }
+        if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
+        return;
+    }
+
+    // 2. LDS start of every halo cell
     for (int e = tid; e < R * (HX + 1); e += kBlock) {
         const int r = e / (HX + 1), jj = e % (HX + 1);
         const int32_t y = y0 - 1 + r % HY, z = z0 - 1 + r / HY;
         int32_t v = 0;
-        if (jj <= ncx && y >= 0 && y < a.ny && z >= 0 && z < a.nz) {
-            const int64_t rb = (int64_t)a.nx * (y + (int64_t)a.ny * z);
-            const int32_t g = a.off[rb + cxlo + jj];
-            v = staged ? g - gstart[r] + rstart[r] : g;
-        }
+        if (jj <= ncx && y >= 0 && y < a.ny && z >= 0 && z < a.nz)
+            v = a.off[(int64_t)rbase[r] + cxlo + jj] - gstart[r] + rstart[r];
         cs[r][jj] = v;
     }
-    // 3. stage the halo particles (flat index -> row by binary search)
-    if (staged) {
-        for (int32_t f = tid; f < total; f += kBlock) {
-            int lo = 0, hi = R; // rstart[lo] <= f < rstart[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (rstart[mid] <= f) lo = mid; else hi = mid;
-            }
-            const int32_t g = gstart[lo] + (f - rstart[lo]);
-            sp[f] = make_float4(a.xs[g], a.ys[g], a.zs[g], a.ws[g]);
+    // 3. stage the halo particles, x relative to the row's first cell
+    for (int32_t f = tid; f < total; f += kBlock) {
+        int lo = 0, hi = R; // rstart[lo] <= f < rstart[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (rstart[mid] <= f) lo = mid; else hi = mid;
         }
+        const int32_t g = gstart[lo] + (f - rstart[lo]);
+        const int32_t cx = a.cell[g] - rbase[lo];
+        sp[f] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, a.xs[g]), a.ys[g], a.zs[g], a.ws[g]);
     }
     __syncthreads();
 
-    // 4. targets
-    const int32_t ntarget = tstart[TR];
-    long long icnt = 0;
-    double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
-    const float W = a.k.w;
-    for (int32_t f = tid; f < ntarget; f += kBlock) {
-        int lo = 0, hi = TR;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (tstart[mid] <= f) lo = mid; else hi = mid;
-        }
-        const int32_t k = tfirst[lo] + (f - tstart[lo]);
-        const int32_t ty_ = lo % TY, tz_ = lo / TY;
-        const int32_t y = y0 + ty_, z = z0 + tz_;
-        const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
-        const int hr = (ty_ + 1) + HY * (tz_ + 1); // halo row of the target
-        float xi, yi, zi, wi;
-        int32_t self;
-        if (staged) {
+    // 4. targets, in rounds of one per thread
+    int32_t *myq = &fifo[wid][0][lane];
+    const float reach2 = a.k.reach2; // conservative squared reach
+    for (int32_t f0 = 0; f0 < ntarget; f0 += kBlock) {
+        const int32_t f = f0 + tid;
+        const bool tgt = f < ntarget;
+        int32_t k = 0, self = -1, nseg = 0;
+        float xt = 0.f, yt = 0.f, zt = 0.f, wi = 0.f;
+        if (tgt) {
+            int lo = 0, hi = TR;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (tstart[mid] <= f) lo = mid; else hi = mid;
+            }
+            k = tfirst[lo] + (f - tstart[lo]);
+            const int32_t ty_ = lo % TY, tz_ = lo / TY;
+            const int32_t y = y0 + ty_, z = z0 + tz_;
+            const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
+            const int hr = (ty_ + 1) + HY * (tz_ + 1);
             self = rstart[hr] + (k - gstart[hr]);
             const float4 p = sp[self];
-            xi = p.x; yi = p.y; zi = p.z; wi = p.w;
-        } else {
-            self = k;
-            xi = a.xs[k]; yi = a.ys[k]; zi = a.zs[k]; wi = a.ws[k];
-        }
-        Target<PREC, INV> T;
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int32_t cz = z + dz;
-            if (cz < 0 || cz >= a.nz) continue;
-            const float tz = zi - (float)dz * W;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int32_t cy = y + dy;
-                if (cy < 0 || cy >= a.ny) continue;
-                const float tyy = yi - (float)dy * W;
-                const int r = (ty_ + 1 + dy) + HY * (tz_ + 1 + dz);
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int32_t cx = ix + dx;
-                    if (cx < 0 || cx >= a.nx) continue;
-                    const float tx = xi - (float)dx * W;
-                    const int jj = cx - cxlo;
-                    const int32_t j0 = cs[r][jj], j1 = cs[r][jj + 1];
-                    if (staged) {
-                        for (int32_t j = j0; j < j1; ++j) {
-                            const float4 s = sp[j];
-                            const float ddx = tx - s.x, ddy = tyy - s.y, ddz = tz - s.z;
-                            const float t = sq_dist(ddx, ddy, ddz);
-                            if (t < a.k.hi && j != self && inside_cutoff(ddx, ddy, ddz, t, a.k))
-                                T.accept(ddx, ddy, ddz, t, s.w, a.k);
-                        }
-                    } else {
-                        for (int32_t j = j0; j < j1; ++j) {
-                            const float ddx = tx - a.xs[j], ddy = tyy - a.ys[j], ddz = tz - a.zs[j];
-                            const float t = sq_dist(ddx, ddy, ddz);
-                            if (t < a.k.hi && j != self && inside_cutoff(ddx, ddy, ddz, t, a.k))
-                                T.accept(ddx, ddy, ddz, t, a.ws[j], a.k);
-                        }
+            xt = p.x; yt = p.y; zt = p.z; wi = p.w;
+            const float xc = a.xs[k]; // cell-relative x of the target
+            const float gxl = xc * xc, gxr = (W - xc) * (W - xc);
+            const float gyl = yt * yt, gyr = (W - yt) * (W - yt);
+            const float gzl = zt * zt, gzr = (W - zt) * (W - zt);
+            const int32_t jc = ix - cxlo;
+            // segments in canonical (dz, dy) order
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int32_t cz = z + dz;
+                if (cz < 0 || cz >= a.nz) continue;
+                const float gz = dz < 0 ? gzl : (dz > 0 ? gzr : 0.f);
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int32_t cy = y + dy;
+                    if (cy < 0 || cy >= a.ny) continue;
+                    const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + gz;
+                    if (gyz >= reach2) continue; // the whole row is out of reach
+                    const bool left = ix > 0 && gxl + gyz < reach2;
+                    const bool right = ix + 1 < a.nx && gxr + gyz < reach2;
+                    const int r = (ty_ + 1 + dy) + HY * (tz_ + 1 + dz);
+                    const int32_t s0 = cs[r][jc - (left ? 1 : 0)];
+                    const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
+                    if (s1 > s0) {
+                        segtab[nseg][tid] = s0 | ((s1 - s0) << 12) | (((dy + 1) * 3 + (dz + 1)) << 25);
+                        ++nseg;
                     }
                 }
             }
         }
-        write_target(a, k, T);
-        if (INV) {
-            long long c1;
-            double a1, a2, a3, a4, a5;
-            target_invariants(T, wi, c1, a1, a2, a3, a4, a5);
-            icnt += c1;
-            inx += a1;
-            iny += a2;
-            inz += a3;
-            isc += a4;
-            irs += a5;
+        Target<PREC, INV> T;
+        int seg = 0, qh = 0, qc = 0, code = 0;
+        int32_t j = 0, jend = 0;
+        float tyy = 0.f, tzz = 0.f;
+        // Evaluate the oldest queued pair of this lane: the differences are
+        // recomputed from the same operands, so they are bit-identical to the
+        // ones the test used.
+        auto pop = [&]() {
+            const int32_t e = myq[qh * 64];
+            qh = (qh + 1) & (Q - 1);
+            --qc;
+            const float4 s = sp[e & 4095];
+            const int c = e >> 12;
+            const float ey = yt - (float)(c / 3 - 1) * W, ez = zt - (float)(c % 3 - 1) * W;
+            const float ddx = xt - s.x, ddy = ey - s.y, ddz = ez - s.z;
+            T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
+        };
+        while (true) {
+            if (j >= jend && seg < nseg) {
+                const int32_t sg = segtab[seg][tid];
+                ++seg;
+                j = sg & 4095;
+                jend = j + ((sg >> 12) & 8191);
+                code = sg >> 25;
+                const int dy = code / 3 - 1, dz = code % 3 - 1;
+                tyy = yt - (float)dy * W;
+                tzz = zt - (float)dz * W;
+            }
+            const bool have = j < jend;
+            if (!__any(have)) break;
+            if (have) {
+                const float4 s = sp[j];
+                const float ddx = xt - s.x, ddy = tyy - s.y, ddz = tzz - s.z;
+                const float t = sq_dist(ddx, ddy, ddz);
+                if (t < a.k.hi && j != self && inside_cutoff(ddx, ddy, ddz, t, a.k)) {
+                    myq[((qh + qc) & (Q - 1)) * 64] = j | (code << 12);
+                    ++qc;
+                }
+                ++j;
+            }
+            if (__any(qc == Q)) {
+                if (qc > 0) pop();
+            }
+        }
+        while (__any(qc > 0)) {
+            if (qc > 0) pop();
+        }
+        if (tgt) {
+            write_target(a, k, T);
+            if (INV) {
+                long long c1;
+                double a1, a2, a3, a4, a5;
+                target_invariants(T, wi, c1, a1, a2, a3, a4, a5);
+                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
+            }
         }
     }
     if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
@@ -409,6 +561,39 @@ __global__ __launch_bounds__(kBlock) void k_inv_stage2(const InvPartial *__restr
     }
 }
 
+// Batch mode: invariants of system s from its workgroups' partials
+// [block_base[s], block_base[s+1]) (one workgroup per system, fixed order).
+__global__ __launch_bounds__(kBlock) void k_inv_systems(const InvPartial *__restrict__ parts,
+                                                        const SysDev *__restrict__ sys, int32_t nsys,
+                                                        int32_t total_blocks, pi_invariants *__restrict__ out)
+{
+    __shared__ double red[kBlock][5];
+    __shared__ long long redc[kBlock];
+    const int s = blockIdx.x;
+    const int32_t b0 = sys[s].block_base;
+    const int32_t b1 = s + 1 < nsys ? sys[s + 1].block_base : total_blocks;
+    long long c = 0;
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int32_t i = b0 + (int32_t)threadIdx.x; i < b1; i += kBlock) {
+        const InvPartial p = parts[i];
+        c += p.pairs;
+        v[0] += p.net[0];
+        v[1] += p.net[1];
+        v[2] += p.net[2];
+        v[3] += p.scale;
+        v[4] += p.rho_sum;
+    }
+    inv_block_reduce(c, v, redc, red);
+    if (threadIdx.x == 0) {
+        out[s].pairs = redc[0];
+        out[s].net[0] = red[0][0];
+        out[s].net[1] = red[0][1];
+        out[s].net[2] = red[0][2];
+        out[s].scale = red[0][3];
+        out[s].rho_sum = red[0][4];
+    }
+}
+
 __global__ void k_inv_zero(pi_invariants *__restrict__ out)
 {
     if (threadIdx.x == 0) {
@@ -421,7 +606,9 @@ __global__ void k_inv_zero(pi_invariants *__restrict__ out)
 
 // ------------------------------------------------------------------ host side
 
-KernelConst make_kernel_const(float rc, float cell_w)
+} // namespace
+
+KernelConst pi_make_kernel_const(float rc, float cell_w)
 {
     KernelConst k;
     const float h = rc;
@@ -430,6 +617,7 @@ KernelConst make_kernel_const(float rc, float cell_w)
     const double u = ldexp(1.0, -24);
     k.lo = nextafterf((float)(r2 * (1.0 - 4.0 * u)), 0.0f);
     k.hi = nextafterf((float)(r2 * (1.0 + 4.0 * u)), INFINITY);
+    k.reach2 = nextafterf((float)(r2 * (1.0 + 16.0 * u)), INFINITY);
     k.hh = h * h;
     k.eh = fmaf(h, h, -k.hh);
     k.hh_quarter = k.hh * 0.25f;
@@ -444,6 +632,8 @@ KernelConst make_kernel_const(float rc, float cell_w)
     return k;
 }
 
+namespace {
+
 // Tile shapes compiled in.  id: 0 = no LDS; 1.. = tiles.
 struct TileCfg {
     int id;
@@ -452,58 +642,296 @@ struct TileCfg {
 };
 
 const TileCfg kTiles[] = {
-    {1, 254, 1, 1, 3072, PI_SWEEP_PENCIL},
-    {2, 62, 1, 1, 3072, PI_SWEEP_PENCIL},
-    {3, 30, 1, 1, 3072, PI_SWEEP_PENCIL},
-    {4, 8, 8, 4, 1536, PI_SWEEP_SUBBOX},
-    {5, 4, 4, 4, 2048, PI_SWEEP_SUBBOX},
-    {6, 4, 4, 2, 2048, PI_SWEEP_SUBBOX},
+    {1, 254, 1, 1, 2560, PI_SWEEP_PENCIL},
+    {2, 62, 1, 1, 1024, PI_SWEEP_PENCIL},
+    {3, 30, 1, 1, 2560, PI_SWEEP_PENCIL},
+    {4, 8, 8, 3, 768, PI_SWEEP_SUBBOX},
+    {5, 6, 6, 6, 768, PI_SWEEP_SUBBOX},
+    {6, 4, 4, 4, 1536, PI_SWEEP_SUBBOX},
+    {7, 4, 4, 2, 1536, PI_SWEEP_SUBBOX},
+    {8, 16, 4, 3, 768, PI_SWEEP_SUBBOX},
 };
 
-template <int TX, int TY, int TZ, int CAP, int PREC, bool INV>
+constexpr int kFifo = 8;
+
+// nblk: in single-system mode computed here from the grid; in batch mode
+// given (the sum of the systems' tile counts).
+template <int TX, int TY, int TZ, int CAP, int PREC, bool INV, bool BATCH>
 void launch_tile(pi_ctx *ctx, const char *name, const SweepArgs &a, hipStream_t s, unsigned &nblk)
 {
-    const int32_t ntx = (a.nx + TX - 1) / TX, nty = (a.ny + TY - 1) / TY, ntz = (a.nz + TZ - 1) / TZ;
-    nblk = (unsigned)((int64_t)ntx * nty * ntz);
-    PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, PREC, INV>), dim3(nblk), dim3(kBlock), 0, s, a, ntx, nty);
+    int32_t ntx = 0, nty = 0;
+    if (!BATCH) {
+        ntx = (a.nx + TX - 1) / TX;
+        nty = (a.ny + TY - 1) / TY;
+        const int32_t ntz = (a.nz + TZ - 1) / TZ;
+        nblk = (unsigned)((int64_t)ntx * nty * ntz);
+    }
+    PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0, s,
+              a, ntx, nty);
 }
 
-template <int PREC, bool INV>
+template <int PREC, bool INV, bool BATCH>
 void launch_sweep(pi_ctx *ctx, int tile_id, const SweepArgs &a, hipStream_t s, unsigned &nblk)
 {
     switch (tile_id) {
-    case 1: launch_tile<254, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_tile<254,1,1>", a, s, nblk); break;
-    case 2: launch_tile<62, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_tile<62,1,1>", a, s, nblk); break;
-    case 3: launch_tile<30, 1, 1, 3072, PREC, INV>(ctx, "k_sweep_tile<30,1,1>", a, s, nblk); break;
-    case 4: launch_tile<8, 8, 4, 1536, PREC, INV>(ctx, "k_sweep_tile<8,8,4>", a, s, nblk); break;
-    case 5: launch_tile<4, 4, 4, 2048, PREC, INV>(ctx, "k_sweep_tile<4,4,4>", a, s, nblk); break;
-    case 6: launch_tile<4, 4, 2, 2048, PREC, INV>(ctx, "k_sweep_tile<4,4,2>", a, s, nblk); break;
+    case 1: launch_tile<254, 1, 1, 2560, PREC, INV, BATCH>(ctx, "k_sweep_tile<254,1,1>", a, s, nblk); break;
+    case 2: launch_tile<62, 1, 1, 1024, PREC, INV, BATCH>(ctx, "k_sweep_tile<62,1,1>", a, s, nblk); break;
+    case 3: launch_tile<30, 1, 1, 2560, PREC, INV, BATCH>(ctx, "k_sweep_tile<30,1,1>", a, s, nblk); break;
+    case 4: launch_tile<8, 8, 3, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<8,8,3>", a, s, nblk); break;
+    case 5: launch_tile<6, 6, 6, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<6,6,6>", a, s, nblk); break;
+    case 6: launch_tile<4, 4, 4, 1536, PREC, INV, BATCH>(ctx, "k_sweep_tile<4,4,4>", a, s, nblk); break;
+    case 7: launch_tile<4, 4, 2, 1536, PREC, INV, BATCH>(ctx, "k_sweep_tile<4,4,2>", a, s, nblk); break;
+    case 8: launch_tile<16, 4, 3, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<16,4,3>", a, s, nblk); break;
     default:
-        nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
-        if (nblk == 0) nblk = 1;
-        PI_LAUNCH(ctx, "k_sweep_nolds", (k_sweep_nolds<PREC, INV>), dim3(nblk), dim3(kBlock), 0, s, a);
+        if (!BATCH) {
+            nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
+            if (nblk == 0) nblk = 1;
+        }
+        PI_LAUNCH(ctx, "k_sweep_nolds", (k_sweep_nolds<PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0, s, a);
         break;
     }
 }
 
-int pick_tile(const pi_interact_opts &o, double ppc)
+template <bool BATCH>
+void launch_sweep_prec(pi_ctx *ctx, int prec, bool inv, int tile_id, const SweepArgs &a, hipStream_t s,
+                       unsigned &nblk)
+{
+    switch (prec) {
+    case PI_PREC_PLAIN:
+        if (inv) launch_sweep<PI_PREC_PLAIN, true, BATCH>(ctx, tile_id, a, s, nblk);
+        else if (!BATCH) launch_sweep<PI_PREC_PLAIN, false, false>(ctx, tile_id, a, s, nblk);
+        break;
+    case PI_PREC_FP64ACC:
+        if (inv) launch_sweep<PI_PREC_FP64ACC, true, BATCH>(ctx, tile_id, a, s, nblk);
+        else if (!BATCH) launch_sweep<PI_PREC_FP64ACC, false, false>(ctx, tile_id, a, s, nblk);
+        break;
+    default:
+        if (inv) launch_sweep<PI_PREC_COMPENSATED, true, BATCH>(ctx, tile_id, a, s, nblk);
+        else if (!BATCH) launch_sweep<PI_PREC_COMPENSATED, false, false>(ctx, tile_id, a, s, nblk);
+        break;
+    }
+}
+
+int pick_tile_default(double ppc)
+{
+    return ppc <= 2.0 ? 5 : (ppc <= 5.0 ? 6 : 0);
+}
+
+} // namespace
+
+bool pi_tile_shape(int tile_id, int *tx, int *ty, int *tz)
+{
+    for (const TileCfg &t : kTiles)
+        if (t.id == tile_id) {
+            *tx = t.tx;
+            *ty = t.ty;
+            *tz = t.tz;
+            return true;
+        }
+    return false;
+}
+
+// Tile id for explicit options; -1 if the shape is not compiled in; AUTO
+// returns the static default (the tuner refines it per system).
+int pi_pick_tile(const pi_interact_opts &o, double ppc)
 {
     if (o.sweep == PI_SWEEP_NOLDS) return 0;
     if (o.sweep == PI_SWEEP_PENCIL || o.sweep == PI_SWEEP_SUBBOX) {
-        // an explicit tile shape must be one of the compiled ones
         if (o.tile[0] > 0) {
             for (const TileCfg &t : kTiles)
                 if (t.sweep == o.sweep && t.tx == o.tile[0] && t.ty == o.tile[1] && t.tz == o.tile[2]) return t.id;
             return -1;
         }
         if (o.sweep == PI_SWEEP_PENCIL) return ppc <= 2.0 ? 1 : (ppc <= 5.0 ? 2 : 3);
-        return ppc <= 2.0 ? 4 : (ppc <= 5.0 ? 5 : 6);
+        return ppc <= 2.0 ? 5 : (ppc <= 5.0 ? 6 : 7);
     }
-    // AUTO
-    return ppc <= 2.0 ? 4 : (ppc <= 5.0 ? 5 : 6);
+    return pick_tile_default(ppc);
+}
+
+// Batch sweep: h_sys gets each system's block_base / ntx / nty for tile_id
+// (the caller uploads the table to d_sys before launching).  Returns the
+// total workgroup count.
+int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys)
+{
+    int tx = 0, ty = 0, tz = 0;
+    const bool tiled = tile_id > 0 && pi_tile_shape(tile_id, &tx, &ty, &tz);
+    int64_t base = 0;
+    for (int32_t s = 0; s < nsys; ++s) {
+        SysDev &d = h_sys[s];
+        d.block_base = (int32_t)base;
+        if (tiled) {
+            d.ntx = (d.g.nx + tx - 1) / tx;
+            d.nty = (d.g.ny + ty - 1) / ty;
+            const int32_t ntz = (d.g.nz + tz - 1) / tz;
+            base += (int64_t)d.ntx * d.nty * ntz;
+        } else {
+            d.ntx = d.nty = 0;
+            base += (d.n + kBlock - 1) / kBlock;
+        }
+    }
+    return base;
+}
+
+pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
+                         int64_t total_blocks, int tile_id, const pi_interact_opts &o, float *rho, float *gx,
+                         float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream)
+{
+    if (total_blocks > cells->cap_partials) return PI_ENOMEM;
+    SweepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.off = cells->offsets;
+    a.cell = cells->cell;
+    a.perm = cells->perm;
+    a.xs = cells->xs;
+    a.ys = cells->ys;
+    a.zs = cells->zs;
+    a.ws = cells->ws;
+    a.n = (int32_t)cells->n;
+    a.orig_order = o.order == PI_ORDER_ORIGINAL;
+    a.rho = rho;
+    a.gx = gx;
+    a.gy = gy;
+    a.gz = gz;
+    a.count = count;
+    a.partials = (InvPartial *)cells->partials;
+    a.sys = d_sys;
+    a.kcs = d_kcs;
+    a.nsys = nsys;
+    unsigned nblk = (unsigned)total_blocks;
+    if (nblk > 0) launch_sweep_prec<true>(ctx, o.precision, true, tile_id, a, stream, nblk);
+    if (inv)
+        PI_LAUNCH(ctx, "k_inv_systems", k_inv_systems, dim3(nsys), dim3(kBlock), 0, stream,
+                  (const InvPartial *)a.partials, d_sys, nsys, (int32_t)total_blocks, inv);
+    PI_CHECK_HIP(hipGetLastError());
+    return PI_OK;
+}
+
+namespace {
+
+uint64_t tune_key(int prec, int64_t n, double ppc, bool batch)
+{
+    const int kn = n > 1 ? (int)floor(2.0 * log2((double)n)) : 0;
+    const int kp = (int)fmin(1023.0, floor(4.0 * ppc + 0.5));
+    return (uint64_t)prec + 4ull * (uint64_t)kn + 256ull * (uint64_t)kp + (batch ? (1ull << 30) : 0ull);
+}
+
+// Time every compiled organisation on this system (second of two runs,
+// without invariants) and return the fastest; the outputs in `a` are
+// overwritten.
+int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, hipStream_t s)
+{
+    SweepArgs a = a0;
+    a.partials = nullptr;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1;
+    }
+    const int was = ctx->timing_on;
+    ctx->timing_on = 0;
+    int best = -1;
+    float best_ms = 0.f;
+    for (int cand = 0; cand <= 8; ++cand) {
+        unsigned nblk = 0;
+        float ms = 0.f;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
+            ok = hipEventRecord(e0, s) == hipSuccess;
+            launch_sweep_prec<false>(ctx, prec, false, cand, a, s, nblk);
+            ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        }
+        if (ok && (best < 0 || ms < best_ms)) {
+            best = cand;
+            best_ms = ms;
+        }
+    }
+    ctx->timing_on = was;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+pi_status tuned_tile(pi_ctx *ctx, const SweepArgs &a, int prec, int64_t n, double ppc, hipStream_t s, int *tile)
+{
+    pi_tuner *t = ctx->tuner;
+    *tile = pick_tile_default(ppc);
+    if (!t || t->mode != PI_TUNE_TIMED) return PI_OK;
+    const uint64_t key = tune_key(prec, n, ppc, false);
+    {
+        std::lock_guard<std::mutex> g(t->mu);
+        auto it = t->choice.find(key);
+        if (it != t->choice.end()) {
+            *tile = it->second;
+            return PI_OK;
+        }
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PI_OK;
+    const int best = time_candidates(ctx, a, prec, s);
+    if (best < 0) return PI_EDEVICE;
+    std::lock_guard<std::mutex> g(t->mu);
+    t->choice[key] = best;
+    *tile = best;
+    return PI_OK;
 }
 
 } // namespace
+
+extern "C" pi_status pi_tuner_mode(pi_ctx *ctx, int32_t mode)
+{
+    if (!ctx || !ctx->tuner || (mode != PI_TUNE_STATIC && mode != PI_TUNE_TIMED)) return PI_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->tuner->mu);
+    ctx->tuner->mode = mode;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t precision, pi_interact_opts *out,
+                                     pi_stream stream)
+{
+    if (!ctx || !cells || !out || cells->ctx != ctx) return PI_EINVAL;
+    if (!cells->binned) return PI_ESTATE;
+    if (precision < PI_PREC_COMPENSATED || precision > PI_PREC_FP64ACC) return PI_EINVAL;
+    const int64_t n = cells->n;
+    const double ppc = cells->n_cells > 0 ? (double)n / (double)cells->n_cells : 0.0;
+    int tile = pick_tile_default(ppc);
+    if (n > 0) {
+        SweepArgs a;
+        memset(&a, 0, sizeof(a));
+        a.off = cells->offsets;
+        a.cell = cells->cell;
+        a.perm = cells->perm;
+        a.xs = cells->xs;
+        a.ys = cells->ys;
+        a.zs = cells->zs;
+        a.ws = cells->ws;
+        a.nc = cells->n_cells;
+        a.n = (int32_t)n;
+        a.nx = cells->grid.dims[0];
+        a.ny = cells->grid.dims[1];
+        a.nz = cells->grid.dims[2];
+        a.k = pi_make_kernel_const(cells->grid.rc, cells->grid.cell_w);
+        // count-only outputs so that tuning writes nothing the caller owns
+        a.rho = a.gx = a.gy = a.gz = nullptr;
+        a.count = nullptr;
+        PI_CHECK_HIP(hipSetDevice(ctx->device));
+        pi_status st = tuned_tile(ctx, a, precision, n, ppc, (hipStream_t)stream, &tile);
+        if (st != PI_OK) return st;
+    }
+    memset(out, 0, sizeof(*out));
+    out->precision = precision;
+    int tx = 0, ty = 0, tz = 0;
+    if (tile > 0 && pi_tile_shape(tile, &tx, &ty, &tz)) {
+        out->sweep = (ty == 1 && tz == 1) ? PI_SWEEP_PENCIL : PI_SWEEP_SUBBOX;
+        out->tile[0] = tx;
+        out->tile[1] = ty;
+        out->tile[2] = tz;
+    } else {
+        out->sweep = PI_SWEEP_NOLDS;
+    }
+    return PI_OK;
+}
 
 extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts *opts, float *rho,
                                  float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv,
@@ -526,10 +954,11 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
     PI_CHECK_HIP(hipSetDevice(ctx->device));
 
     const double ppc = cells->n_cells > 0 ? (double)n / (double)cells->n_cells : 0.0;
-    const int tile = pick_tile(o, ppc);
+    int tile = pi_pick_tile(o, ppc);
     if (tile < 0) return PI_EINVAL;
 
     SweepArgs a;
+    memset(&a, 0, sizeof(a));
     a.off = cells->offsets;
     a.cell = cells->cell;
     a.perm = cells->perm;
@@ -549,12 +978,17 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
     a.gz = gz;
     a.count = count;
     a.partials = (InvPartial *)cells->partials;
-    a.k = make_kernel_const(cells->grid.rc, cells->grid.cell_w);
+    a.k = pi_make_kernel_const(cells->grid.rc, cells->grid.cell_w);
 
     if (n == 0) {
         if (inv) PI_LAUNCH(ctx, "k_inv_zero", k_inv_zero, dim3(1), dim3(64), 0, stream, inv);
         PI_CHECK_HIP(hipGetLastError());
         return PI_OK;
+    }
+
+    if (o.sweep == PI_SWEEP_AUTO) {
+        pi_status ts = tuned_tile(ctx, a, o.precision, n, ppc, stream, &tile);
+        if (ts != PI_OK) return ts;
     }
 
     // enough partial records for any tiling of this grid
@@ -575,20 +1009,7 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
             a.partials = (InvPartial *)mc->partials;
         }
     }
-    switch (o.precision) {
-    case PI_PREC_PLAIN:
-        if (want_inv) launch_sweep<PI_PREC_PLAIN, true>(ctx, tile, a, stream, nblk);
-        else launch_sweep<PI_PREC_PLAIN, false>(ctx, tile, a, stream, nblk);
-        break;
-    case PI_PREC_FP64ACC:
-        if (want_inv) launch_sweep<PI_PREC_FP64ACC, true>(ctx, tile, a, stream, nblk);
-        else launch_sweep<PI_PREC_FP64ACC, false>(ctx, tile, a, stream, nblk);
-        break;
-    default:
-        if (want_inv) launch_sweep<PI_PREC_COMPENSATED, true>(ctx, tile, a, stream, nblk);
-        else launch_sweep<PI_PREC_COMPENSATED, false>(ctx, tile, a, stream, nblk);
-        break;
-    }
+    launch_sweep_prec<false>(ctx, o.precision, want_inv, tile, a, stream, nblk);
     if (want_inv) {
         // stage-1 records go after the sweep's records in the same buffer
         const int32_t n1 = (int32_t)((nblk + kInvRun - 1) / kInvRun);

@@ -129,3 +129,80 @@ def _copy_d2d(dst: int, src: int, nbytes: int):
     st = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), ctypes.c_size_t(nbytes), 3)
     if st != 0:
         raise RuntimeError(f"hipMemcpy failed: {st}")
+
+
+class DeviceBatch:
+    """Many systems concatenated on the GPU and run through pi_batch_run."""
+
+    def __init__(self, systems, device: int = 0, ctx: Context | None = None):
+        self.systems = list(systems)
+        self.ctx = ctx or Context.get(device)
+        self.dev = torch.device("cuda", device)
+        cat = lambda k: torch.from_numpy(np.ascontiguousarray(
+            np.concatenate([getattr(s, k) for s in self.systems]).astype(np.float32))).to(self.dev)
+        self.x, self.y, self.z, self.w = cat("x"), cat("y"), cat("z"), cat("w")
+        self.descs = pi.make_system_descs(self.systems)
+        self.offsets = [int(self.descs[i].offset) for i in range(len(self.systems))]
+        n = sum(s.n for s in self.systems)
+        self.n = n
+        f = dict(dtype=torch.float32, device=self.dev)
+        self.rho = torch.empty(max(n, 1), **f)
+        self.gx = torch.empty(max(n, 1), **f)
+        self.gy = torch.empty(max(n, 1), **f)
+        self.gz = torch.empty(max(n, 1), **f)
+        self.count = torch.empty(max(n, 1), dtype=torch.int32, device=self.dev)
+        self.inv = torch.zeros(pi.INV_BYTES * len(self.systems), dtype=torch.uint8, device=self.dev)
+        self.batch = pi.pi_batch_create(self.ctx.handle)
+
+    def close(self):
+        if self.batch is not None:
+            pi.pi_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, precision="compensated", sweep="auto", order="original", tile=(0, 0, 0), stream=None):
+        opts = pi.make_opts(precision, sweep, order, tile)
+        pi.pi_batch_run(self.ctx.handle, self.batch, self.descs, self.x, self.y, self.z, self.w, opts,
+                        self.rho, self.gx, self.gy, self.gz, self.count, self.inv, stream)
+
+    def sync(self, stream=None):
+        pi.pi_batch_sync(self.ctx.handle, self.batch, stream)
+
+    def results(self):
+        """Per-system dicts of numpy outputs (original order)."""
+        allr = {k: getattr(self, k)[:self.n].cpu().numpy() for k in ("rho", "gx", "gy", "gz", "count")}
+        out = []
+        for s, off in zip(self.systems, self.offsets):
+            out.append({k: v[off:off + s.n] for k, v in allr.items()})
+        return out
+
+    def invariants(self):
+        raw = self.inv.cpu().numpy().tobytes()
+        res = []
+        for i in range(len(self.systems)):
+            r = pi.pi_invariants.from_buffer_copy(raw[i * pi.INV_BYTES:(i + 1) * pi.INV_BYTES])
+            res.append({"pairs": int(r.pairs), "net": [r.net[0], r.net[1], r.net[2]],
+                        "scale": float(r.scale), "rho_sum": float(r.rho_sum)})
+        return res
+
+    def binned(self):
+        """Concatenated binned arrays and each system's first global cell."""
+        v, cell_base = pi.pi_batch_get_view(self.batch, len(self.systems))
+        n, nc = int(v.n), int(v.n_cells)
+        out = {}
+        torch.cuda.synchronize(self.dev)
+        for name, cnt, dt in (("counts", nc, torch.int32), ("offsets", nc + 1, torch.int32),
+                              ("perm", n, torch.int32), ("cell", n, torch.int32),
+                              ("xs", n, torch.float32), ("ys", n, torch.float32),
+                              ("zs", n, torch.float32), ("ws", n, torch.float32)):
+            t = torch.empty(max(cnt, 1), dtype=dt, device=self.dev)
+            if cnt > 0:
+                _copy_d2d(t.data_ptr(), getattr(v, name), cnt * 4)
+            out[name] = t[:cnt].cpu().numpy()
+        out["cell_base"] = cell_base
+        return out

@@ -58,6 +58,35 @@ class pi_invariants(ctypes.Structure):
                 ("scale", ctypes.c_double), ("rho_sum", ctypes.c_double)]
 
 
+class pi_system_desc(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("n", ctypes.c_int64), ("grid", pi_grid)]
+
+
+class pi_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("max_slots", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class pi_request(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("grid", pi_grid), ("n_sweeps", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("sweep", ctypes.c_int32), ("jitter_sigma", ctypes.c_float),
+                ("lattice", ctypes.c_float), ("pad", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class pi_result(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("status", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("sweeps", ctypes.c_int32), ("pad", ctypes.c_int32), ("pairs_total", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("rho", ctypes.c_void_p), ("gx", ctypes.c_void_p), ("gy", ctypes.c_void_p),
+                ("gz", ctypes.c_void_p), ("count", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("z", ctypes.c_void_p), ("invariants", ctypes.c_void_p)]
+
+
+class pi_server_stats_t(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("hbm_in_use", ctypes.c_int64)]
+
+
 class pi_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
@@ -79,6 +108,22 @@ _SIGS = [
     ("pi_cells_get_view", ctypes.c_int32, [_P, ctypes.POINTER(pi_cells_view)]),
     ("pi_interact", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_interact_opts), _P, _P, _P, _P, _P, _P, _P]),
     ("pi_sync", ctypes.c_int32, [_P, _P, _P]),
+    ("pi_batch_create", ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
+    ("pi_batch_destroy", ctypes.c_int32, [_P]),
+    ("pi_batch_run", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(pi_system_desc), _P, _P, _P, _P,
+                                      ctypes.POINTER(pi_interact_opts), _P, _P, _P, _P, _P, _P, _P]),
+    ("pi_batch_get_view", ctypes.c_int32, [_P, ctypes.POINTER(pi_cells_view), ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.c_int32]),
+    ("pi_batch_sync", ctypes.c_int32, [_P, _P, _P]),
+    ("pi_server_create", ctypes.c_int32, [_P, ctypes.POINTER(pi_server_opts), ctypes.POINTER(_P)]),
+    ("pi_server_destroy", ctypes.c_int32, [_P]),
+    ("pi_submit", ctypes.c_int32, [_P, ctypes.POINTER(pi_request), ctypes.POINTER(ctypes.c_uint64)]),
+    ("pi_poll", ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.POINTER(pi_result)]),
+    ("pi_wait", ctypes.c_int32, [_P, ctypes.c_uint64, ctypes.POINTER(pi_result)]),
+    ("pi_release", ctypes.c_int32, [_P, ctypes.c_uint64]),
+    ("pi_server_stats", ctypes.c_int32, [_P, ctypes.POINTER(pi_server_stats_t)]),
+    ("pi_tuner_mode", ctypes.c_int32, [_P, ctypes.c_int32]),
+    ("pi_tuner_choice", ctypes.c_int32, [_P, _P, ctypes.c_int32, ctypes.POINTER(pi_interact_opts), _P]),
     ("pi_timing_enable", ctypes.c_int32, [_P, ctypes.c_int32]),
     ("pi_timing_read", ctypes.c_int32, [_P, ctypes.POINTER(pi_kernel_time), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32)]),
@@ -200,6 +245,146 @@ def pi_interact(ctx, cells, opts, rho, gx, gy, gz, count, inv=None, stream=None)
 
 def pi_sync(ctx, cells=None, stream=None):
     _check(_lib().pi_sync(ctx, cells, _stream(stream)), "pi_sync")
+
+
+def pi_batch_create(ctx):
+    h = _P()
+    _check(_lib().pi_batch_create(ctx, ctypes.byref(h)), "pi_batch_create")
+    return h
+
+
+def pi_batch_destroy(batch):
+    _check(_lib().pi_batch_destroy(batch), "pi_batch_destroy")
+
+
+def make_system_descs(systems):
+    """pi_system_desc array for systems concatenated in order."""
+    arr = (pi_system_desc * len(systems))()
+    off = 0
+    for i, s in enumerate(systems):
+        arr[i].offset = off
+        arr[i].n = s.n
+        arr[i].grid = make_grid(s.origin, s.dims, s.cell_w, s.rc)
+        off += s.n
+    return arr
+
+
+def pi_batch_run(ctx, batch, descs, x, y, z, w, opts, rho, gx, gy, gz, count, inv=None, stream=None):
+    _check(_lib().pi_batch_run(ctx, batch, len(descs), descs, _ptr(x), _ptr(y), _ptr(z), _ptr(w),
+                               ctypes.byref(opts) if opts is not None else None, _ptr(rho), _ptr(gx),
+                               _ptr(gy), _ptr(gz), _ptr(count), _ptr(inv), _stream(stream)), "pi_batch_run")
+
+
+def pi_batch_get_view(batch, nsys):
+    v = pi_cells_view()
+    cb = (ctypes.c_int64 * nsys)()
+    _check(_lib().pi_batch_get_view(batch, ctypes.byref(v), cb, nsys), "pi_batch_get_view")
+    return v, [cb[i] for i in range(nsys)]
+
+
+def pi_batch_sync(ctx, batch, stream=None):
+    _check(_lib().pi_batch_sync(ctx, batch, _stream(stream)), "pi_batch_sync")
+
+
+PI_TUNE_STATIC, PI_TUNE_TIMED = 0, 1
+
+
+def pi_tuner_mode(ctx, mode):
+    _check(_lib().pi_tuner_mode(ctx, int(mode)), "pi_tuner_mode")
+
+
+def pi_tuner_choice(ctx, cells, precision="compensated", stream=None) -> pi_interact_opts:
+    o = pi_interact_opts()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(_lib().pi_tuner_choice(ctx, cells, prec, ctypes.byref(o), _stream(stream)), "pi_tuner_choice")
+    return o
+
+
+def pi_server_create(ctx, hbm_budget=64 << 30, max_slots=8, n_streams=4, queue_capacity=1024):
+    o = pi_server_opts(hbm_budget, max_slots, n_streams, queue_capacity, 0)
+    h = _P()
+    _check(_lib().pi_server_create(ctx, ctypes.byref(o), ctypes.byref(h)), "pi_server_create")
+    return h
+
+
+def pi_server_destroy(server):
+    _check(_lib().pi_server_destroy(server), "pi_server_destroy")
+
+
+def make_request(system, n_sweeps=1, precision="compensated", sweep="auto", jitter_sigma=0.0, lattice=0.0,
+                 seed=0):
+    """pi_request for a synth.System (the numpy arrays must stay alive until
+    pi_submit returns; they are copied there)."""
+    import numpy as np
+    arrs = [np.ascontiguousarray(getattr(system, k), dtype=np.float32) for k in ("x", "y", "z", "w")]
+    r = pi_request()
+    r.x, r.y, r.z, r.w = (a.ctypes.data for a in arrs)
+    r.n = system.n
+    r.grid = make_grid(system.origin, system.dims, system.cell_w, system.rc)
+    r.n_sweeps = int(n_sweeps)
+    r.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    r.sweep = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
+    r.jitter_sigma = float(jitter_sigma)
+    r.lattice = float(lattice)
+    r.seed = int(seed)
+    r._keep = arrs
+    return r
+
+
+def pi_submit(server, req) -> int:
+    t = ctypes.c_uint64(0)
+    _check(_lib().pi_submit(server, ctypes.byref(req), ctypes.byref(t)), "pi_submit")
+    return int(t.value)
+
+
+def pi_submit_status(server, req):
+    """(status, ticket) without raising (for PI_EAGAIN / PI_ENOMEM handling)."""
+    t = ctypes.c_uint64(0)
+    st = _lib().pi_submit(server, ctypes.byref(req), ctypes.byref(t))
+    return int(st), int(t.value)
+
+
+def _result_dict(r: pi_result, copy=True):
+    import numpy as np
+    out = {"done": bool(r.done), "status": int(r.status), "n": int(r.n), "sweeps": int(r.sweeps),
+           "pairs_total": int(r.pairs_total), "t_submit": r.t_submit, "t_start": r.t_start,
+           "t_done": r.t_done}
+    if r.done and r.status == PI_OK:
+        n = int(r.n)
+
+        def arr(ptr, ct, dt):
+            if n == 0 or not ptr:
+                return np.zeros(0, dt)
+            a = np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ct)), shape=(n,))
+            return a.copy() if copy else a
+        for k in ("rho", "gx", "gy", "gz", "x", "y", "z"):
+            out[k] = arr(getattr(r, k), ctypes.c_float, np.float32)
+        out["count"] = arr(r.count, ctypes.c_int32, np.int32)
+        inv = ctypes.cast(r.invariants, ctypes.POINTER(pi_invariants))
+        out["pairs_per_sweep"] = [int(inv[i].pairs) for i in range(int(r.sweeps))]
+    return out
+
+
+def pi_poll(server, ticket, copy=True) -> dict:
+    r = pi_result()
+    _check(_lib().pi_poll(server, ctypes.c_uint64(ticket), ctypes.byref(r)), "pi_poll")
+    return _result_dict(r, copy)
+
+
+def pi_wait(server, ticket, copy=True) -> dict:
+    r = pi_result()
+    _check(_lib().pi_wait(server, ctypes.c_uint64(ticket), ctypes.byref(r)), "pi_wait")
+    return _result_dict(r, copy)
+
+
+def pi_release(server, ticket):
+    _check(_lib().pi_release(server, ctypes.c_uint64(ticket)), "pi_release")
+
+
+def pi_server_stats(server) -> dict:
+    st = pi_server_stats_t()
+    _check(_lib().pi_server_stats(server, ctypes.byref(st)), "pi_server_stats")
+    return {"queued": st.queued, "running": st.running, "hbm_in_use": st.hbm_in_use}
 
 
 def pi_timing_enable(ctx, on=True):

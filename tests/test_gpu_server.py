@@ -1,0 +1,157 @@
+"""The request server (pi_server_*): results against the FP64 oracle on the
+final positions, the same result alone and in a concurrent mix, admission by
+memory budget, queue-full and unknown-ticket errors.  Also the tuner: AUTO
+runs the organisation the tuner reports, with the same outputs."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_16091_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_16091_amd import device, pi
+    pi.load()
+    return pi, device
+
+
+def _requests(count=6, seed=91):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        g = int(rng.integers(8, 24))
+        ppc = [1, 2, 4, 8][k % 4]
+        n = ppc * g ** 3
+        out.append(synth.box_system(n, g, seed=seed * 100 + k, lattice_log2=16, clustered_blobs=8 if k % 2 else 0))
+    return out
+
+
+def _check_final(res, s):
+    """Oracle on the positions the request ended with."""
+    fs = synth.System("final", res["x"], res["y"], res["z"], s.w, s.origin, s.dims, s.cell_w, s.rc)
+    b = oracle.bin_particles(fs.x, fs.y, fs.z, fs.w, fs.origin, fs.dims, fs.cell_w, fs.rc)
+    ref = oracle.sweep(fs.x, fs.y, fs.z, fs.w, fs.dims, fs.rc, b)
+    assert (res["count"].astype(np.int64) == ref.count).all()
+    assert np.all(np.abs(res["rho"].astype(np.float64) - ref.rho) <= TOL * ref.rho)
+    for k in ("gx", "gy", "gz"):
+        assert np.all(np.abs(res[k].astype(np.float64) - getattr(ref, k)) <= TOL * ref.ascale)
+    assert res["pairs_per_sweep"][-1] == int(ref.count.sum())
+    # jittered positions stay on the 2^-16 lattice inside the box
+    for v, d in ((fs.x, s.dims[0]), (fs.y, s.dims[1]), (fs.z, s.dims[2])):
+        assert np.all(v >= 0) and np.all(v < d)
+        assert np.all(np.float64(v) * 2 ** 16 == np.floor(np.float64(v) * 2 ** 16))
+
+
+def _submit_all(pi, server, systems, sweeps=3):
+    tickets = []
+    for k, s in enumerate(systems):
+        req = pi.make_request(s, n_sweeps=sweeps, jitter_sigma=0.1 * s.rc, lattice=2.0 ** -16, seed=1000 + k)
+        tickets.append(pi.pi_submit(server, req))
+    return tickets
+
+
+def test_server_results_match_oracle(lib):
+    pi, device = lib
+    ctx = device.Context.get(0).handle
+    server = pi.pi_server_create(ctx, max_slots=4, n_streams=4)
+    try:
+        systems = _requests()
+        tickets = _submit_all(pi, server, systems)
+        for t, s in zip(tickets, systems):
+            res = pi.pi_wait(server, t)
+            assert res["done"] and res["status"] == pi.PI_OK
+            assert res["t_submit"] <= res["t_start"] <= res["t_done"]
+            assert len(res["pairs_per_sweep"]) == 3 and res["pairs_total"] == sum(res["pairs_per_sweep"])
+            _check_final(res, s)
+            pi.pi_release(server, t)
+    finally:
+        pi.pi_server_destroy(server)
+
+
+def test_alone_and_in_the_mix_are_identical(lib):
+    pi, device = lib
+    ctx = device.Context.get(0).handle
+    systems = _requests(seed=92)
+    alone = []
+    server = pi.pi_server_create(ctx, max_slots=1, n_streams=1)
+    try:
+        for k, s in enumerate(systems):
+            req = pi.make_request(s, n_sweeps=3, jitter_sigma=0.1 * s.rc, lattice=2.0 ** -16, seed=1000 + k)
+            t = pi.pi_submit(server, req)
+            alone.append(pi.pi_wait(server, t))
+            pi.pi_release(server, t)
+    finally:
+        pi.pi_server_destroy(server)
+    server = pi.pi_server_create(ctx, max_slots=8, n_streams=4)
+    try:
+        tickets = _submit_all(pi, server, systems)
+        for t, a in zip(tickets, alone):
+            m = pi.pi_wait(server, t)
+            for k in ("rho", "gx", "gy", "gz", "count", "x", "y", "z"):
+                assert (m[k].view(np.uint32) == a[k].view(np.uint32)).all(), k
+            assert m["pairs_per_sweep"] == a["pairs_per_sweep"]
+            pi.pi_release(server, t)
+    finally:
+        pi.pi_server_destroy(server)
+
+
+def test_admission_and_errors(lib):
+    pi, device = lib
+    ctx = device.Context.get(0).handle
+    big = synth.box_system(1 << 21, 128, seed=93, lattice_log2=16)
+    small = synth.box_system(5000, 10, seed=94, lattice_log2=16)
+    # a request larger than the whole budget is refused at once
+    server = pi.pi_server_create(ctx, hbm_budget=50 << 20, max_slots=2, n_streams=1, queue_capacity=1)
+    try:
+        st, _ = pi.pi_submit_status(server, pi.make_request(big, n_sweeps=1))
+        assert st == pi.PI_ENOMEM
+        with pytest.raises(pi.PiError) as e:
+            pi.pi_poll(server, 987654321)
+        assert e.value.status == pi.PI_ENOTFOUND
+    finally:
+        pi.pi_server_destroy(server)
+    # one slot: a long request runs, the next waits in the queue, the third
+    # finds the queue full
+    server = pi.pi_server_create(ctx, hbm_budget=8 << 30, max_slots=1, n_streams=1, queue_capacity=1)
+    try:
+        t1 = pi.pi_submit(server, pi.make_request(big, n_sweeps=12, jitter_sigma=0.1, lattice=2.0 ** -16))
+        for _ in range(200):   # wait until the worker has admitted it
+            if pi.pi_server_stats(server)["running"] == 1:
+                break
+            time.sleep(0.001)
+        t2 = pi.pi_submit(server, pi.make_request(small, n_sweeps=1))
+        st, _ = pi.pi_submit_status(server, pi.make_request(small, n_sweeps=1))
+        r1 = pi.pi_poll(server, t1)
+        if not r1["done"]:
+            assert st == pi.PI_EAGAIN
+        assert pi.pi_wait(server, t1)["status"] == pi.PI_OK
+        assert pi.pi_wait(server, t2)["status"] == pi.PI_OK
+    finally:
+        pi.pi_server_destroy(server)
+
+
+def test_tuner_choice_is_what_auto_runs(lib):
+    pi, device = lib
+    s = synth.uniform_unit_cube(1 << 17, -5, seed=95)   # 4 per cell
+    ds = device.DeviceSystem(s)
+    ds.bin()
+    pi.pi_tuner_mode(ds.ctx.handle, pi.PI_TUNE_TIMED)
+    choice = pi.pi_tuner_choice(ds.ctx.handle, ds.cells)
+    assert choice.sweep in (pi.PI_SWEEP_NOLDS, pi.PI_SWEEP_PENCIL, pi.PI_SWEEP_SUBBOX)
+    ds.interact(sweep="auto", order="original")
+    auto = ds.results()
+    ds.interact(sweep=int(choice.sweep), tile=tuple(choice.tile), order="original")
+    chosen = ds.results()
+    for k in ("rho", "gx", "gy", "gz", "count"):
+        assert (auto[k].view(np.uint32) == chosen[k].view(np.uint32)).all()
+    print(f"[tuner] 4 ppc, 2^17 particles -> sweep {choice.sweep} tile {tuple(choice.tile)}", flush=True)
