@@ -20,9 +20,9 @@
 //                    written out in runs (key, index, x, y, z, w)
 // The first pass computes the cell id from the position (float32 decision,
 // see axis_index); the last pass writes the final arrays perm, cell and the
-// cell-relative coordinates.  Counts then come from atomics on the sorted
-// cell ids (consecutive threads hit consecutive counters) and the offsets
-// and M_C from the same DPP scan.
+// cell-relative coordinates.  Counts then come from the runs of equal ids in
+// the sorted cell ids (wave ballots, one store per cell), and the offsets and
+// M_C from the same DPP scan.
 #include <string.h>
 
 #include "pi_internal.h"
@@ -36,6 +36,8 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kBlock * kSortItems; // 4096 keys per sort tile
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSBlock = 512;                  // scatter: 8 wavefronts,
+constexpr int kSItems = kSortTile / kSBlock;  // 8 keys per thread
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
@@ -234,6 +236,7 @@ struct SortArgs {
     const float *x_in, *y_in, *z_in, *w_in;
     // outputs (ping-pong buffer, or the final arrays on the last pass)
     uint32_t *key_out;
+    uint32_t *gkey_out; // batch mode, last pass: global cell ids (for counting)
     int32_t *idx_out;
     float *x_out, *y_out, *z_out, *w_out;
     const int32_t *gbase; // scanned histogram, digit-major
@@ -281,34 +284,70 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid)
     return m;
 }
 
-template <bool FIRST, bool LAST, bool BATCH>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(SortArgs a)
+// Global cell key of caller particle e at position (x, y, z).
+template <bool BATCH>
+__device__ __forceinline__ uint32_t key_at(const SortArgs &a, int64_t e, float x, float y, float z)
 {
-    __shared__ int32_t wcnt[4][kRadix];  // per-wave digit counters, then wave bases
+    if (!BATCH) return cell_key(x, y, z, a.g, a.err);
+    const SysDev &s = a.sys[sys_of_particle(a.sys, a.nsys, e)];
+    return (uint32_t)s.cell_base + cell_key(x, y, z, s.g, a.err);
+}
+
+template <bool FIRST, bool LAST, bool BATCH>
+__global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
+{
+    constexpr int W = kSBlock / 64;      // wavefronts per block
+    __shared__ int32_t wcnt[W][kRadix];  // per-wave digit counters, then wave bases
     __shared__ int32_t lstart[kRadix];   // tile-local start of each digit
     __shared__ int32_t gdst[kRadix];     // global start of each digit's run
-    __shared__ int32_t scan_tmp[8];
-    __shared__ int32_t lds_dst[kSortTile];
-    __shared__ uint32_t lds_buf[kSortTile];
+    __shared__ int32_t scan_tmp[4];
+    __shared__ uint32_t lds_buf[2][kSortTile + 1]; // [1] first holds the destinations
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile_base = (int64_t)blockIdx.x * kSortTile;
-    for (int i = tid; i < 4 * kRadix; i += kBlock) (&wcnt[0][0])[i] = 0;
+    for (int i = tid; i < W * kRadix; i += kSBlock) (&wcnt[0][0])[i] = 0;
+
+    // 0. the whole tile's keys and payload (index, x, y, z, w) in registers:
+    //    every global load of the tile is issued before the first barrier
+    auto elem = [&](int r) { return tile_base + wid * (kSItems * 64) + r * 64 + lane; };
+    // (indices past the end are clamped, so the loads need no branches; the
+    // clamped copies are never ranked or written)
+    const int64_t last_e = (int64_t)a.n - 1;
+    uint32_t key[kSItems];
+    int32_t pidx[kSItems];
+    float px[kSItems], py[kSItems], pz[kSItems], pw[kSItems];
+#pragma unroll
+    for (int r = 0; r < kSItems; ++r) {
+        const int64_t e = min(elem(r), last_e);
+        if (FIRST) {
+            px[r] = a.x[e];
+            py[r] = a.y[e];
+            pz[r] = a.z[e];
+            pw[r] = a.w[e];
+            pidx[r] = (int32_t)e;
+        } else {
+            key[r] = a.key_in[e];
+            pidx[r] = a.idx_in[e];
+            px[r] = a.x_in[e];
+            py[r] = a.y_in[e];
+            pz[r] = a.z_in[e];
+            pw[r] = a.w_in[e];
+        }
+    }
+    if (FIRST) {
+#pragma unroll
+        for (int r = 0; r < kSItems; ++r) key[r] = key_at<BATCH>(a, min(elem(r), last_e), px[r], py[r], pz[r]);
+    }
     __syncthreads();
 
-    // 1. stable rank of each key among the keys of its wavefront's 1024-key
-    //    chunk with the same digit (rounds in key order, lanes in key order)
+    // 1. stable rank of each key among the keys of its wavefront's chunk with
+    //    the same digit (rounds in key order, lanes in key order)
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t key[kSortItems];
-    int32_t rank[kSortItems];
+    int32_t pos[kSItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const int64_t e = tile_base + wid * (kSortItems * 64) + r * 64 + lane;
-        const bool valid = e < a.n;
-        uint32_t k = 0;
-        if (valid) k = FIRST ? first_key<BATCH>(a, e) : a.key_in[e];
-        key[r] = k;
-        const uint32_t d = (k >> a.shift) & (kRadix - 1);
+    for (int r = 0; r < kSItems; ++r) {
+        const bool valid = elem(r) < a.n;
+        const uint32_t d = (key[r] >> a.shift) & (kRadix - 1);
         const uint64_t vmask = __ballot(valid);
         const uint64_t peers = match_digit(d, vmask);
         int32_t rk = -1;
@@ -318,126 +357,157 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(SortArgs a)
             rk = base + before;
             if (before == 0) wcnt[wid][d] = base + __popcll(peers);
         }
-        rank[r] = rk;
+        pos[r] = rk; // rank within the wave for now, -1 past the end
     }
     __syncthreads();
 
-    // 2. per digit: bases of the waves, tile total, tile-local start (scan)
-    {
-        const int d = tid;
-        const int32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
-        const int32_t tot = c0 + c1 + c2 + c3;
-        const int32_t inc = wave_incl_scan(tot);
-        if (lane == 63) scan_tmp[wid] = inc;
-        __syncthreads();
+    // 2. per digit (threads 0..255): bases of the waves, tile total,
+    //    tile-local start (scan over the first four wavefronts)
+    const int d = tid & (kRadix - 1);
+    int32_t tot = 0;
+    if (tid < kRadix) {
+        int32_t run = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const int32_t c = wcnt[k][d];
+            wcnt[k][d] = run;
+            run += c;
+        }
+        tot = run;
+    }
+    const int32_t inc = wave_incl_scan(tot);
+    if (tid < kRadix && lane == 63) scan_tmp[wid] = inc;
+    __syncthreads();
+    if (tid < kRadix) {
         int32_t wofs = 0;
         for (int k = 0; k < wid; ++k) wofs += scan_tmp[k];
         lstart[d] = wofs + inc - tot;
         gdst[d] = a.gbase[(int64_t)d * a.ntiles + blockIdx.x];
-        wcnt[0][d] = 0;
-        wcnt[1][d] = c0;
-        wcnt[2][d] = c0 + c1;
-        wcnt[3][d] = c0 + c1 + c2;
     }
     __syncthreads();
 
     // 3. tile-local position of every key and the global destination of that
     //    position (consecutive positions of one digit go to consecutive
     //    addresses, so the copies below are coalesced runs)
-    int32_t pos[kSortItems];
+    // (keys past the end get the spare slot kSortTile, written but never read)
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        pos[r] = -1;
-        if (rank[r] >= 0) {
-            const uint32_t d = (key[r] >> a.shift) & (kRadix - 1);
-            const int32_t within = wcnt[wid][d] + rank[r];
-            pos[r] = lstart[d] + within;
-            lds_dst[pos[r]] = gdst[d] + within;
-        }
+    for (int r = 0; r < kSItems; ++r) {
+        const uint32_t dg = (key[r] >> a.shift) & (kRadix - 1);
+        const int32_t within = wcnt[wid][dg] + pos[r];
+        const bool valid = pos[r] >= 0;
+        pos[r] = valid ? lstart[dg] + within : kSortTile;
+        lds_buf[1][pos[r]] = (uint32_t)(gdst[dg] + within);
     }
     const int32_t nvalid = (int32_t)min((int64_t)kSortTile, (int64_t)a.n - tile_base);
+    __syncthreads();
+    int32_t dst[kSItems];
+#pragma unroll
+    for (int k = 0; k < kSItems; ++k) {
+        const int p = tid + k * kSBlock;
+        dst[k] = p < nvalid ? (int32_t)lds_buf[1][p] : 0;
+    }
 
-    // 4. reorder each array through LDS and write it out
+    // 4. each array reordered through LDS (two buffers, one barrier per
+    //    array) and written out in runs
+    int buf = 0;
     auto pass_array = [&](auto value_of, auto store) {
+#pragma unroll
+        for (int r = 0; r < kSItems; ++r) lds_buf[buf][pos[r]] = value_of(r);
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kSortItems; ++r)
-            if (pos[r] >= 0) lds_buf[pos[r]] = value_of(r);
-        __syncthreads();
-        for (int p = tid; p < nvalid; p += kBlock) store(lds_dst[p], lds_buf[p]);
+        for (int k = 0; k < kSItems; ++k) {
+            const int p = tid + k * kSBlock;
+            if (p < nvalid) store(dst[k], lds_buf[buf][p]);
+        }
+        buf ^= 1;
     };
-    auto elem = [&](int r) { return tile_base + wid * (kSortItems * 64) + r * 64 + lane; };
 
     if (LAST) {
         // final arrays: local cell ids, and the cell-relative coordinates
         // fma(-i, w, x - o) of the original coordinate carried along
-        int32_t lcell[kSortItems];
-        const GridDev *gr[kSortItems];
+        int32_t lcell[kSItems];
+        const GridDev *gr[kSItems];
 #pragma unroll
-        for (int r = 0; r < kSortItems; ++r) {
-            lcell[r] = 0;
+        for (int r = 0; r < kSItems; ++r) {
+            lcell[r] = (int32_t)key[r];
             gr[r] = &a.g;
-            if (pos[r] >= 0 && BATCH) {
+            if (BATCH) {
                 const SysDev &sd = a.sys[sys_of_cell(a.sys, a.nsys, key[r])];
                 lcell[r] = (int32_t)(key[r] - (uint32_t)sd.cell_base);
                 gr[r] = &sd.g;
-            } else {
-                lcell[r] = (int32_t)key[r];
             }
         }
         pass_array([&](int r) { return (uint32_t)lcell[r]; }, [&](int32_t o, uint32_t v) { a.key_out[o] = v; });
-        pass_array([&](int r) { return FIRST ? (uint32_t)elem(r) : (uint32_t)a.idx_in[elem(r)]; },
-                   [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
+        if (BATCH)
+            pass_array([&](int r) { return key[r]; }, [&](int32_t o, uint32_t v) { a.gkey_out[o] = v; });
+        pass_array([&](int r) { return (uint32_t)pidx[r]; }, [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
         pass_array(
             [&](int r) {
                 const GridDev &g = *gr[r];
-                const float x = FIRST ? a.x[elem(r)] : a.x_in[elem(r)];
                 const int32_t ix = lcell[r] % g.nx;
-                return __float_as_uint(__builtin_fmaf(-(float)ix, g.w, x - g.ox));
+                return __float_as_uint(__builtin_fmaf(-(float)ix, g.w, px[r] - g.ox));
             },
             [&](int32_t o, uint32_t v) { a.x_out[o] = __uint_as_float(v); });
         pass_array(
             [&](int r) {
                 const GridDev &g = *gr[r];
-                const float y = FIRST ? a.y[elem(r)] : a.y_in[elem(r)];
                 const int32_t iy = (lcell[r] / g.nx) % g.ny;
-                return __float_as_uint(__builtin_fmaf(-(float)iy, g.w, y - g.oy));
+                return __float_as_uint(__builtin_fmaf(-(float)iy, g.w, py[r] - g.oy));
             },
             [&](int32_t o, uint32_t v) { a.y_out[o] = __uint_as_float(v); });
         pass_array(
             [&](int r) {
                 const GridDev &g = *gr[r];
-                const float z = FIRST ? a.z[elem(r)] : a.z_in[elem(r)];
                 const int32_t iz = lcell[r] / (g.nx * g.ny);
-                return __float_as_uint(__builtin_fmaf(-(float)iz, g.w, z - g.oz));
+                return __float_as_uint(__builtin_fmaf(-(float)iz, g.w, pz[r] - g.oz));
             },
             [&](int32_t o, uint32_t v) { a.z_out[o] = __uint_as_float(v); });
     } else {
         pass_array([&](int r) { return key[r]; }, [&](int32_t o, uint32_t v) { a.key_out[o] = v; });
-        pass_array([&](int r) { return FIRST ? (uint32_t)elem(r) : (uint32_t)a.idx_in[elem(r)]; },
-                   [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
-        pass_array([&](int r) { return __float_as_uint(FIRST ? a.x[elem(r)] : a.x_in[elem(r)]); },
+        pass_array([&](int r) { return (uint32_t)pidx[r]; }, [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
+        pass_array([&](int r) { return __float_as_uint(px[r]); },
                    [&](int32_t o, uint32_t v) { a.x_out[o] = __uint_as_float(v); });
-        pass_array([&](int r) { return __float_as_uint(FIRST ? a.y[elem(r)] : a.y_in[elem(r)]); },
+        pass_array([&](int r) { return __float_as_uint(py[r]); },
                    [&](int32_t o, uint32_t v) { a.y_out[o] = __uint_as_float(v); });
-        pass_array([&](int r) { return __float_as_uint(FIRST ? a.z[elem(r)] : a.z_in[elem(r)]); },
+        pass_array([&](int r) { return __float_as_uint(pz[r]); },
                    [&](int32_t o, uint32_t v) { a.z_out[o] = __uint_as_float(v); });
     }
-    pass_array([&](int r) { return __float_as_uint(FIRST ? a.w[elem(r)] : a.w_in[elem(r)]); },
+    pass_array([&](int r) { return __float_as_uint(pw[r]); },
                [&](int32_t o, uint32_t v) { a.w_out[o] = __uint_as_float(v); });
 }
 
-// counts[c] += 1 for every sorted cell id: consecutive threads touch
-// consecutive counters, so the atomics are coalesced.
-template <bool BATCH>
-__global__ __launch_bounds__(kBlock) void k_count_sorted(int32_t n, const int32_t *__restrict__ cell,
-                                                         int32_t *__restrict__ counts, const SysDev *sys,
-                                                         int32_t nsys)
+// Per-cell counts from the sorted global cell ids, one wavefront per 64
+// consecutive ids and no loop: a lane that starts a run of equal ids, or lane
+// 0 (which may continue a run from the chunk before), owns the piece of the
+// run up to the next such lane or the chunk's end.  A piece that is a whole
+// run is stored; pieces of runs that cross chunks are added atomically
+// (counts start at zero).
+__global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t *__restrict__ key,
+                                                       int32_t *__restrict__ counts)
 {
-    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (k >= n) return;
-    const int32_t base = BATCH ? sys[sys_of_particle(sys, nsys, k)].cell_base : 0;
-    atomicAdd(&counts[base + cell[k]], 1);
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool valid = k < n;
+    const int64_t kc = valid ? k : (int64_t)n - 1;
+    const uint32_t c = key[kc];
+    const bool start = valid && (kc == 0 || key[kc - 1] != c);
+    const bool head = valid && (start || lane == 0);
+    const uint64_t heads = __ballot(head);
+    if (!head) return;
+    const uint64_t above = heads & ~((2ull << lane) - 1ull); // heads after this lane
+    int32_t end_lane;                                        // exclusive
+    bool run_ends;
+    if (above) {
+        end_lane = __ffsll((unsigned long long)above) - 1;
+        run_ends = true; // every head after lane 0 starts a run
+    } else {
+        const int64_t chunk_end = k - lane + 64;
+        end_lane = (int32_t)(min(chunk_end, (int64_t)n) - (k - lane));
+        run_ends = chunk_end >= n || key[chunk_end] != c;
+    }
+    const int32_t len = end_lane - lane;
+    if (start && run_ends) counts[c] = len;
+    else atomicAdd(&counts[c], len);
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -510,6 +580,7 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
             a.y_in = cells->sy[src];
             a.z_in = cells->sz[src];
             a.w_in = cells->sw[src];
+            a.gkey_out = cells->skey[dst];
             if (last) {
                 a.key_out = (uint32_t *)cells->cell;
                 a.idx_out = cells->perm;
@@ -531,7 +602,7 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
             else PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<false, false>), grid, block, 0, stream, a);
             launch_scan(ctx, cells->hist, hlen, cells->hist, cells->hist_total, nullptr, cells->hist_tsum,
                         cells->hist_tmax, stream);
-#define PI_SCATTER(F, L, B) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<F, L, B>), grid, block, 0, stream, a)
+#define PI_SCATTER(F, L, B) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<F, L, B>), grid, dim3(kSBlock), 0, stream, a)
             if (batch) {
                 if (first && last) PI_SCATTER(true, true, true);
                 else if (first) PI_SCATTER(true, false, true);
@@ -549,12 +620,14 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
     PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks(nc, kBlock)), dim3(kBlock), 0, stream, cells->counts, nc,
               0);
     if (n > 0) {
-        if (batch)
-            PI_LAUNCH(ctx, "k_count_sorted", (k_count_sorted<true>), dim3(nblocks(n, kBlock)), dim3(kBlock), 0,
-                      stream, (int32_t)n, (const int32_t *)cells->cell, cells->counts, d_sys, nsys);
-        else
-            PI_LAUNCH(ctx, "k_count_sorted", (k_count_sorted<false>), dim3(nblocks(n, kBlock)), dim3(kBlock), 0,
-                      stream, (int32_t)n, (const int32_t *)cells->cell, cells->counts, d_sys, nsys);
+        // global ids of the sorted particles: the cell array itself for one
+        // system, the extra key copy of the last pass for a batch
+        int bits = 1;
+        while (bits < 31 && ((int64_t)1 << bits) < nc) ++bits;
+        const int passes = (bits + kRadixBits - 1) / kRadixBits;
+        const uint32_t *gkey = batch ? cells->skey[(passes - 1) & 1] : (const uint32_t *)cells->cell;
+        PI_LAUNCH(ctx, "k_count_runs", k_count_runs, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, stream, (int32_t)n,
+                  gkey, cells->counts);
     }
     launch_scan(ctx, cells->counts, nc, cells->offsets, cells->offsets + nc, cells->max_per_cell, cells->tile_sum,
                 cells->tile_max, stream);

@@ -258,6 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     __shared__ float4 sp[CAP];
     __shared__ int32_t fifo[kBlock / 64][Q][64]; // accepted source: LDS index | (dy,dz) code << 12
     __shared__ int32_t segtab[9][kBlock]; // start | len << 12 | (dy,dz) code << 25
+    // (dy, dz) code: (dy + 1) << 2 | (dz + 1)
     __shared__ int32_t cs[R][HX + 1];
     __shared__ int32_t rstart[R + 1];
     __shared__ int32_t gstart[R];
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                     const int32_t s0 = cs[r][jc - (left ? 1 : 0)];
                     const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
                     if (s1 > s0) {
-                        segtab[nseg][tid] = s0 | ((s1 - s0) << 12) | (((dy + 1) * 3 + (dz + 1)) << 25);
+                        segtab[nseg][tid] = s0 | ((s1 - s0) << 12) | ((((dy + 1) << 2) | (dz + 1)) << 25);
                         ++nseg;
                     }
                 }
@@ -427,6 +428,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         int seg = 0, qh = 0, qc = 0, code = 0;
         int32_t j = 0, jend = 0;
         float tyy = 0.f, tzz = 0.f;
+        // target coordinate shifted into the frame of neighbour row dy (dz):
+        // y - dy W for dy = -1, 0, 1 (the same roundings as the subtraction)
+        const float ym = yt + W, yp = yt - W, zm = zt + W, zp = zt - W;
+        auto shift_y = [&](int c) { const int q = c >> 2; return q == 0 ? ym : (q == 1 ? yt : yp); };
+        auto shift_z = [&](int c) { const int q = c & 3; return q == 0 ? zm : (q == 1 ? zt : zp); };
         // Evaluate the oldest queued pair of this lane: the differences are
         // recomputed from the same operands, so they are bit-identical to the
         // ones the test used.
@@ -436,8 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             --qc;
             const float4 s = sp[e & 4095];
             const int c = e >> 12;
-            const float ey = yt - (float)(c / 3 - 1) * W, ez = zt - (float)(c % 3 - 1) * W;
-            const float ddx = xt - s.x, ddy = ey - s.y, ddz = ez - s.z;
+            const float ddx = xt - s.x, ddy = shift_y(c) - s.y, ddz = shift_z(c) - s.z;
             T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
         };
         while (true) {
@@ -447,9 +452,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                 j = sg & 4095;
                 jend = j + ((sg >> 12) & 8191);
                 code = sg >> 25;
-                const int dy = code / 3 - 1, dz = code % 3 - 1;
-                tyy = yt - (float)dy * W;
-                tzz = zt - (float)dz * W;
+                tyy = shift_y(code);
+                tzz = shift_z(code);
             }
             const bool have = j < jend;
             if (!__any(have)) break;
