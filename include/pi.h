@@ -141,6 +141,9 @@ pi_status pi_cells_get_view(const pi_cells *cells, pi_cells_view *out);
 #define PI_SWEEP_SUBBOX 3 /* a workgroup owns a 3-D sub-box of target cells;
                              the sub-box and its ghost shell are staged in LDS
                              (Sec. 5.1, All-in-SM, Algorithm 4) */
+#define PI_SWEEP_STREAM 4 /* as NOLDS (nothing staged), with accepted pairs
+                             queued per thread in LDS and evaluated by the
+                             whole wavefront at once (works at any occupancy) */
 
 /* Order of the per-particle outputs. */
 #define PI_ORDER_SORTED   0 /* output[k] belongs to sorted slot k */
@@ -206,7 +209,7 @@ pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream);
 pi_status pi_tuner_mode(pi_ctx *ctx, int32_t mode);
 /* The organisation AUTO uses for this binned system and precision (tuning
  * it now if the class is new and the mode is timed).  out->sweep is
- * PI_SWEEP_NOLDS, _PENCIL or _SUBBOX and out->tile its shape. */
+ * PI_SWEEP_NOLDS, _STREAM, _PENCIL or _SUBBOX and out->tile its shape. */
 pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t precision, pi_interact_opts *out,
                           pi_stream stream);
 

@@ -2,25 +2,40 @@
 // of Sec. 2 applied to a set of systems at once).  The systems' particles are
 // concatenated; one radix sort orders them by global cell id (system cell
 // base + local cell), which keeps every system's particles contiguous and in
-// system order, and one work-list sweep covers all systems' tiles.  The whole
-// sequence is captured once into a hipGraph per batch layout (systems,
-// pointers, options) and replayed afterwards with a single launch.
+// system order.  Each system gets its own sweep organisation (the tuner's
+// choice for its size and occupancy, or the caller's explicit one); systems
+// with the same organisation share one work-list launch, so a batch costs at
+// most one sweep launch per organisation.  The whole sequence is captured
+// once into a hipGraph per batch layout (systems, pointers, options) and
+// replayed afterwards with a single launch.
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "pair.h"
 
+// Systems sharing one sweep organisation: entries [first, first + count) of
+// the sweep table, their workgroups' partials from record part_base on.
+struct BatchGroup {
+    int tile;
+    int32_t first, count;
+    int64_t blocks, part_base;
+};
+
 struct pi_batch {
     pi_ctx *ctx;
     pi_cells *cells;            // concatenated binned system
-    SysDev *d_sys;
-    KernelConst *d_kcs;
+    SysDev *d_sys;              // binning table, caller's order
+    SysDev *d_sweep;            // sweep table, grouped by organisation
+    KernelConst *d_kcs;         // kernel constants, sweep-table order
     int32_t cap_sys;
     int32_t nsys;
     std::vector<SysDev> h_sys;
+    std::vector<SysDev> h_sweep;
     std::vector<int64_t> cell_base; // host copy, nsys entries
-    int tile;
+    std::vector<int> tile_of;       // organisation of each system (caller's order)
+    std::vector<BatchGroup> groups;
     int64_t total_blocks;
     // graph cache
     std::vector<unsigned char> sig;
@@ -60,6 +75,7 @@ extern "C" pi_status pi_batch_destroy(pi_batch *b)
     (void)hipSetDevice(b->ctx->device);
     drop_graph(b);
     if (b->d_sys) (void)hipFree(b->d_sys);
+    if (b->d_sweep) (void)hipFree(b->d_sweep);
     if (b->d_kcs) (void)hipFree(b->d_kcs);
     pi_cells_destroy(b->cells);
     delete b;
@@ -82,8 +98,12 @@ pi_status launch_all(pi_batch *b, const float *x, const float *y, const float *z
     memset(&g0, 0, sizeof(g0));
     pi_status st = pi_bin_systems(b->ctx, b->cells, x, y, z, w, n_total, cells_total, b->nsys, b->d_sys, g0, stream);
     if (st != PI_OK) return st;
-    return pi_sweep_batch(b->ctx, b->cells, b->nsys, b->d_sys, b->d_kcs, b->total_blocks, b->tile, o, rho, gx, gy,
-                          gz, count, inv, stream);
+    for (const BatchGroup &g : b->groups) {
+        st = pi_sweep_batch(b->ctx, b->cells, g.count, b->d_sweep + g.first, b->d_kcs + g.first, g.blocks,
+                            g.part_base, g.tile, o, rho, gx, gy, gz, count, inv, stream);
+        if (st != PI_OK) return st;
+    }
+    return PI_OK;
 }
 
 } // namespace
@@ -98,7 +118,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (o.precision < PI_PREC_COMPENSATED || o.precision > PI_PREC_FP64ACC) return PI_EINVAL;
-    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_SUBBOX) return PI_EINVAL;
+    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_STREAM) return PI_EINVAL;
     if (o.order != PI_ORDER_SORTED && o.order != PI_ORDER_ORIGINAL) return PI_EINVAL;
     const bool anyf = rho || gx || gy || gz;
     if (anyf && !(rho && gx && gy && gz)) return PI_EINVAL;
@@ -128,13 +148,10 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     }
     drop_graph(b);
 
-    // system table and kernel constants
-    const double ppc = cells_total > 0 ? (double)n_total / (double)cells_total : 0.0;
-    const int tile = pi_pick_tile(o, ppc);
-    if (tile < 0) return PI_EINVAL;
+    // binning table (caller's order)
     b->h_sys.assign((size_t)nsys, SysDev());
     b->cell_base.assign((size_t)nsys, 0);
-    std::vector<KernelConst> kcs((size_t)nsys);
+    b->tile_of.assign((size_t)nsys, 0);
     int64_t cb = 0;
     for (int32_t s = 0; s < nsys; ++s) {
         SysDev &d = b->h_sys[s];
@@ -143,6 +160,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         d.first = sys[s].offset;
         d.n = (int32_t)sys[s].n;
         d.cell_base = (int32_t)cb;
+        d.orig = s;
         b->cell_base[s] = cb;
         d.g.ox = g.origin[0];
         d.g.oy = g.origin[1];
@@ -151,20 +169,55 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         d.g.nx = g.dims[0];
         d.g.ny = g.dims[1];
         d.g.nz = g.dims[2];
-        cb += (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
-        kcs[s] = pi_make_kernel_const(g.rc, g.cell_w);
+        const int64_t nc = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
+        cb += nc;
+        // organisation of this system
+        const double ppc = (double)sys[s].n / (double)nc;
+        int t = pi_pick_tile(o, ppc);
+        if (t < 0) return PI_EINVAL;
+        if (o.sweep == PI_SWEEP_AUTO) t = pi_auto_tile(ctx, o.precision, sys[s].n, ppc);
+        b->tile_of[s] = t;
     }
-    b->tile = tile;
-    b->total_blocks = pi_batch_layout(tile, b->h_sys.data(), nsys);
+    // sweep table: systems grouped by organisation (caller's order within a
+    // group), one work-list layout per group
+    std::vector<int32_t> order((size_t)nsys);
+    for (int32_t s = 0; s < nsys; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t p, int32_t q) { return b->tile_of[p] < b->tile_of[q]; });
+    b->h_sweep.assign((size_t)nsys, SysDev());
+    std::vector<KernelConst> kcs((size_t)nsys);
+    b->groups.clear();
+    int64_t part_base = 0;
+    for (int32_t i = 0; i < nsys;) {
+        int32_t j = i;
+        while (j < nsys && b->tile_of[order[j]] == b->tile_of[order[i]]) {
+            b->h_sweep[j] = b->h_sys[order[j]];
+            kcs[j] = pi_make_kernel_const(sys[order[j]].grid.rc, sys[order[j]].grid.cell_w);
+            ++j;
+        }
+        BatchGroup g;
+        g.tile = b->tile_of[order[i]];
+        g.first = i;
+        g.count = j - i;
+        g.blocks = pi_batch_layout(g.tile, b->h_sweep.data() + i, g.count);
+        g.part_base = part_base;
+        part_base += g.blocks;
+        b->groups.push_back(g);
+        i = j;
+    }
+    b->total_blocks = part_base;
     b->nsys = nsys;
     if (nsys > b->cap_sys) {
         PI_CHECK_HIP(hipStreamSynchronize(stream));
         if (b->d_sys) (void)hipFree(b->d_sys);
+        if (b->d_sweep) (void)hipFree(b->d_sweep);
         if (b->d_kcs) (void)hipFree(b->d_kcs);
         b->d_sys = nullptr;
+        b->d_sweep = nullptr;
         b->d_kcs = nullptr;
         b->cap_sys = 0;
         if (hipMalloc((void **)&b->d_sys, sizeof(SysDev) * (size_t)nsys) != hipSuccess ||
+            hipMalloc((void **)&b->d_sweep, sizeof(SysDev) * (size_t)nsys) != hipSuccess ||
             hipMalloc((void **)&b->d_kcs, sizeof(KernelConst) * (size_t)nsys) != hipSuccess)
             return PI_ENOMEM;
         b->cap_sys = nsys;
@@ -187,6 +240,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     // layout; wait for them before overwriting it
     PI_CHECK_HIP(hipStreamSynchronize(stream));
     PI_CHECK_HIP(hipMemcpy(b->d_sys, b->h_sys.data(), sizeof(SysDev) * (size_t)nsys, hipMemcpyHostToDevice));
+    PI_CHECK_HIP(hipMemcpy(b->d_sweep, b->h_sweep.data(), sizeof(SysDev) * (size_t)nsys, hipMemcpyHostToDevice));
     PI_CHECK_HIP(hipMemcpy(b->d_kcs, kcs.data(), sizeof(KernelConst) * (size_t)nsys, hipMemcpyHostToDevice));
     c->n = n_total;
     c->n_cells = cells_total;

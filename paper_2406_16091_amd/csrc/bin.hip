@@ -36,8 +36,12 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kBlock * kSortItems; // 4096 keys per sort tile
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSBlock = 512;                  // scatter: 8 wavefronts,
-constexpr int kSItems = kSortTile / kSBlock;  // 8 keys per thread
+#ifndef PI_SCATTER_BLOCK
+#define PI_SCATTER_BLOCK 512
+#endif
+constexpr int kSBlock = PI_SCATTER_BLOCK;     // scatter threads per tile (256, 512 or 1024)
+constexpr int kSItems = kSortTile / kSBlock;  // keys per thread
+static_assert(kSBlock >= kRadix && kSBlock <= 1024 && kSortTile % kSBlock == 0, "scatter block size");
 
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
@@ -476,38 +480,56 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
                [&](int32_t o, uint32_t v) { a.w_out[o] = __uint_as_float(v); });
 }
 
-// Per-cell counts from the sorted global cell ids, one wavefront per 64
-// consecutive ids and no loop: a lane that starts a run of equal ids, or lane
-// 0 (which may continue a run from the chunk before), owns the piece of the
-// run up to the next such lane or the chunk's end.  A piece that is a whole
-// run is stored; pieces of runs that cross chunks are added atomically
-// (counts start at zero).
+// Per-cell counts from the sorted global cell ids, without a loop or an
+// atomic per particle.  A wavefront reads 8 consecutive chunks of 64 ids at
+// once (all loads in flight together); in each chunk, a lane that starts a
+// run of equal ids, or lane 0 (which may continue a run from the chunk
+// before), owns the piece of the run up to the next such lane or the chunk's
+// end.  A piece that is a whole run is stored; pieces of runs that cross
+// chunks are added atomically (counts start at zero).
+constexpr int kRunChunks = 8;
+
 __global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t *__restrict__ key,
                                                        int32_t *__restrict__ counts)
 {
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const bool valid = k < n;
-    const int64_t kc = valid ? k : (int64_t)n - 1;
-    const uint32_t c = key[kc];
-    const bool start = valid && (kc == 0 || key[kc - 1] != c);
-    const bool head = valid && (start || lane == 0);
-    const uint64_t heads = __ballot(head);
-    if (!head) return;
-    const uint64_t above = heads & ~((2ull << lane) - 1ull); // heads after this lane
-    int32_t end_lane;                                        // exclusive
-    bool run_ends;
-    if (above) {
-        end_lane = __ffsll((unsigned long long)above) - 1;
-        run_ends = true; // every head after lane 0 starts a run
-    } else {
-        const int64_t chunk_end = k - lane + 64;
-        end_lane = (int32_t)(min(chunk_end, (int64_t)n) - (k - lane));
-        run_ends = chunk_end >= n || key[chunk_end] != c;
+    const int64_t wbase = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * (64 * kRunChunks);
+    if (wbase >= n) return; // uniform over the wavefront
+    const int64_t last = (int64_t)n - 1;
+    uint32_t kv[kRunChunks];
+#pragma unroll
+    for (int r = 0; r < kRunChunks; ++r) kv[r] = key[min(wbase + r * 64 + lane, last)];
+    const uint32_t before = key[wbase > 0 ? wbase - 1 : 0];       // id before the range
+    const uint32_t after = key[min(wbase + 64 * kRunChunks, last)]; // id after it
+#pragma unroll
+    for (int r = 0; r < kRunChunks; ++r) {
+        const int64_t k = wbase + r * 64 + lane;
+        const bool valid = k < n;
+        const uint32_t c = kv[r];
+        const uint32_t up = __shfl_up(c, 1);
+        const uint32_t p63 = r > 0 ? __shfl(kv[r > 0 ? r - 1 : 0], 63) : before;
+        const uint32_t prev = lane == 0 ? p63 : up;
+        const uint32_t nxt = r + 1 < kRunChunks ? __shfl(kv[r + 1 < kRunChunks ? r + 1 : r], 0) : after;
+        const bool start = valid && (k == 0 || prev != c);
+        const bool head = valid && (start || lane == 0);
+        const uint64_t heads = __ballot(head);
+        if (head) {
+            const uint64_t above = heads & ~((2ull << lane) - 1ull); // heads after this lane
+            const int64_t chunk_end = wbase + (r + 1) * 64;
+            int32_t end_lane; // exclusive
+            bool run_ends;
+            if (above) {
+                end_lane = __ffsll((unsigned long long)above) - 1;
+                run_ends = true; // every head after lane 0 starts a run
+            } else {
+                end_lane = (int32_t)(min(chunk_end, (int64_t)n) - (chunk_end - 64));
+                run_ends = chunk_end >= n || nxt != c;
+            }
+            const int32_t len = end_lane - lane;
+            if (start && run_ends) counts[c] = len;
+            else atomicAdd(&counts[c], len);
+        }
     }
-    const int32_t len = end_lane - lane;
-    if (start && run_ends) counts[c] = len;
-    else atomicAdd(&counts[c], len);
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -626,8 +648,9 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
         while (bits < 31 && ((int64_t)1 << bits) < nc) ++bits;
         const int passes = (bits + kRadixBits - 1) / kRadixBits;
         const uint32_t *gkey = batch ? cells->skey[(passes - 1) & 1] : (const uint32_t *)cells->cell;
-        PI_LAUNCH(ctx, "k_count_runs", k_count_runs, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, stream, (int32_t)n,
-                  gkey, cells->counts);
+        const int64_t waves = (n + 64 * kRunChunks - 1) / (64 * kRunChunks);
+        PI_LAUNCH(ctx, "k_count_runs", k_count_runs, dim3(nblocks(waves * 64, kBlock)), dim3(kBlock), 0, stream,
+                  (int32_t)n, gkey, cells->counts);
     }
     launch_scan(ctx, cells->counts, nc, cells->offsets, cells->offsets + nc, cells->max_per_cell, cells->tile_sum,
                 cells->tile_max, stream);

@@ -162,7 +162,7 @@ struct SysDev {
     int32_t cell_base;
     int32_t block_base; // first workgroup of this system in a sweep launch
     int32_t ntx, nty;   // tiles per axis in that launch
-    int32_t pad;
+    int32_t orig;       // index of the system in the caller's list
     GridDev g;
 };
 
@@ -173,10 +173,11 @@ struct pi_interact_opts;
 KernelConst pi_make_kernel_const(float rc, float cell_w);
 bool pi_tile_shape(int tile_id, int *tx, int *ty, int *tz);
 int pi_pick_tile(const pi_interact_opts &o, double ppc);
+int pi_auto_tile(pi_ctx *ctx, int precision, int64_t n, double ppc);
 int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys);
 pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
-                         int64_t total_blocks, int tile_id, const pi_interact_opts &o, float *rho, float *gx,
-                         float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);
+                         int64_t total_blocks, int64_t part_base, int tile_id, const pi_interact_opts &o, float *rho,
+                         float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);
 
 // Host-side binning of a concatenated set of systems (bin.hip): one radix
 // sort over global cell ids; sorted arrays hold local cell ids.

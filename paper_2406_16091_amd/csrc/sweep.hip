@@ -183,6 +183,139 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
     }
 }
 
+// ------------------------------------------------------------------ stream
+// One thread per sorted target with sources read through the caches, as in
+// NOLDS, but with candidate testing decoupled from pair evaluation by the
+// per-lane LDS FIFO of the tiles (see below): the test of one candidate is
+// about ten instructions, the evaluation of an accepted pair about a
+// hundred, and at several particles per cell some lane of a wavefront
+// accepts on nearly every step.  Nothing is staged, so the organisation
+// works at any occupancy.  Each lane first writes its target's non-empty
+// row segments (neighbour rows in canonical (dz, dy) order, the reach test
+// of the tiles trimming the outer cells) into an LDS table as global index
+// ranges with their inner cell boundaries, from which the x shift of a
+// source follows.
+template <int Q, int PREC, bool INV, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
+{
+    static_assert((Q & (Q - 1)) == 0, "FIFO depth must be a power of two");
+    __shared__ int4 segtab[9][kBlock];             // [e0, e1) dx = -1, [e1, e2) dx = 0, [e2, e3) dx = +1
+    __shared__ uint8_t segcode[9][kBlock];         // row: (dy + 1) << 2 | (dz + 1)
+    __shared__ int32_t fifo[kBlock / 64][Q][64];   // accepted source: sorted index
+    __shared__ uint8_t fcode[kBlock / 64][Q][64];  // its shifts: (dx + 1) | row << 2
+
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    int32_t k, kend;
+    if (BATCH) {
+        const SysDev &sd = a.sys[enter_system(a, lb)];
+        k = (int32_t)sd.first + (int32_t)(lb - sd.block_base) * kBlock + (int32_t)threadIdx.x;
+        kend = (int32_t)sd.first + sd.n;
+    } else {
+        k = (int32_t)(lb * kBlock + threadIdx.x);
+        kend = min(a.off[a.nc], a.n);
+    }
+    const bool active = k < kend;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const float W = a.k.w;
+    const float reach2 = a.k.reach2;
+    float xi = 0.f, yi = 0.f, zi = 0.f, wi = 0.f;
+    int nseg = 0;
+    if (active) {
+        const int32_t c = a.cell[k];
+        const int32_t ix = c % a.nx, iy = (c / a.nx) % a.ny, iz = c / (a.nx * a.ny);
+        xi = a.xs[k];
+        yi = a.ys[k];
+        zi = a.zs[k];
+        wi = a.ws[k];
+        const float gxl = xi * xi, gxr = (W - xi) * (W - xi);
+        const float gyl = yi * yi, gyr = (W - yi) * (W - yi);
+        const float gzl = zi * zi, gzr = (W - zi) * (W - zi);
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int32_t cz = iz + dz;
+            if (cz < 0 || cz >= a.nz) continue;
+            const float gz = dz < 0 ? gzl : (dz > 0 ? gzr : 0.f);
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int32_t cy = iy + dy;
+                if (cy < 0 || cy >= a.ny) continue;
+                const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + gz;
+                if (gyz >= reach2) continue; // the whole row is out of reach
+                const bool left = ix > 0 && gxl + gyz < reach2;
+                const bool right = ix + 1 < a.nx && gxr + gyz < reach2;
+                const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz) + ix;
+                const int32_t e1 = a.off[rb], e2 = a.off[rb + 1];
+                const int32_t e0 = left ? a.off[rb - 1] : e1;
+                const int32_t e3 = right ? a.off[rb + 2] : e2;
+                if (e3 > e0) {
+                    segtab[nseg][tid] = make_int4(e0, e1, e2, e3);
+                    segcode[nseg][tid] = (uint8_t)(((dy + 1) << 2) | (dz + 1));
+                    ++nseg;
+                }
+            }
+        }
+    }
+    // target coordinate shifted into the frame of a neighbour cell:
+    // x - dx W for dx = -1, 0, 1 (the same roundings as the subtraction)
+    const float xm = xi + W, xp = xi - W, ym = yi + W, yp = yi - W, zm = zi + W, zp = zi - W;
+    auto sel = [](int q, float m, float o, float p) { return q == 0 ? m : (q == 1 ? o : p); };
+
+    Target<PREC, INV> T;
+    int32_t *myq = &fifo[wid][0][lane];
+    uint8_t *myc = &fcode[wid][0][lane];
+    int seg = 0, qh = 0, qc = 0, row = 0;
+    int32_t j = 0, jend = 0, b1 = 0, b2 = 0;
+    float ty = 0.f, tz = 0.f;
+    auto pop = [&]() {
+        const int32_t jj = myq[qh * 64];
+        const int c = myc[qh * 64];
+        qh = (qh + 1) & (Q - 1);
+        --qc;
+        const float ddx = sel(c & 3, xm, xi, xp) - a.xs[jj];
+        const float ddy = sel((c >> 4) & 3, ym, yi, yp) - a.ys[jj];
+        const float ddz = sel((c >> 2) & 3, zm, zi, zp) - a.zs[jj];
+        T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), a.ws[jj], a.k);
+    };
+    while (true) {
+        if (j >= jend && seg < nseg) {
+            const int4 sg = segtab[seg][tid];
+            row = segcode[seg][tid];
+            ++seg;
+            j = sg.x;
+            b1 = sg.y;
+            b2 = sg.z;
+            jend = sg.w;
+            ty = sel(row >> 2, ym, yi, yp);
+            tz = sel(row & 3, zm, zi, zp);
+        }
+        const bool have = j < jend;
+        if (!__any(have)) break;
+        if (have) {
+            const int dxc = j < b1 ? 0 : (j < b2 ? 1 : 2);
+            const float ddx = sel(dxc, xm, xi, xp) - a.xs[j], ddy = ty - a.ys[j], ddz = tz - a.zs[j];
+            const float t = sq_dist(ddx, ddy, ddz);
+            if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k)) {
+                const int slot = ((qh + qc) & (Q - 1)) * 64;
+                myq[slot] = j;
+                myc[slot] = (uint8_t)(dxc | (row << 2));
+                ++qc;
+            }
+            ++j;
+        }
+        if (__any(qc == Q)) {
+            if (qc > 0) pop();
+        }
+    }
+    while (__any(qc > 0)) {
+        if (qc > 0) pop();
+    }
+    if (active) write_target(a, k, T);
+    if (INV) {
+        long long cnt = 0;
+        double nx = 0, ny = 0, nz = 0, sc = 0, rs = 0;
+        if (active) target_invariants(T, wi, cnt, nx, ny, nz, sc, rs);
+        reduce_invariants(a, lb, cnt, nx, ny, nz, sc, rs);
+    }
+}
+
 // ------------------------------------------------------------------ LDS tiles
 // A workgroup owns a tile of TX x TY x TZ target cells.  The tile's halo box
 // ((TX+2) x (TY+2) x (TZ+2) cells, clipped to the grid) is staged in LDS:
@@ -194,18 +327,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
 // resident at once instead of streamed; larger TY, TZ is the full sub-box
 // (Sec. 5.1).
 //
-// Staged x coordinates are relative to the first cell of their halo row, so
-// the (up to) three cells a target needs from one row form a single range:
-// 9 row segments per target instead of 27 cells.  Each lane first writes its
-// target's non-empty segments, in canonical order, into an LDS table; a
-// neighbour cell whose nearest face is provably beyond the cutoff (a
-// conservative test in squared distances) is left out of its segment, which
-// removes about a quarter of the candidates without changing which pairs are
-// accepted or their order.
+// Staged coordinates are relative to the corner of the halo box, so the
+// difference of two staged positions is the pair's difference vector (exact
+// for positions on a power-of-two lattice with a power-of-two cell width,
+// and then bit-identical to the cell-relative differences of the other
+// organisations), and the (up to) three cells a target needs from one X-row
+// form a single range: 9 row segments per target instead of 27 cells.  Each
+// lane first writes its target's non-empty segments, in canonical order,
+// into an LDS table; a neighbour cell whose nearest face is provably beyond
+// the cutoff (a conservative test in squared distances) is left out of its
+// segment, which removes about a quarter of the candidates without changing
+// which pairs are accepted or their order.
 //
 // Candidate testing and pair evaluation are decoupled: each lane walks its
-// segments in lockstep with the wavefront and pushes every accepted pair
-// (dx, dy, dz, w_j) into a private FIFO of Q entries in LDS; whenever some
+// segments in lockstep with the wavefront and pushes the LDS index of every
+// accepted source into a private FIFO of Q entries in LDS; whenever some
 // lane's FIFO is full, the wavefront pops one entry per non-empty lane and
 // evaluates the kernel.  Otherwise the wavefront would run the long
 // evaluation on almost every candidate step (about one candidate in six is
@@ -254,11 +390,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     constexpr int TR = TY * TZ;  // target rows
     static_assert(R <= 64 && TR <= 64, "row tables are scanned by one wavefront");
     static_assert((Q & (Q - 1)) == 0, "FIFO depth must be a power of two");
-    static_assert(CAP <= 4096, "segment table packs LDS indices in 12 bits");
+    static_assert(CAP < 4096, "segment table packs LDS indices in 12 bits");
     __shared__ float4 sp[CAP];
-    __shared__ int32_t fifo[kBlock / 64][Q][64]; // accepted source: LDS index | (dy,dz) code << 12
-    __shared__ int32_t segtab[9][kBlock]; // start | len << 12 | (dy,dz) code << 25
-    // (dy, dz) code: (dy + 1) << 2 | (dz + 1)
+    __shared__ int32_t fifo[kBlock / 64][Q][64]; // accepted source: LDS index
+    __shared__ int32_t segtab[9][kBlock]; // LDS range of a row segment: start | end << 12
     __shared__ int32_t cs[R][HX + 1];
     __shared__ int32_t rstart[R + 1];
     __shared__ int32_t gstart[R];
@@ -362,7 +497,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             v = a.off[(int64_t)rbase[r] + cxlo + jj] - gstart[r] + rstart[r];
         cs[r][jj] = v;
     }
-    // 3. stage the halo particles, x relative to the row's first cell
+    // 3. stage the halo particles in tile-relative coordinates: offsets from
+    //    the corner of the halo box (cell (cxlo, y0 - 1, z0 - 1)), so that a
+    //    difference of two staged positions is the pair's difference vector
+    //    with no per-row shift
     for (int32_t f = tid; f < total; f += kBlock) {
         int lo = 0, hi = R; // rstart[lo] <= f < rstart[hi]
         while (hi - lo > 1) {
@@ -371,7 +509,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         }
         const int32_t g = gstart[lo] + (f - rstart[lo]);
         const int32_t cx = a.cell[g] - rbase[lo];
-        sp[f] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, a.xs[g]), a.ys[g], a.zs[g], a.ws[g]);
+        sp[f] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, a.xs[g]),
+                            __builtin_fmaf((float)(lo % HY), W, a.ys[g]),
+                            __builtin_fmaf((float)(lo / HY), W, a.zs[g]), a.ws[g]);
     }
     __syncthreads();
 
@@ -397,10 +537,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             self = rstart[hr] + (k - gstart[hr]);
             const float4 p = sp[self];
             xt = p.x; yt = p.y; zt = p.z; wi = p.w;
-            const float xc = a.xs[k]; // cell-relative x of the target
+            // cell-relative position of the target, for the reach test
+            const float xc = a.xs[k], yc = a.ys[k], zc = a.zs[k];
             const float gxl = xc * xc, gxr = (W - xc) * (W - xc);
-            const float gyl = yt * yt, gyr = (W - yt) * (W - yt);
-            const float gzl = zt * zt, gzr = (W - zt) * (W - zt);
+            const float gyl = yc * yc, gyr = (W - yc) * (W - yc);
+            const float gzl = zc * zc, gzr = (W - zc) * (W - zc);
             const int32_t jc = ix - cxlo;
             // segments in canonical (dz, dy) order
             for (int dz = -1; dz <= 1; ++dz) {
@@ -418,21 +559,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                     const int32_t s0 = cs[r][jc - (left ? 1 : 0)];
                     const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
                     if (s1 > s0) {
-                        segtab[nseg][tid] = s0 | ((s1 - s0) << 12) | ((((dy + 1) << 2) | (dz + 1)) << 25);
+                        segtab[nseg][tid] = s0 | (s1 << 12);
                         ++nseg;
                     }
                 }
             }
         }
         Target<PREC, INV> T;
-        int seg = 0, qh = 0, qc = 0, code = 0;
+        int seg = 0, qh = 0, qc = 0;
         int32_t j = 0, jend = 0;
-        float tyy = 0.f, tzz = 0.f;
-        // target coordinate shifted into the frame of neighbour row dy (dz):
-        // y - dy W for dy = -1, 0, 1 (the same roundings as the subtraction)
-        const float ym = yt + W, yp = yt - W, zm = zt + W, zp = zt - W;
-        auto shift_y = [&](int c) { const int q = c >> 2; return q == 0 ? ym : (q == 1 ? yt : yp); };
-        auto shift_z = [&](int c) { const int q = c & 3; return q == 0 ? zm : (q == 1 ? zt : zp); };
         // Evaluate the oldest queued pair of this lane: the differences are
         // recomputed from the same operands, so they are bit-identical to the
         // ones the test used.
@@ -440,9 +575,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             const int32_t e = myq[qh * 64];
             qh = (qh + 1) & (Q - 1);
             --qc;
-            const float4 s = sp[e & 4095];
-            const int c = e >> 12;
-            const float ddx = xt - s.x, ddy = shift_y(c) - s.y, ddz = shift_z(c) - s.z;
+            const float4 s = sp[e];
+            const float ddx = xt - s.x, ddy = yt - s.y, ddz = zt - s.z;
             T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
         };
         while (true) {
@@ -450,19 +584,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                 const int32_t sg = segtab[seg][tid];
                 ++seg;
                 j = sg & 4095;
-                jend = j + ((sg >> 12) & 8191);
-                code = sg >> 25;
-                tyy = shift_y(code);
-                tzz = shift_z(code);
+                jend = sg >> 12;
             }
             const bool have = j < jend;
             if (!__any(have)) break;
             if (have) {
                 const float4 s = sp[j];
-                const float ddx = xt - s.x, ddy = tyy - s.y, ddz = tzz - s.z;
+                const float ddx = xt - s.x, ddy = yt - s.y, ddz = zt - s.z;
                 const float t = sq_dist(ddx, ddy, ddz);
                 if (t < a.k.hi && j != self && inside_cutoff(ddx, ddy, ddz, t, a.k)) {
-                    myq[((qh + qc) & (Q - 1)) * 64] = j | (code << 12);
+                    myq[((qh + qc) & (Q - 1)) * 64] = j;
                     ++qc;
                 }
                 ++j;
@@ -565,8 +696,9 @@ __global__ __launch_bounds__(kBlock) void k_inv_stage2(const InvPartial *__restr
     }
 }
 
-// Batch mode: invariants of system s from its workgroups' partials
-// [block_base[s], block_base[s+1]) (one workgroup per system, fixed order).
+// Batch mode: invariants of table entry s from its workgroups' partials
+// [block_base[s], block_base[s+1]) (one workgroup per system, fixed order),
+// written to the system's place in the caller's list.
 __global__ __launch_bounds__(kBlock) void k_inv_systems(const InvPartial *__restrict__ parts,
                                                         const SysDev *__restrict__ sys, int32_t nsys,
                                                         int32_t total_blocks, pi_invariants *__restrict__ out)
@@ -589,12 +721,13 @@ __global__ __launch_bounds__(kBlock) void k_inv_systems(const InvPartial *__rest
     }
     inv_block_reduce(c, v, redc, red);
     if (threadIdx.x == 0) {
-        out[s].pairs = redc[0];
-        out[s].net[0] = red[0][0];
-        out[s].net[1] = red[0][1];
-        out[s].net[2] = red[0][2];
-        out[s].scale = red[0][3];
-        out[s].rho_sum = red[0][4];
+        pi_invariants &o = out[sys[s].orig];
+        o.pairs = redc[0];
+        o.net[0] = red[0][0];
+        o.net[1] = red[0][1];
+        o.net[2] = red[0][2];
+        o.scale = red[0][3];
+        o.rho_sum = red[0][4];
     }
 }
 
@@ -657,6 +790,7 @@ const TileCfg kTiles[] = {
 };
 
 constexpr int kFifo = 8;
+constexpr int kStreamId = 9; // organisation id of the FIFO stream sweep
 
 // nblk: in single-system mode computed here from the grid; in batch mode
 // given (the sum of the systems' tile counts).
@@ -686,6 +820,14 @@ void launch_sweep(pi_ctx *ctx, int tile_id, const SweepArgs &a, hipStream_t s, u
     case 6: launch_tile<4, 4, 4, 1536, PREC, INV, BATCH>(ctx, "k_sweep_tile<4,4,4>", a, s, nblk); break;
     case 7: launch_tile<4, 4, 2, 1536, PREC, INV, BATCH>(ctx, "k_sweep_tile<4,4,2>", a, s, nblk); break;
     case 8: launch_tile<16, 4, 3, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<16,4,3>", a, s, nblk); break;
+    case kStreamId:
+        if (!BATCH) {
+            nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
+            if (nblk == 0) nblk = 1;
+        }
+        PI_LAUNCH(ctx, "k_sweep_stream", (k_sweep_stream<kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0, s,
+                  a);
+        break;
     default:
         if (!BATCH) {
             nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
@@ -740,6 +882,7 @@ bool pi_tile_shape(int tile_id, int *tx, int *ty, int *tz)
 int pi_pick_tile(const pi_interact_opts &o, double ppc)
 {
     if (o.sweep == PI_SWEEP_NOLDS) return 0;
+    if (o.sweep == PI_SWEEP_STREAM) return kStreamId;
     if (o.sweep == PI_SWEEP_PENCIL || o.sweep == PI_SWEEP_SUBBOX) {
         if (o.tile[0] > 0) {
             for (const TileCfg &t : kTiles)
@@ -776,11 +919,13 @@ int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys)
     return base;
 }
 
+// One sweep launch over the systems of table d_sys[0 .. nsys) (all with tile
+// tile_id); their workgroup partials go to records part_base + block.
 pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
-                         int64_t total_blocks, int tile_id, const pi_interact_opts &o, float *rho, float *gx,
-                         float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream)
+                         int64_t total_blocks, int64_t part_base, int tile_id, const pi_interact_opts &o, float *rho,
+                         float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream)
 {
-    if (total_blocks > cells->cap_partials) return PI_ENOMEM;
+    if (part_base + total_blocks > cells->cap_partials) return PI_ENOMEM;
     SweepArgs a;
     memset(&a, 0, sizeof(a));
     a.off = cells->offsets;
@@ -797,7 +942,7 @@ pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDe
     a.gy = gy;
     a.gz = gz;
     a.count = count;
-    a.partials = (InvPartial *)cells->partials;
+    a.partials = (InvPartial *)cells->partials + part_base;
     a.sys = d_sys;
     a.kcs = d_kcs;
     a.nsys = nsys;
@@ -836,7 +981,7 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, hipStream_t s)
     ctx->timing_on = 0;
     int best = -1;
     float best_ms = 0.f;
-    for (int cand = 0; cand <= 8; ++cand) {
+    for (int cand = 0; cand <= kStreamId; ++cand) {
         unsigned nblk = 0;
         float ms = 0.f;
         bool ok = true;
@@ -882,6 +1027,20 @@ pi_status tuned_tile(pi_ctx *ctx, const SweepArgs &a, int prec, int64_t n, doubl
 }
 
 } // namespace
+
+// AUTO organisation of one system of a batch: the tuner's cached choice for
+// the system's class if there is one, else the static rule (no trials are
+// run inside a batch).
+int pi_auto_tile(pi_ctx *ctx, int precision, int64_t n, double ppc)
+{
+    pi_tuner *t = ctx->tuner;
+    if (t && t->mode == PI_TUNE_TIMED) {
+        std::lock_guard<std::mutex> g(t->mu);
+        auto it = t->choice.find(tune_key(precision, n, ppc, false));
+        if (it != t->choice.end()) return it->second;
+    }
+    return pick_tile_default(ppc);
+}
 
 extern "C" pi_status pi_tuner_mode(pi_ctx *ctx, int32_t mode)
 {
@@ -932,7 +1091,7 @@ extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t
         out->tile[1] = ty;
         out->tile[2] = tz;
     } else {
-        out->sweep = PI_SWEEP_NOLDS;
+        out->sweep = tile == kStreamId ? PI_SWEEP_STREAM : PI_SWEEP_NOLDS;
     }
     return PI_OK;
 }
@@ -947,7 +1106,7 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (o.precision < PI_PREC_COMPENSATED || o.precision > PI_PREC_FP64ACC) return PI_EINVAL;
-    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_SUBBOX) return PI_EINVAL;
+    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_STREAM) return PI_EINVAL;
     if (o.order != PI_ORDER_SORTED && o.order != PI_ORDER_ORIGINAL) return PI_EINVAL;
     const bool anyf = rho || gx || gy || gz;
     const bool allf = rho && gx && gy && gz;

@@ -20,12 +20,12 @@ LIB_PATH = os.path.join(HERE, "libpi.so")
 PI_OK, PI_EINVAL, PI_ENOMEM, PI_ERANGE, PI_EDEVICE, PI_EAGAIN, PI_ENOTFOUND, PI_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
 PI_PREC_COMPENSATED, PI_PREC_PLAIN, PI_PREC_FP64ACC = 0, 1, 2
-PI_SWEEP_AUTO, PI_SWEEP_NOLDS, PI_SWEEP_PENCIL, PI_SWEEP_SUBBOX = 0, 1, 2, 3
+PI_SWEEP_AUTO, PI_SWEEP_NOLDS, PI_SWEEP_PENCIL, PI_SWEEP_SUBBOX, PI_SWEEP_STREAM = 0, 1, 2, 3, 4
 PI_ORDER_SORTED, PI_ORDER_ORIGINAL = 0, 1
 
 PRECISIONS = {"compensated": PI_PREC_COMPENSATED, "plain": PI_PREC_PLAIN, "fp64acc": PI_PREC_FP64ACC}
 SWEEPS = {"auto": PI_SWEEP_AUTO, "nolds": PI_SWEEP_NOLDS, "pencil": PI_SWEEP_PENCIL,
-          "subbox": PI_SWEEP_SUBBOX}
+          "subbox": PI_SWEEP_SUBBOX, "stream": PI_SWEEP_STREAM}
 
 
 class PiError(RuntimeError):

@@ -58,8 +58,8 @@ def _check(res, ref):
         assert np.all(np.abs(res[k].astype(np.float64) - getattr(ref, k)) <= TOL * ref.ascale)
 
 
-@pytest.mark.parametrize("sweep,tile", [("auto", (0, 0, 0)), ("nolds", (0, 0, 0)), ("subbox", (4, 4, 4)),
-                                        ("pencil", (30, 1, 1)), ("subbox", (6, 6, 6))])
+@pytest.mark.parametrize("sweep,tile", [("auto", (0, 0, 0)), ("nolds", (0, 0, 0)), ("stream", (0, 0, 0)),
+                                        ("subbox", (4, 4, 4)), ("pencil", (30, 1, 1)), ("subbox", (6, 6, 6))])
 def test_batch_matches_oracle_per_system(dev, sweep, tile):
     systems = _mixed_systems()
     db = dev.DeviceBatch(systems)

@@ -147,7 +147,7 @@ def test_tuner_choice_is_what_auto_runs(lib):
     ds.bin()
     pi.pi_tuner_mode(ds.ctx.handle, pi.PI_TUNE_TIMED)
     choice = pi.pi_tuner_choice(ds.ctx.handle, ds.cells)
-    assert choice.sweep in (pi.PI_SWEEP_NOLDS, pi.PI_SWEEP_PENCIL, pi.PI_SWEEP_SUBBOX)
+    assert choice.sweep in (pi.PI_SWEEP_NOLDS, pi.PI_SWEEP_STREAM, pi.PI_SWEEP_PENCIL, pi.PI_SWEEP_SUBBOX)
     ds.interact(sweep="auto", order="original")
     auto = ds.results()
     ds.interact(sweep=int(choice.sweep), tile=tuple(choice.tile), order="original")
