@@ -252,10 +252,7 @@ static int list_buffers(pi_cells *c, BufRef *out)
     for (int b = 0; b < 2; ++b) {
         add((void **)&c->skey[b], BUF_N, 4);
         add((void **)&c->sidx[b], BUF_N, 4);
-        add((void **)&c->sx[b], BUF_N, 4);
-        add((void **)&c->sy[b], BUF_N, 4);
-        add((void **)&c->sz[b], BUF_N, 4);
-        add((void **)&c->sw[b], BUF_N, 4);
+        add((void **)&c->sp[b], BUF_N, 16);
     }
     add((void **)&c->hist, BUF_HIST, 4);
     add((void **)&c->hist_tsum, BUF_HIST_TILES, 4);

@@ -43,10 +43,15 @@ constexpr int kSBlock = PI_SCATTER_BLOCK;     // scatter threads per tile (256, 
 constexpr int kSItems = kSortTile / kSBlock;  // keys per thread
 static_assert(kSBlock >= kRadix && kSBlock <= 1024 && kSortTile % kSBlock == 0, "scatter block size");
 
+// p[0 .. n) = v, four entries per thread (p 16-byte aligned)
 __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) p[i] = v;
+    const int64_t i = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (i + 3 < n) {
+        *reinterpret_cast<int4 *>(p + i) = make_int4(v, v, v, v);
+    } else {
+        for (int64_t q = i; q < n; ++q) p[q] = v;
+    }
 }
 
 // ------------------------------------------------------------- scan (DPP)
@@ -234,46 +239,67 @@ struct SortArgs {
     int32_t nsys;
     // first pass reads the caller's arrays
     const float *x, *y, *z, *w;
-    // later passes read the previous pass's output
+    // later passes read the previous pass's output: keys and indices as
+    // arrays, the payload (x, y, z, w) as 16-byte records
     const uint32_t *key_in;
     const int32_t *idx_in;
-    const float *x_in, *y_in, *z_in, *w_in;
-    // outputs (ping-pong buffer, or the final arrays on the last pass)
+    const float4 *p_in;
+    // outputs: the ping-pong buffers (key_out, idx_out, p_out), or on the
+    // last pass the final arrays (key_out = cell, idx_out = perm, x_out ..
+    // w_out = cell-relative SoA)
     uint32_t *key_out;
     uint32_t *gkey_out; // batch mode, last pass: global cell ids (for counting)
     int32_t *idx_out;
+    float4 *p_out;
     float *x_out, *y_out, *z_out, *w_out;
     const int32_t *gbase; // scanned histogram, digit-major
     int32_t *hist;
     uint32_t *err;
 };
 
-// Global cell key of caller particle e.
+// Global cell key of caller particle e at position (x, y, z).
 template <bool BATCH>
-__device__ __forceinline__ uint32_t first_key(const SortArgs &a, int64_t e)
+__device__ __forceinline__ uint32_t key_at(const SortArgs &a, int64_t e, float x, float y, float z)
 {
-    if (!BATCH) return cell_key(a.x[e], a.y[e], a.z[e], a.g, a.err);
+    if (!BATCH) return cell_key(x, y, z, a.g, a.err);
     const SysDev &s = a.sys[sys_of_particle(a.sys, a.nsys, e)];
-    return (uint32_t)s.cell_base + cell_key(a.x[e], a.y[e], a.z[e], s.g, a.err);
+    return (uint32_t)s.cell_base + cell_key(x, y, z, s.g, a.err);
 }
 
 template <bool FIRST, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_radix_hist(SortArgs a)
 {
-    __shared__ int32_t h[kRadix];
-    h[threadIdx.x] = 0;
-    __syncthreads();
+    __shared__ int32_t h[4][kRadix]; // one histogram per wavefront
+    const int wid = threadIdx.x >> 6;
+    for (int w = 0; w < 4; ++w) h[w][threadIdx.x] = 0;
+    // all of the tile's loads first (indices past the end clamped; their
+    // keys are not counted)
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
-    for (int q = 0; q < kSortItems; ++q) {
-        const int64_t e = base + q * kBlock + threadIdx.x;
-        if (e < a.n) {
-            const uint32_t key = FIRST ? first_key<BATCH>(a, e) : a.key_in[e];
-            atomicAdd(&h[(key >> a.shift) & (kRadix - 1)], 1);
+    const int64_t last = (int64_t)a.n - 1;
+    uint32_t key[kSortItems];
+    if (FIRST) {
+        float px[kSortItems], py[kSortItems], pz[kSortItems];
+#pragma unroll
+        for (int q = 0; q < kSortItems; ++q) {
+            const int64_t e = min(base + q * kBlock + threadIdx.x, last);
+            px[q] = a.x[e];
+            py[q] = a.y[e];
+            pz[q] = a.z[e];
         }
+#pragma unroll
+        for (int q = 0; q < kSortItems; ++q)
+            key[q] = key_at<BATCH>(a, min(base + q * kBlock + threadIdx.x, last), px[q], py[q], pz[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < kSortItems; ++q) key[q] = a.key_in[min(base + q * kBlock + threadIdx.x, last)];
     }
     __syncthreads();
-    a.hist[(int64_t)threadIdx.x * a.ntiles + blockIdx.x] = h[threadIdx.x];
+#pragma unroll
+    for (int q = 0; q < kSortItems; ++q)
+        if (base + q * kBlock + threadIdx.x < a.n) atomicAdd(&h[wid][(key[q] >> a.shift) & (kRadix - 1)], 1);
+    __syncthreads();
+    const int d = threadIdx.x;
+    a.hist[(int64_t)d * a.ntiles + blockIdx.x] = (h[0][d] + h[1][d]) + (h[2][d] + h[3][d]);
 }
 
 // Lanes of the wavefront whose digit equals this lane's (among `valid`).
@@ -288,15 +314,6 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid)
     return m;
 }
 
-// Global cell key of caller particle e at position (x, y, z).
-template <bool BATCH>
-__device__ __forceinline__ uint32_t key_at(const SortArgs &a, int64_t e, float x, float y, float z)
-{
-    if (!BATCH) return cell_key(x, y, z, a.g, a.err);
-    const SysDev &s = a.sys[sys_of_particle(a.sys, a.nsys, e)];
-    return (uint32_t)s.cell_base + cell_key(x, y, z, s.g, a.err);
-}
-
 template <bool FIRST, bool LAST, bool BATCH>
 __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
 {
@@ -305,7 +322,7 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
     __shared__ int32_t lstart[kRadix];   // tile-local start of each digit
     __shared__ int32_t gdst[kRadix];     // global start of each digit's run
     __shared__ int32_t scan_tmp[4];
-    __shared__ uint32_t lds_buf[2][kSortTile + 1]; // [1] first holds the destinations
+    __shared__ uint2 lds2[2][kSortTile + 1]; // reorder buffers; [1] first holds the destinations
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile_base = (int64_t)blockIdx.x * kSortTile;
@@ -332,10 +349,11 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
         } else {
             key[r] = a.key_in[e];
             pidx[r] = a.idx_in[e];
-            px[r] = a.x_in[e];
-            py[r] = a.y_in[e];
-            pz[r] = a.z_in[e];
-            pw[r] = a.w_in[e];
+            const float4 q = a.p_in[e];
+            px[r] = q.x;
+            py[r] = q.y;
+            pz[r] = q.z;
+            pw[r] = q.w;
         }
     }
     if (FIRST) {
@@ -400,7 +418,7 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
         const int32_t within = wcnt[wid][dg] + pos[r];
         const bool valid = pos[r] >= 0;
         pos[r] = valid ? lstart[dg] + within : kSortTile;
-        lds_buf[1][pos[r]] = (uint32_t)(gdst[dg] + within);
+        reinterpret_cast<uint32_t *>(lds2[1])[pos[r]] = (uint32_t)(gdst[dg] + within);
     }
     const int32_t nvalid = (int32_t)min((int64_t)kSortTile, (int64_t)a.n - tile_base);
     __syncthreads();
@@ -408,23 +426,26 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
 #pragma unroll
     for (int k = 0; k < kSItems; ++k) {
         const int p = tid + k * kSBlock;
-        dst[k] = p < nvalid ? (int32_t)lds_buf[1][p] : 0;
+        dst[k] = p < nvalid ? (int32_t)reinterpret_cast<const uint32_t *>(lds2[1])[p] : 0;
     }
 
     // 4. each array reordered through LDS (two buffers, one barrier per
-    //    array) and written out in runs
+    //    array) and written out in runs; the element type is 4 or 8 bytes
     int buf = 0;
-    auto pass_array = [&](auto value_of, auto store) {
+    auto pass = [&](auto zero, auto value_of, auto store) {
+        using T = decltype(zero);
+        T *lb = reinterpret_cast<T *>(lds2[buf]);
 #pragma unroll
-        for (int r = 0; r < kSItems; ++r) lds_buf[buf][pos[r]] = value_of(r);
+        for (int r = 0; r < kSItems; ++r) lb[pos[r]] = value_of(r);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kSItems; ++k) {
             const int p = tid + k * kSBlock;
-            if (p < nvalid) store(dst[k], lds_buf[buf][p]);
+            if (p < nvalid) store(dst[k], lb[p]);
         }
         buf ^= 1;
     };
+    auto pass_array = [&](auto value_of, auto store) { pass(uint32_t(0), value_of, store); };
 
     if (LAST) {
         // final arrays: local cell ids, and the cell-relative coordinates
@@ -466,27 +487,30 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
                 return __float_as_uint(__builtin_fmaf(-(float)iz, g.w, pz[r] - g.oz));
             },
             [&](int32_t o, uint32_t v) { a.z_out[o] = __uint_as_float(v); });
+        pass_array([&](int r) { return __float_as_uint(pw[r]); },
+                   [&](int32_t o, uint32_t v) { a.w_out[o] = __uint_as_float(v); });
     } else {
+        // ping-pong buffers: keys and indices, then the 16-byte payload
+        // records in two 8-byte halves (the two halves of a record meet in
+        // the L2 before the line is written back)
         pass_array([&](int r) { return key[r]; }, [&](int32_t o, uint32_t v) { a.key_out[o] = v; });
         pass_array([&](int r) { return (uint32_t)pidx[r]; }, [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
-        pass_array([&](int r) { return __float_as_uint(px[r]); },
-                   [&](int32_t o, uint32_t v) { a.x_out[o] = __uint_as_float(v); });
-        pass_array([&](int r) { return __float_as_uint(py[r]); },
-                   [&](int32_t o, uint32_t v) { a.y_out[o] = __uint_as_float(v); });
-        pass_array([&](int r) { return __float_as_uint(pz[r]); },
-                   [&](int32_t o, uint32_t v) { a.z_out[o] = __uint_as_float(v); });
+        float2 *pout = reinterpret_cast<float2 *>(a.p_out);
+        pass(make_uint2(0, 0), [&](int r) { return make_uint2(__float_as_uint(px[r]), __float_as_uint(py[r])); },
+             [&](int32_t o, uint2 v) { pout[2 * (int64_t)o] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y)); });
+        pass(make_uint2(0, 0), [&](int r) { return make_uint2(__float_as_uint(pz[r]), __float_as_uint(pw[r])); },
+             [&](int32_t o, uint2 v) {
+                 pout[2 * (int64_t)o + 1] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+             });
     }
-    pass_array([&](int r) { return __float_as_uint(pw[r]); },
-               [&](int32_t o, uint32_t v) { a.w_out[o] = __uint_as_float(v); });
 }
 
-// Per-cell counts from the sorted global cell ids, without a loop or an
-// atomic per particle.  A wavefront reads 8 consecutive chunks of 64 ids at
-// once (all loads in flight together); in each chunk, a lane that starts a
-// run of equal ids, or lane 0 (which may continue a run from the chunk
-// before), owns the piece of the run up to the next such lane or the chunk's
-// end.  A piece that is a whole run is stored; pieces of runs that cross
-// chunks are added atomically (counts start at zero).
+// Per-cell counts from the sorted global cell ids, one plain store per
+// occupied cell and no atomics (counts start at zero).  A wavefront reads 8
+// consecutive chunks of 64 ids at once; the lane at the start of a run of
+// equal ids finds the run's end as the next run start, from the chunks' start
+// masks (wave ballots), or past the wavefront's range by galloping over the
+// sorted ids (rare: only the last run of a range can cross it).
 constexpr int kRunChunks = 8;
 
 __global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t *__restrict__ key,
@@ -496,39 +520,54 @@ __global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t
     const int64_t wbase = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * (64 * kRunChunks);
     if (wbase >= n) return; // uniform over the wavefront
     const int64_t last = (int64_t)n - 1;
+    const int64_t wend = wbase + 64 * kRunChunks; // first id past the range
     uint32_t kv[kRunChunks];
 #pragma unroll
     for (int r = 0; r < kRunChunks; ++r) kv[r] = key[min(wbase + r * 64 + lane, last)];
-    const uint32_t before = key[wbase > 0 ? wbase - 1 : 0];       // id before the range
-    const uint32_t after = key[min(wbase + 64 * kRunChunks, last)]; // id after it
+    const uint32_t before = key[wbase > 0 ? wbase - 1 : 0]; // id before the range
+    // run starts of every chunk
+    uint64_t starts[kRunChunks];
+    bool mine[kRunChunks];
 #pragma unroll
     for (int r = 0; r < kRunChunks; ++r) {
         const int64_t k = wbase + r * 64 + lane;
-        const bool valid = k < n;
-        const uint32_t c = kv[r];
-        const uint32_t up = __shfl_up(c, 1);
+        const uint32_t up = __shfl_up(kv[r], 1);
         const uint32_t p63 = r > 0 ? __shfl(kv[r > 0 ? r - 1 : 0], 63) : before;
         const uint32_t prev = lane == 0 ? p63 : up;
-        const uint32_t nxt = r + 1 < kRunChunks ? __shfl(kv[r + 1 < kRunChunks ? r + 1 : r], 0) : after;
-        const bool start = valid && (k == 0 || prev != c);
-        const bool head = valid && (start || lane == 0);
-        const uint64_t heads = __ballot(head);
-        if (head) {
-            const uint64_t above = heads & ~((2ull << lane) - 1ull); // heads after this lane
-            const int64_t chunk_end = wbase + (r + 1) * 64;
-            int32_t end_lane; // exclusive
-            bool run_ends;
-            if (above) {
-                end_lane = __ffsll((unsigned long long)above) - 1;
-                run_ends = true; // every head after lane 0 starts a run
-            } else {
-                end_lane = (int32_t)(min(chunk_end, (int64_t)n) - (chunk_end - 64));
-                run_ends = chunk_end >= n || nxt != c;
-            }
-            const int32_t len = end_lane - lane;
-            if (start && run_ends) counts[c] = len;
-            else atomicAdd(&counts[c], len);
+        mine[r] = k < n && (k == 0 || prev != kv[r]);
+        starts[r] = __ballot(mine[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kRunChunks; ++r) {
+        if (!mine[r]) continue;
+        const int64_t k = wbase + r * 64 + lane;
+        const uint32_t c = kv[r];
+        int64_t end = -1;
+        const uint64_t above = starts[r] & ~((2ull << lane) - 1ull); // later starts in this chunk
+        if (above) {
+            end = wbase + r * 64 + (__ffsll((unsigned long long)above) - 1);
+        } else {
+#pragma unroll
+            for (int q = r + 1; q < kRunChunks; ++q)
+                if (end < 0 && starts[q]) end = wbase + q * 64 + (__ffsll((unsigned long long)starts[q]) - 1);
         }
+        if (end < 0) {
+            // the run reaches the end of the range: gallop, then bisect, for
+            // the first id past it (ids are sorted, so it is the first != c)
+            int64_t lo = wend - 1, hi = wend, step = 64; // key[lo] == c
+            while (hi < n && key[hi] == c) {
+                lo = hi;
+                hi = hi + step;
+                step *= 2;
+            }
+            if (hi > n) hi = n;
+            while (hi - lo > 1) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (key[mid] == c) lo = mid; else hi = mid;
+            }
+            end = hi;
+        }
+        counts[c] = (int32_t)(end - k);
     }
 }
 
@@ -598,10 +637,7 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
             a.shift = p * kRadixBits;
             a.key_in = cells->skey[src];
             a.idx_in = cells->sidx[src];
-            a.x_in = cells->sx[src];
-            a.y_in = cells->sy[src];
-            a.z_in = cells->sz[src];
-            a.w_in = cells->sw[src];
+            a.p_in = cells->sp[src];
             a.gkey_out = cells->skey[dst];
             if (last) {
                 a.key_out = (uint32_t *)cells->cell;
@@ -613,10 +649,8 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
             } else {
                 a.key_out = cells->skey[dst];
                 a.idx_out = cells->sidx[dst];
-                a.x_out = cells->sx[dst];
-                a.y_out = cells->sy[dst];
-                a.z_out = cells->sz[dst];
-                a.w_out = cells->sw[dst];
+                a.p_out = cells->sp[dst];
+                a.x_out = a.y_out = a.z_out = a.w_out = nullptr;
             }
             const dim3 grid(ntiles), block(kBlock);
             if (first && batch) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, true>), grid, block, 0, stream, a);
@@ -639,7 +673,7 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
 #undef PI_SCATTER
         }
     }
-    PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks(nc, kBlock)), dim3(kBlock), 0, stream, cells->counts, nc,
+    PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks((nc + 3) / 4, kBlock)), dim3(kBlock), 0, stream, cells->counts, nc,
               0);
     if (n > 0) {
         // global ids of the sorted particles: the cell array itself for one

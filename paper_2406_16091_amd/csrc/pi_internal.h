@@ -73,7 +73,7 @@ struct pi_cells {
     // radix-sort ping-pong buffers: key, original index, x, y, z, w
     uint32_t *skey[2];
     int32_t *sidx[2];
-    float *sx[2], *sy[2], *sz[2], *sw[2];
+    float4 *sp[2];       // payload records (x, y, z, w)
     // radix histograms (digit-major, 256 x sort tiles) and their scan scratch
     int32_t *hist;        // [cap_hist]
     int32_t *hist_tsum;   // [cap_hist / 4096 + 1]
