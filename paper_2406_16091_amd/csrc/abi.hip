@@ -222,14 +222,13 @@ extern "C" pi_status pi_cells_create(pi_ctx *ctx, pi_cells **out)
     if (hipMalloc((void **)&c->d_err, 256) != hipSuccess) { free(c); return PI_ENOMEM; }
     if (hipMemset(c->d_err, 0, 256) != hipSuccess) { (void)hipFree(c->d_err); free(c); return PI_EDEVICE; }
     c->max_per_cell = (int32_t *)((char *)c->d_err + 64);
-    c->hist_total = (int32_t *)((char *)c->d_err + 128);
     *out = c;
     return PI_OK;
 }
 
 // Every device buffer of a pi_cells object except the error word, with the
 // capacity class it is sized by.
-enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_TILES, BUF_HIST, BUF_HIST_TILES, BUF_PARTIALS };
+enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_TILES, BUF_HIST, BUF_PARTIALS, BUF_RADIX };
 
 struct BufRef {
     void **ptr;
@@ -255,11 +254,10 @@ static int list_buffers(pi_cells *c, BufRef *out)
         add((void **)&c->sp[b], BUF_N, 16);
     }
     add((void **)&c->hist, BUF_HIST, 4);
-    add((void **)&c->hist_tsum, BUF_HIST_TILES, 4);
-    add((void **)&c->hist_tmax, BUF_HIST_TILES, 4);
     add((void **)&c->tile_sum, BUF_TILES, 4);
     add((void **)&c->tile_max, BUF_TILES, 4);
     add((void **)&c->partials, BUF_PARTIALS, 64);
+    add((void **)&c->dtot, BUF_RADIX, 4);
     return k;
 }
 
@@ -305,7 +303,6 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     const int64_t cap_c = grow_c ? grow(n_cells < 64 ? 64 : n_cells, c->cap_cells) : c->cap_cells;
     const int64_t sort_tiles = (cap_n + 4095) / 4096 + 1;
     const int64_t cap_hist = 256 * sort_tiles;
-    const int64_t cap_hist_tiles = cap_hist / 4096 + 2;
     const int64_t cap_tiles = (cap_c + 4095) / 4096 + 1;
     const int64_t cap_parts = 2 * (cap_c + cap_n / 64) + 64;
     BufRef b[40];
@@ -316,11 +313,11 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
         switch (b[i].cls) {
         case BUF_N: count = cap_n; redo = grow_n; break;
         case BUF_HIST: count = cap_hist; redo = grow_n; break;
-        case BUF_HIST_TILES: count = cap_hist_tiles; redo = grow_n; break;
         case BUF_CELLS: count = cap_c; redo = grow_c; break;
         case BUF_CELLS1: count = cap_c + 1; redo = grow_c; break;
         case BUF_TILES: count = cap_tiles; redo = grow_c; break;
         case BUF_PARTIALS: count = cap_parts; redo = grow_n || grow_c; break;
+        case BUF_RADIX: count = 256; redo = false; break;
         }
         if (!redo && *b[i].ptr) continue;
         if (*b[i].ptr) (void)hipFree(*b[i].ptr);

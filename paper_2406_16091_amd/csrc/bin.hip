@@ -193,6 +193,41 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t *in, int64_t
 
 // ------------------------------------------------------------- radix sort
 
+// Exclusive scan, in place, of each digit's per-tile counts (the histogram is
+// digit-major, so a digit's counts are contiguous); one workgroup per digit,
+// 4096 entries per round; the digit's total goes to dtot[digit].
+__global__ __launch_bounds__(kBlock) void k_digit_scan(int32_t *hist, int32_t ntiles, int32_t *dtot)
+{
+    __shared__ int32_t wsum[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t *h = hist + (int64_t)blockIdx.x * ntiles;
+    int32_t carry = 0;
+    for (int32_t base = 0; base < ntiles; base += kScanTile) {
+        const int32_t t0 = base + (int32_t)threadIdx.x * kScanItems;
+        int32_t v[kScanItems];
+        int32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            v[q] = t0 + q < ntiles ? h[t0 + q] : 0;
+            sum += v[q];
+        }
+        const int32_t inc = wave_incl_scan(sum);
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        int32_t run = carry + inc - sum;
+        for (int k = 0; k < wid; ++k) run += wsum[k];
+        const int32_t round_total = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+#pragma unroll
+        for (int q = 0; q < kScanItems; ++q) {
+            if (t0 + q < ntiles) h[t0 + q] = run;
+            run += v[q];
+        }
+        carry += round_total;
+        __syncthreads(); // wsum is rewritten by the next round
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
+}
+
 // Cell id of a position (X fastest, Fig. 1).  A particle outside the box
 // raises the error bit and is put in the last cell, so that every kernel
 // stays inside its buffers; the results of that call are then unspecified.
@@ -252,7 +287,8 @@ struct SortArgs {
     int32_t *idx_out;
     float4 *p_out;
     float *x_out, *y_out, *z_out, *w_out;
-    const int32_t *gbase; // scanned histogram, digit-major
+    const int32_t *gbase; // per digit: exclusive scan of its per-tile counts
+    const int32_t *dtot;  // per digit: total count
     int32_t *hist;
     uint32_t *err;
 };
@@ -322,6 +358,7 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
     __shared__ int32_t lstart[kRadix];   // tile-local start of each digit
     __shared__ int32_t gdst[kRadix];     // global start of each digit's run
     __shared__ int32_t scan_tmp[4];
+    __shared__ int32_t dscan_tmp[4];
     __shared__ uint2 lds2[2][kSortTile + 1]; // reorder buffers; [1] first holds the destinations
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -398,13 +435,23 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
         tot = run;
     }
     const int32_t inc = wave_incl_scan(tot);
-    if (tid < kRadix && lane == 63) scan_tmp[wid] = inc;
+    // where each digit's run starts in the output: the totals of the smaller
+    // digits plus this digit's count in the tiles before this one
+    const int32_t dt = tid < kRadix ? a.dtot[d] : 0;
+    const int32_t dinc = wave_incl_scan(dt);
+    if (tid < kRadix && lane == 63) {
+        scan_tmp[wid] = inc;
+        dscan_tmp[wid] = dinc;
+    }
     __syncthreads();
     if (tid < kRadix) {
-        int32_t wofs = 0;
-        for (int k = 0; k < wid; ++k) wofs += scan_tmp[k];
+        int32_t wofs = 0, dofs = 0;
+        for (int k = 0; k < wid; ++k) {
+            wofs += scan_tmp[k];
+            dofs += dscan_tmp[k];
+        }
         lstart[d] = wofs + inc - tot;
-        gdst[d] = a.gbase[(int64_t)d * a.ntiles + blockIdx.x];
+        gdst[d] = dofs + dinc - dt + a.gbase[(int64_t)d * a.ntiles + blockIdx.x];
     }
     __syncthreads();
 
@@ -616,7 +663,6 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
         while (bits < 31 && ((int64_t)1 << bits) < nc) ++bits;
         const int passes = (bits + kRadixBits - 1) / kRadixBits;
         const int32_t ntiles = (int32_t)((n + kSortTile - 1) / kSortTile);
-        const int64_t hlen = (int64_t)kRadix * ntiles;
         SortArgs a;
         memset(&a, 0, sizeof(a));
         a.n = (int32_t)n;
@@ -630,6 +676,7 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
         a.w = w;
         a.hist = cells->hist;
         a.gbase = cells->hist;
+        a.dtot = cells->dtot;
         a.err = cells->d_err;
         for (int p = 0; p < passes; ++p) {
             const bool first = p == 0, last = p == passes - 1;
@@ -656,8 +703,8 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
             if (first && batch) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, true>), grid, block, 0, stream, a);
             else if (first) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, false>), grid, block, 0, stream, a);
             else PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<false, false>), grid, block, 0, stream, a);
-            launch_scan(ctx, cells->hist, hlen, cells->hist, cells->hist_total, nullptr, cells->hist_tsum,
-                        cells->hist_tmax, stream);
+            PI_LAUNCH(ctx, "k_digit_scan", k_digit_scan, dim3(kRadix), dim3(kBlock), 0, stream, cells->hist, ntiles,
+                      cells->dtot);
 #define PI_SCATTER(F, L, B) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<F, L, B>), grid, dim3(kSBlock), 0, stream, a)
             if (batch) {
                 if (first && last) PI_SCATTER(true, true, true);

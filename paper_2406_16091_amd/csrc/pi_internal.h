@@ -74,11 +74,9 @@ struct pi_cells {
     uint32_t *skey[2];
     int32_t *sidx[2];
     float4 *sp[2];       // payload records (x, y, z, w)
+    int32_t *dtot;       // radix digit totals (256)
     // radix histograms (digit-major, 256 x sort tiles) and their scan scratch
     int32_t *hist;        // [cap_hist]
-    int32_t *hist_tsum;   // [cap_hist / 4096 + 1]
-    int32_t *hist_tmax;
-    int32_t *hist_total;  // [1]
     // cell-scan scratch
     int32_t *tile_sum;  // [cap_tiles]
     int32_t *tile_max;  // [cap_tiles]

@@ -292,12 +292,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
             const int dxc = j < b1 ? 0 : (j < b2 ? 1 : 2);
             const float ddx = sel(dxc, xm, xi, xp) - a.xs[j], ddy = ty - a.ys[j], ddz = tz - a.zs[j];
             const float t = sq_dist(ddx, ddy, ddz);
-            if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k)) {
-                const int slot = ((qh + qc) & (Q - 1)) * 64;
-                myq[slot] = j;
-                myc[slot] = (uint8_t)(dxc | (row << 2));
-                ++qc;
-            }
+            bool acc = t < a.k.lo;
+            if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
+            // written always (the slot after the tail is free), kept if accepted
+            const int slot = ((qh + qc) & (Q - 1)) * 64;
+            myq[slot] = j;
+            myc[slot] = (uint8_t)(dxc | (row << 2));
+            qc += (acc && j != k) ? 1 : 0;
             ++j;
         }
         if (__any(qc == Q)) {
@@ -393,7 +394,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     static_assert(CAP < 4096, "segment table packs LDS indices in 12 bits");
     __shared__ float4 sp[CAP];
     __shared__ int32_t fifo[kBlock / 64][Q][64]; // accepted source: LDS index
-    __shared__ int32_t segtab[9][kBlock]; // LDS range of a row segment: start | end << 12
+    // LDS ranges of the row segments (start | end << 12); the target's own
+    // row is cut in two around the target itself, so at most 10
+    __shared__ int32_t segtab[10][kBlock];
     __shared__ int32_t cs[R][HX + 1];
     __shared__ int32_t rstart[R + 1];
     __shared__ int32_t gstart[R];
@@ -558,7 +561,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                     const int r = (ty_ + 1 + dy) + HY * (tz_ + 1 + dz);
                     const int32_t s0 = cs[r][jc - (left ? 1 : 0)];
                     const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
-                    if (s1 > s0) {
+                    if (dy == 0 && dz == 0) {
+                        // s0 <= self < s1: the parts before and after it
+                        if (self > s0) segtab[nseg++][tid] = s0 | (self << 12);
+                        if (s1 > self + 1) segtab[nseg++][tid] = (self + 1) | (s1 << 12);
+                    } else if (s1 > s0) {
                         segtab[nseg][tid] = s0 | (s1 << 12);
                         ++nseg;
                     }
@@ -592,10 +599,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                 const float4 s = sp[j];
                 const float ddx = xt - s.x, ddy = yt - s.y, ddz = zt - s.z;
                 const float t = sq_dist(ddx, ddy, ddz);
-                if (t < a.k.hi && j != self && inside_cutoff(ddx, ddy, ddz, t, a.k)) {
-                    myq[((qh + qc) & (Q - 1)) * 64] = j;
-                    ++qc;
-                }
+                // surely inside below lo; the thin band [lo, hi) takes the
+                // exact test (inside_cutoff, unrolled to keep the step short)
+                bool acc = t < a.k.lo;
+                if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
+                // the slot after the queue's tail is free (qc < Q at every
+                // step), so it is written always and kept if accepted
+                myq[((qh + qc) & (Q - 1)) * 64] = j;
+                qc += acc ? 1 : 0;
                 ++j;
             }
             if (__any(qc == Q)) {
