@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
             if (qc > 0) pop();
         }
     }
-    while (__any(qc > 0)) {
+    for (int left = wave_max(qc); left > 0; --left) {
         if (qc > 0) pop();
     }
     if (active) write_target(a, k, T);
@@ -613,7 +613,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                 if (qc > 0) pop();
             }
         }
-        while (__any(qc > 0)) {
+        // drain: as many rounds as the fullest queue holds (a uniform count)
+        for (int left = wave_max(qc); left > 0; --left) {
             if (qc > 0) pop();
         }
         if (tgt) {
