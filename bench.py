@@ -88,12 +88,15 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, inv: bool = True):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summaries (profiles/traffic_*.md), or None if none matches the current
-    kernel sources."""
+    kernel sources.  Among the template instances that match, the one with
+    the invariant reduction on (and not the batch form) is preferred when
+    `inv` is set, since that is the instance the timed step launches."""
     import glob
     want, cur = kernel_key(kernel), source_hash()
+    found = []
     for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
         with open(p) as f:
             for line in f:
@@ -101,8 +104,14 @@ def measured_traffic(kernel: str):
                     parts = line.split()
                     name, val, h = " ".join(parts[1:-2]), parts[-2], parts[-1]
                     if kernel_key(name) == want and h == cur:
-                        return float(val)
-    return None
+                        found.append((name, float(val)))
+    if not found:
+        return None
+    if inv:
+        for name, val in found:
+            if name.replace(" ", "").endswith(",true,false>"):
+                return val
+    return found[0][1]
 
 
 def candidates_from_counts(counts: np.ndarray, dims) -> int:
