@@ -249,8 +249,7 @@ static int list_buffers(pi_cells *c, BufRef *out)
     add((void **)&c->zs, BUF_N, 4);
     add((void **)&c->ws, BUF_N, 4);
     for (int b = 0; b < 2; ++b) {
-        add((void **)&c->skey[b], BUF_N, 4);
-        add((void **)&c->sidx[b], BUF_N, 4);
+        add((void **)&c->skv[b], BUF_N, 8);
         add((void **)&c->sp[b], BUF_N, 16);
     }
     add((void **)&c->hist, BUF_HIST, 4);

@@ -272,21 +272,15 @@ struct SortArgs {
     GridDev g;
     const SysDev *sys; // batch mode: system table (nsys entries), else null
     int32_t nsys;
-    // first pass reads the caller's arrays
+    // the first pass reads the caller's arrays
     const float *x, *y, *z, *w;
-    // later passes read the previous pass's output: keys and indices as
-    // arrays, the payload (x, y, z, w) as 16-byte records
-    const uint32_t *key_in;
-    const int32_t *idx_in;
+    // later passes read the previous pass's records: (cell id, original
+    // index) and the payload (x, y, z, w)
+    const uint2 *kv_in;
     const float4 *p_in;
-    // outputs: the ping-pong buffers (key_out, idx_out, p_out), or on the
-    // last pass the final arrays (key_out = cell, idx_out = perm, x_out ..
-    // w_out = cell-relative SoA)
-    uint32_t *key_out;
-    uint32_t *gkey_out; // batch mode, last pass: global cell ids (for counting)
-    int32_t *idx_out;
+    // every pass writes records of the same two kinds (ping-pong buffers)
+    uint2 *kv_out;
     float4 *p_out;
-    float *x_out, *y_out, *z_out, *w_out;
     const int32_t *gbase; // per digit: exclusive scan of its per-tile counts
     const int32_t *dtot;  // per digit: total count
     int32_t *hist;
@@ -327,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(SortArgs a)
             key[q] = key_at<BATCH>(a, min(base + q * kBlock + threadIdx.x, last), px[q], py[q], pz[q]);
     } else {
 #pragma unroll
-        for (int q = 0; q < kSortItems; ++q) key[q] = a.key_in[min(base + q * kBlock + threadIdx.x, last)];
+        for (int q = 0; q < kSortItems; ++q) key[q] = a.kv_in[min(base + q * kBlock + threadIdx.x, last)].x;
     }
     __syncthreads();
 #pragma unroll
@@ -344,14 +338,16 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid)
     uint64_t m = valid;
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
-        const uint64_t bal = __ballot((d >> b) & 1u);
+        const uint64_t bal = __ballot((d >> b) & 1);
         m &= ((d >> b) & 1u) ? bal : ~bal;
     }
     return m;
 }
 
-template <bool FIRST, bool LAST, bool BATCH>
-__global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
+// (LDS allows two workgroups, i.e. 4 wavefronts per SIMD: registers are
+// budgeted for that, so the prefetched tile stays in registers)
+template <bool FIRST, bool BATCH>
+__global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_radix_scatter(SortArgs a)
 {
     constexpr int W = kSBlock / 64;      // wavefronts per block
     __shared__ int32_t wcnt[W][kRadix];  // per-wave digit counters, then wave bases
@@ -359,17 +355,23 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
     __shared__ int32_t gdst[kRadix];     // global start of each digit's run
     __shared__ int32_t scan_tmp[4];
     __shared__ int32_t dscan_tmp[4];
-    __shared__ uint2 lds2[2][kSortTile + 1]; // reorder buffers; [1] first holds the destinations
+    // reorder buffer: first the destinations (4 bytes per position), then
+    // the (key, index) records (8 bytes), then the payload (16 bytes)
+    __shared__ float4 lbuf[kSortTile + 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t tile_base = (int64_t)blockIdx.x * kSortTile;
     for (int i = tid; i < W * kRadix; i += kSBlock) (&wcnt[0][0])[i] = 0;
+    // this tile's digit offsets (threads 0..255), loaded with the tile
+    const int d = tid & (kRadix - 1);
+    const int32_t dt = tid < kRadix ? a.dtot[d] : 0;
+    const int32_t gb = tid < kRadix ? a.gbase[(int64_t)d * a.ntiles + blockIdx.x] : 0;
 
-    // 0. the whole tile's keys and payload (index, x, y, z, w) in registers:
-    //    every global load of the tile is issued before the first barrier
+    // 0. the whole tile's keys and payload in registers: every global load
+    //    of the tile is issued before the first barrier (indices past the
+    //    end are clamped, so the loads need no branches; the clamped copies
+    //    are never ranked or written)
     auto elem = [&](int r) { return tile_base + wid * (kSItems * 64) + r * 64 + lane; };
-    // (indices past the end are clamped, so the loads need no branches; the
-    // clamped copies are never ranked or written)
     const int64_t last_e = (int64_t)a.n - 1;
     uint32_t key[kSItems];
     int32_t pidx[kSItems];
@@ -384,8 +386,9 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
             pw[r] = a.w[e];
             pidx[r] = (int32_t)e;
         } else {
-            key[r] = a.key_in[e];
-            pidx[r] = a.idx_in[e];
+            const uint2 kv = a.kv_in[e];
+            key[r] = kv.x;
+            pidx[r] = (int32_t)kv.y;
             const float4 q = a.p_in[e];
             px[r] = q.x;
             py[r] = q.y;
@@ -421,8 +424,9 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
     __syncthreads();
 
     // 2. per digit (threads 0..255): bases of the waves, tile total,
-    //    tile-local start (scan over the first four wavefronts)
-    const int d = tid & (kRadix - 1);
+    //    tile-local start (scan over the first four wavefronts), and where
+    //    the digit's run of this tile starts in the output: the totals of
+    //    the smaller digits plus this digit's count in the tiles before
     int32_t tot = 0;
     if (tid < kRadix) {
         int32_t run = 0;
@@ -435,9 +439,6 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
         tot = run;
     }
     const int32_t inc = wave_incl_scan(tot);
-    // where each digit's run starts in the output: the totals of the smaller
-    // digits plus this digit's count in the tiles before this one
-    const int32_t dt = tid < kRadix ? a.dtot[d] : 0;
     const int32_t dinc = wave_incl_scan(dt);
     if (tid < kRadix && lane == 63) {
         scan_tmp[wid] = inc;
@@ -451,21 +452,22 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
             dofs += dscan_tmp[k];
         }
         lstart[d] = wofs + inc - tot;
-        gdst[d] = dofs + dinc - dt + a.gbase[(int64_t)d * a.ntiles + blockIdx.x];
+        gdst[d] = dofs + dinc - dt + gb;
     }
     __syncthreads();
 
     // 3. tile-local position of every key and the global destination of that
     //    position (consecutive positions of one digit go to consecutive
-    //    addresses, so the copies below are coalesced runs)
-    // (keys past the end get the spare slot kSortTile, written but never read)
+    //    addresses, so the copies below are coalesced runs); keys past the
+    //    end get the spare slot kSortTile, written but never read
+    uint32_t *lb4 = reinterpret_cast<uint32_t *>(lbuf);
 #pragma unroll
     for (int r = 0; r < kSItems; ++r) {
         const uint32_t dg = (key[r] >> a.shift) & (kRadix - 1);
         const int32_t within = wcnt[wid][dg] + pos[r];
         const bool valid = pos[r] >= 0;
         pos[r] = valid ? lstart[dg] + within : kSortTile;
-        reinterpret_cast<uint32_t *>(lds2[1])[pos[r]] = (uint32_t)(gdst[dg] + within);
+        lb4[pos[r]] = (uint32_t)(gdst[dg] + within);
     }
     const int32_t nvalid = (int32_t)min((int64_t)kSortTile, (int64_t)a.n - tile_base);
     __syncthreads();
@@ -473,122 +475,94 @@ __global__ __launch_bounds__(kSBlock) void k_radix_scatter(SortArgs a)
 #pragma unroll
     for (int k = 0; k < kSItems; ++k) {
         const int p = tid + k * kSBlock;
-        dst[k] = p < nvalid ? (int32_t)reinterpret_cast<const uint32_t *>(lds2[1])[p] : 0;
+        dst[k] = p < nvalid ? (int32_t)lb4[p] : 0;
     }
+    __syncthreads();
 
-    // 4. each array reordered through LDS (two buffers, one barrier per
-    //    array) and written out in runs; the element type is 4 or 8 bytes
-    int buf = 0;
-    auto pass = [&](auto zero, auto value_of, auto store) {
-        using T = decltype(zero);
-        T *lb = reinterpret_cast<T *>(lds2[buf]);
+    // 4. the (key, index) records, then the payload, reordered through LDS
+    //    and written out in runs
+    uint2 *lb8 = reinterpret_cast<uint2 *>(lbuf);
 #pragma unroll
-        for (int r = 0; r < kSItems; ++r) lb[pos[r]] = value_of(r);
-        __syncthreads();
+    for (int r = 0; r < kSItems; ++r) lb8[pos[r]] = make_uint2(key[r], (uint32_t)pidx[r]);
+    __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kSItems; ++k) {
-            const int p = tid + k * kSBlock;
-            if (p < nvalid) store(dst[k], lb[p]);
-        }
-        buf ^= 1;
-    };
-    auto pass_array = [&](auto value_of, auto store) { pass(uint32_t(0), value_of, store); };
-
-    if (LAST) {
-        // final arrays: local cell ids, and the cell-relative coordinates
-        // fma(-i, w, x - o) of the original coordinate carried along
-        int32_t lcell[kSItems];
-        const GridDev *gr[kSItems];
+    for (int k = 0; k < kSItems; ++k) {
+        const int p = tid + k * kSBlock;
+        if (p < nvalid) a.kv_out[dst[k]] = lb8[p];
+    }
+    __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kSItems; ++r) {
-            lcell[r] = (int32_t)key[r];
-            gr[r] = &a.g;
-            if (BATCH) {
-                const SysDev &sd = a.sys[sys_of_cell(a.sys, a.nsys, key[r])];
-                lcell[r] = (int32_t)(key[r] - (uint32_t)sd.cell_base);
-                gr[r] = &sd.g;
-            }
-        }
-        pass_array([&](int r) { return (uint32_t)lcell[r]; }, [&](int32_t o, uint32_t v) { a.key_out[o] = v; });
-        if (BATCH)
-            pass_array([&](int r) { return key[r]; }, [&](int32_t o, uint32_t v) { a.gkey_out[o] = v; });
-        pass_array([&](int r) { return (uint32_t)pidx[r]; }, [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
-        pass_array(
-            [&](int r) {
-                const GridDev &g = *gr[r];
-                const int32_t ix = lcell[r] % g.nx;
-                return __float_as_uint(__builtin_fmaf(-(float)ix, g.w, px[r] - g.ox));
-            },
-            [&](int32_t o, uint32_t v) { a.x_out[o] = __uint_as_float(v); });
-        pass_array(
-            [&](int r) {
-                const GridDev &g = *gr[r];
-                const int32_t iy = (lcell[r] / g.nx) % g.ny;
-                return __float_as_uint(__builtin_fmaf(-(float)iy, g.w, py[r] - g.oy));
-            },
-            [&](int32_t o, uint32_t v) { a.y_out[o] = __uint_as_float(v); });
-        pass_array(
-            [&](int r) {
-                const GridDev &g = *gr[r];
-                const int32_t iz = lcell[r] / (g.nx * g.ny);
-                return __float_as_uint(__builtin_fmaf(-(float)iz, g.w, pz[r] - g.oz));
-            },
-            [&](int32_t o, uint32_t v) { a.z_out[o] = __uint_as_float(v); });
-        pass_array([&](int r) { return __float_as_uint(pw[r]); },
-                   [&](int32_t o, uint32_t v) { a.w_out[o] = __uint_as_float(v); });
-    } else {
-        // ping-pong buffers: keys and indices, then the 16-byte payload
-        // records in two 8-byte halves (the two halves of a record meet in
-        // the L2 before the line is written back)
-        pass_array([&](int r) { return key[r]; }, [&](int32_t o, uint32_t v) { a.key_out[o] = v; });
-        pass_array([&](int r) { return (uint32_t)pidx[r]; }, [&](int32_t o, uint32_t v) { a.idx_out[o] = (int32_t)v; });
-        float2 *pout = reinterpret_cast<float2 *>(a.p_out);
-        pass(make_uint2(0, 0), [&](int r) { return make_uint2(__float_as_uint(px[r]), __float_as_uint(py[r])); },
-             [&](int32_t o, uint2 v) { pout[2 * (int64_t)o] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y)); });
-        pass(make_uint2(0, 0), [&](int r) { return make_uint2(__float_as_uint(pz[r]), __float_as_uint(pw[r])); },
-             [&](int32_t o, uint2 v) {
-                 pout[2 * (int64_t)o + 1] = make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
-             });
+    for (int r = 0; r < kSItems; ++r) lbuf[pos[r]] = make_float4(px[r], py[r], pz[r], pw[r]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSItems; ++k) {
+        const int p = tid + k * kSBlock;
+        if (p < nvalid) a.p_out[dst[k]] = lbuf[p];
     }
 }
 
-// Per-cell counts from the sorted global cell ids, one plain store per
-// occupied cell and no atomics (counts start at zero).  A wavefront reads 8
-// consecutive chunks of 64 ids at once; the lane at the start of a run of
-// equal ids finds the run's end as the next run start, from the chunks' start
-// masks (wave ballots), or past the wavefront's range by galloping over the
-// sorted ids (rare: only the last run of a range can cross it).
+// After the last pass: the final arrays in sorted order (local cell id,
+// original index, cell-relative position fma(-i, w, x - o), weight), read
+// and written in order, and the per-cell counts from the runs of equal ids
+// -- one plain store per occupied cell and no atomics (counts start at
+// zero).  A wavefront takes 8 consecutive chunks of 64 ids at once; the lane
+// at the start of a run finds the run's end as the next run start, from the
+// chunks' start masks (wave ballots), or past the wavefront's range by
+// galloping over the sorted ids (only the last run of a range can cross it).
 constexpr int kRunChunks = 8;
 
-__global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t *__restrict__ key,
-                                                       int32_t *__restrict__ counts)
+struct FinalArgs {
+    int32_t n;
+    GridDev g;
+    const SysDev *sys; // batch mode
+    int32_t nsys;
+    const uint2 *kv;   // sorted (global cell id, original index)
+    const float4 *p;   // sorted payload
+    int32_t *cell, *perm;
+    float *xs, *ys, *zs, *ws;
+    int32_t *counts;   // indexed by global cell id
+};
+
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * (64 * kRunChunks);
-    if (wbase >= n) return; // uniform over the wavefront
+    if (wbase >= f.n) return; // uniform over the wavefront
+    const int32_t n = f.n;
     const int64_t last = (int64_t)n - 1;
     const int64_t wend = wbase + 64 * kRunChunks; // first id past the range
-    uint32_t kv[kRunChunks];
+    uint2 kv[kRunChunks];
+    float4 pv[kRunChunks];
 #pragma unroll
-    for (int r = 0; r < kRunChunks; ++r) kv[r] = key[min(wbase + r * 64 + lane, last)];
-    const uint32_t before = key[wbase > 0 ? wbase - 1 : 0]; // id before the range
-    // run starts of every chunk
+    for (int r = 0; r < kRunChunks; ++r) {
+        const int64_t e = min(wbase + r * 64 + lane, last);
+        kv[r] = f.kv[e];
+        pv[r] = f.p[e];
+    }
+    const uint32_t before = f.kv[wbase > 0 ? wbase - 1 : 0].x; // id before the range
+
+    // counts first (all loads, including the rare galloping ones, before
+    // any store: a load waits for every earlier memory operation of the
+    // wavefront): run starts of every chunk, then each run's length
     uint64_t starts[kRunChunks];
     bool mine[kRunChunks];
+    int32_t runlen[kRunChunks];
 #pragma unroll
     for (int r = 0; r < kRunChunks; ++r) {
         const int64_t k = wbase + r * 64 + lane;
-        const uint32_t up = __shfl_up(kv[r], 1);
-        const uint32_t p63 = r > 0 ? __shfl(kv[r > 0 ? r - 1 : 0], 63) : before;
+        const uint32_t up = __shfl_up(kv[r].x, 1);
+        const uint32_t p63 = r > 0 ? __shfl(kv[r > 0 ? r - 1 : 0].x, 63) : before;
         const uint32_t prev = lane == 0 ? p63 : up;
-        mine[r] = k < n && (k == 0 || prev != kv[r]);
+        mine[r] = k < n && (k == 0 || prev != kv[r].x);
         starts[r] = __ballot(mine[r]);
     }
 #pragma unroll
     for (int r = 0; r < kRunChunks; ++r) {
+        runlen[r] = 0;
         if (!mine[r]) continue;
         const int64_t k = wbase + r * 64 + lane;
-        const uint32_t c = kv[r];
+        const uint32_t c = kv[r].x;
         int64_t end = -1;
         const uint64_t above = starts[r] & ~((2ull << lane) - 1ull); // later starts in this chunk
         if (above) {
@@ -601,8 +575,8 @@ __global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t
         if (end < 0) {
             // the run reaches the end of the range: gallop, then bisect, for
             // the first id past it (ids are sorted, so it is the first != c)
-            int64_t lo = wend - 1, hi = wend, step = 64; // key[lo] == c
-            while (hi < n && key[hi] == c) {
+            int64_t lo = wend - 1, hi = wend, step = 64; // id lo == c
+            while (hi < n && f.kv[hi].x == c) {
                 lo = hi;
                 hi = hi + step;
                 step *= 2;
@@ -610,13 +584,49 @@ __global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t
             if (hi > n) hi = n;
             while (hi - lo > 1) {
                 const int64_t mid = lo + (hi - lo) / 2;
-                if (key[mid] == c) lo = mid; else hi = mid;
+                if (f.kv[mid].x == c) lo = mid; else hi = mid;
             }
             end = hi;
         }
-        counts[c] = (int32_t)(end - k);
+        runlen[r] = (int32_t)(end - k);
+    }
+
+    // final values (in batch mode the grid lookups load, so they come
+    // before any store too)
+    uint32_t gk[kRunChunks];
+#pragma unroll
+    for (int r = 0; r < kRunChunks; ++r) {
+        gk[r] = kv[r].x;
+        const uint32_t c = kv[r].x;
+        int32_t lc = (int32_t)c;
+        GridDev g = f.g;
+        if (BATCH) {
+            const SysDev &sd = f.sys[sys_of_cell(f.sys, f.nsys, c)];
+            lc = (int32_t)(c - (uint32_t)sd.cell_base);
+            g = sd.g;
+        }
+        const int32_t ix = lc % g.nx, iy = (lc / g.nx) % g.ny, iz = lc / (g.nx * g.ny);
+        kv[r].x = (uint32_t)lc;
+        pv[r] = make_float4(__builtin_fmaf(-(float)ix, g.w, pv[r].x - g.ox),
+                            __builtin_fmaf(-(float)iy, g.w, pv[r].y - g.oy),
+                            __builtin_fmaf(-(float)iz, g.w, pv[r].z - g.oz), pv[r].w);
+    }
+
+    // stores: the final arrays, and each run's count at its start
+#pragma unroll
+    for (int r = 0; r < kRunChunks; ++r) {
+        const int64_t e = wbase + r * 64 + lane;
+        if (e >= n) continue;
+        f.cell[e] = (int32_t)kv[r].x;
+        f.perm[e] = (int32_t)kv[r].y;
+        f.xs[e] = pv[r].x;
+        f.ys[e] = pv[r].y;
+        f.zs[e] = pv[r].z;
+        f.ws[e] = pv[r].w;
+        if (mine[r]) f.counts[gk[r]] = runlen[r];
     }
 }
+
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -657,6 +667,8 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
                          const GridDev &g0, hipStream_t stream)
 {
     const bool batch = nsys > 0;
+    PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks((nc + 3) / 4, kBlock)), dim3(kBlock), 0, stream,
+              cells->counts, nc, 0);
     if (n > 0) {
         // 8-bit digits needed to sort keys 0 .. nc-1
         int bits = 1;
@@ -679,59 +691,43 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
         a.dtot = cells->dtot;
         a.err = cells->d_err;
         for (int p = 0; p < passes; ++p) {
-            const bool first = p == 0, last = p == passes - 1;
+            const bool first = p == 0;
             const int src = (p + 1) & 1, dst = p & 1;
             a.shift = p * kRadixBits;
-            a.key_in = cells->skey[src];
-            a.idx_in = cells->sidx[src];
+            a.kv_in = cells->skv[src];
             a.p_in = cells->sp[src];
-            a.gkey_out = cells->skey[dst];
-            if (last) {
-                a.key_out = (uint32_t *)cells->cell;
-                a.idx_out = cells->perm;
-                a.x_out = cells->xs;
-                a.y_out = cells->ys;
-                a.z_out = cells->zs;
-                a.w_out = cells->ws;
-            } else {
-                a.key_out = cells->skey[dst];
-                a.idx_out = cells->sidx[dst];
-                a.p_out = cells->sp[dst];
-                a.x_out = a.y_out = a.z_out = a.w_out = nullptr;
-            }
+            a.kv_out = cells->skv[dst];
+            a.p_out = cells->sp[dst];
             const dim3 grid(ntiles), block(kBlock);
             if (first && batch) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, true>), grid, block, 0, stream, a);
             else if (first) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, false>), grid, block, 0, stream, a);
             else PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<false, false>), grid, block, 0, stream, a);
             PI_LAUNCH(ctx, "k_digit_scan", k_digit_scan, dim3(kRadix), dim3(kBlock), 0, stream, cells->hist, ntiles,
                       cells->dtot);
-#define PI_SCATTER(F, L, B) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<F, L, B>), grid, dim3(kSBlock), 0, stream, a)
-            if (batch) {
-                if (first && last) PI_SCATTER(true, true, true);
-                else if (first) PI_SCATTER(true, false, true);
-                else if (last) PI_SCATTER(false, true, true);
-                else PI_SCATTER(false, false, true);
-            } else {
-                if (first && last) PI_SCATTER(true, true, false);
-                else if (first) PI_SCATTER(true, false, false);
-                else if (last) PI_SCATTER(false, true, false);
-                else PI_SCATTER(false, false, false);
-            }
-#undef PI_SCATTER
+            const dim3 sblock(kSBlock);
+            if (first && batch) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<true, true>), grid, sblock, 0, stream, a);
+            else if (first) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<true, false>), grid, sblock, 0, stream, a);
+            else PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<false, false>), grid, sblock, 0, stream, a);
         }
-    }
-    PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks((nc + 3) / 4, kBlock)), dim3(kBlock), 0, stream, cells->counts, nc,
-              0);
-    if (n > 0) {
-        // global ids of the sorted particles: the cell array itself for one
-        // system, the extra key copy of the last pass for a batch
-        int bits = 1;
-        while (bits < 31 && ((int64_t)1 << bits) < nc) ++bits;
-        const int passes = (bits + kRadixBits - 1) / kRadixBits;
-        const uint32_t *gkey = batch ? cells->skey[(passes - 1) & 1] : (const uint32_t *)cells->cell;
+        FinalArgs f;
+        memset(&f, 0, sizeof(f));
+        f.n = (int32_t)n;
+        f.g = g0;
+        f.sys = d_sys;
+        f.nsys = nsys;
+        f.kv = cells->skv[(passes - 1) & 1];
+        f.p = cells->sp[(passes - 1) & 1];
+        f.cell = cells->cell;
+        f.perm = cells->perm;
+        f.xs = cells->xs;
+        f.ys = cells->ys;
+        f.zs = cells->zs;
+        f.ws = cells->ws;
+        f.counts = cells->counts;
         const int64_t waves = (n + 64 * kRunChunks - 1) / (64 * kRunChunks);
-        PI_LAUNCH(ctx, "k_count_runs", k_count_runs, dim3(nblocks(waves * 64, kBlock)), dim3(kBlock), 0, stream,
-                  (int32_t)n, gkey, cells->counts);
+        const dim3 fgrid(nblocks(waves * 64, kBlock));
+        if (batch) PI_LAUNCH(ctx, "k_finalize", k_finalize<true>, fgrid, dim3(kBlock), 0, stream, f);
+        else PI_LAUNCH(ctx, "k_finalize", k_finalize<false>, fgrid, dim3(kBlock), 0, stream, f);
     }
     launch_scan(ctx, cells->counts, nc, cells->offsets, cells->offsets + nc, cells->max_per_cell, cells->tile_sum,
                 cells->tile_max, stream);

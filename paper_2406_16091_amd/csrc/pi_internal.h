@@ -71,8 +71,7 @@ struct pi_cells {
     int32_t *cell;      // [cap_n] cell of sorted slot
     float *xs, *ys, *zs, *ws;   // [cap_n]
     // radix-sort ping-pong buffers: key, original index, x, y, z, w
-    uint32_t *skey[2];
-    int32_t *sidx[2];
+    uint2 *skv[2];       // radix ping-pong records (cell id, original index)
     float4 *sp[2];       // payload records (x, y, z, w)
     int32_t *dtot;       // radix digit totals (256)
     // radix histograms (digit-major, 256 x sort tiles) and their scan scratch
