@@ -169,6 +169,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         d.g.nx = g.dims[0];
         d.g.ny = g.dims[1];
         d.g.nz = g.dims[2];
+        grid_set_magic(d.g);
         const int64_t nc = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
         cb += nc;
         // organisation of this system

@@ -605,7 +605,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f)
             lc = (int32_t)(c - (uint32_t)sd.cell_base);
             g = sd.g;
         }
-        const int32_t ix = lc % g.nx, iy = (lc / g.nx) % g.ny, iz = lc / (g.nx * g.ny);
+        const int32_t iz = (int32_t)div_by((uint32_t)lc, g.mxy);
+        const int32_t rem = lc - iz * g.nx * g.ny;
+        const int32_t iy = (int32_t)div_by((uint32_t)rem, g.mx);
+        const int32_t ix = rem - iy * g.nx;
         kv[r].x = (uint32_t)lc;
         pv[r] = make_float4(__builtin_fmaf(-(float)ix, g.w, pv[r].x - g.ox),
                             __builtin_fmaf(-(float)iy, g.w, pv[r].y - g.oy),
@@ -762,6 +765,7 @@ extern "C" pi_status pi_bin(pi_ctx *ctx, pi_cells *cells, const float *x, const 
     g.ny = grid->dims[1];
     g.nz = grid->dims[2];
     g.pad = 0;
+    grid_set_magic(g);
 
     return pi_bin_systems(ctx, cells, x, y, z, w, n, nc, 0, nullptr, g, stream);
 }

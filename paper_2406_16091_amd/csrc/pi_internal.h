@@ -135,7 +135,32 @@ struct GridDev {
     float w;        // cell width
     int32_t nx, ny, nz;
     int32_t pad;
+    // multipliers for dividing a cell id by nx and by nx * ny (div_by)
+    uint64_t mx, mxy;
 };
+
+// Multiplier M for exact division n / d of any n < 2^31 by a fixed d < 2^31
+// (division by a constant as a multiply-high): with M = ceil(2^62 / d) * 4,
+// floor(n / d) = mulhi64(n, M).  Since d * M / 4 = 2^62 + e with 0 <= e < d,
+// n M / 2^64 = n / d + n e / (d 2^62), and n e < 2^62 keeps the floor.
+// d = 1 is marked by M = 0.
+inline uint64_t div_magic(int64_t d)
+{
+    if (d <= 1) return 0;
+    const unsigned __int128 one = 1;
+    return (uint64_t)(((one << 62) + (unsigned __int128)(d - 1)) / (unsigned __int128)d) << 2;
+}
+
+inline void grid_set_magic(GridDev &g)
+{
+    g.mx = div_magic(g.nx);
+    g.mxy = div_magic((int64_t)g.nx * g.ny);
+}
+
+__device__ __forceinline__ uint32_t div_by(uint32_t n, uint64_t m)
+{
+    return m ? (uint32_t)__umul64hi((uint64_t)n, m) : n;
+}
 
 // One axis of the cell decision: t = (x - o) / w in float32 (IEEE), inside
 // iff 0 <= t < n, index floor(t).  NaN fails the test.

@@ -111,6 +111,47 @@ __device__ __forceinline__ void reduce_invariants(const SweepArgs &a, uint32_t s
     }
 }
 
+// The same reduction through LDS for workgroups that have a free LDS area of
+// at least 12 KB (256 lanes x 6 doubles): every lane parks its partials, and
+// the first wavefront alone folds the 256 entries (4 per lane, then a wave
+// butterfly), so the other wavefronts skip the butterfly.  The order of the
+// additions is fixed, so the result is deterministic.
+__device__ __forceinline__ void reduce_invariants_lds(const SweepArgs &a, uint32_t slot, long long cnt, double nx,
+                                                      double ny, double nz, double sc, double rs, double *park)
+{
+    const int t = threadIdx.x;
+    __syncthreads(); // the area may still be read by other lanes
+    park[0 * kBlock + t] = (double)cnt;
+    park[1 * kBlock + t] = nx;
+    park[2 * kBlock + t] = ny;
+    park[3 * kBlock + t] = nz;
+    park[4 * kBlock + t] = sc;
+    park[5 * kBlock + t] = rs;
+    __syncthreads();
+    if (t >= 64) return;
+    double v[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const double *col = park + q * kBlock;
+        v[q] = (col[t] + col[t + 64]) + (col[t + 128] + col[t + 192]);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] += __shfl_xor(v[q], o, 64);
+    }
+    if (t == 0) {
+        InvPartial p;
+        p.pairs = (long long)v[0];
+        p.net[0] = v[1];
+        p.net[1] = v[2];
+        p.net[2] = v[3];
+        p.scale = v[4];
+        p.rho_sum = v[5];
+        p.pad[0] = p.pad[1] = 0.0;
+        a.partials[slot] = p;
+    }
+}
+
 template <int PREC, bool INV>
 __device__ __forceinline__ void target_invariants(const Target<PREC, INV> &T, float wi, long long &cnt,
                                                   double &nx, double &ny, double &nz, double &sc, double &rs)
@@ -627,7 +668,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             }
         }
     }
-    if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
+    static_assert(sizeof(float4) * CAP >= sizeof(double) * 6 * kBlock, "the staging area parks the partials");
+    if (INV) reduce_invariants_lds(a, lb, icnt, inx, iny, inz, isc, irs, reinterpret_cast<double *>(sp));
 }
 
 // FP64 reduction of the per-workgroup partials in two fixed-order stages
@@ -799,10 +841,12 @@ const TileCfg kTiles[] = {
     {6, 4, 4, 4, 1536, PI_SWEEP_SUBBOX},
     {7, 4, 4, 2, 1536, PI_SWEEP_SUBBOX},
     {8, 16, 4, 3, 768, PI_SWEEP_SUBBOX},
+    {10, 7, 7, 5, 768, PI_SWEEP_SUBBOX},
 };
 
 constexpr int kFifo = 8;
 constexpr int kStreamId = 9; // organisation id of the FIFO stream sweep
+constexpr int kMaxOrgId = 10; // organisation ids are 0 .. kMaxOrgId
 
 // nblk: in single-system mode computed here from the grid; in batch mode
 // given (the sum of the systems' tile counts).
@@ -832,6 +876,7 @@ void launch_sweep(pi_ctx *ctx, int tile_id, const SweepArgs &a, hipStream_t s, u
     case 6: launch_tile<4, 4, 4, 1536, PREC, INV, BATCH>(ctx, "k_sweep_tile<4,4,4>", a, s, nblk); break;
     case 7: launch_tile<4, 4, 2, 1536, PREC, INV, BATCH>(ctx, "k_sweep_tile<4,4,2>", a, s, nblk); break;
     case 8: launch_tile<16, 4, 3, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<16,4,3>", a, s, nblk); break;
+    case 10: launch_tile<7, 7, 5, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<7,7,5>", a, s, nblk); break;
     case kStreamId:
         if (!BATCH) {
             nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
@@ -993,7 +1038,7 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, hipStream_t s)
     ctx->timing_on = 0;
     int best = -1;
     float best_ms = 0.f;
-    for (int cand = 0; cand <= kStreamId; ++cand) {
+    for (int cand = 0; cand <= kMaxOrgId; ++cand) {
         unsigned nblk = 0;
         float ms = 0.f;
         bool ok = true;
