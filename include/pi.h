@@ -110,7 +110,11 @@ pi_status pi_bin(pi_ctx *ctx, pi_cells *cells,
                  int64_t n, const pi_grid *grid, pi_stream stream);
 
 /* Device pointers into a binned system (valid until the next pi_bin or
- * pi_cells_destroy on it).  All arrays are int32/float32 in device memory. */
+ * pi_cells_destroy on it).  All arrays are int32/float32 in device memory.
+ * The library keeps the sorted coordinates as one 16-byte record per slot;
+ * the first view taken after a pi_bin writes the four arrays xs, ys, zs, ws
+ * from those records, asynchronously on the stream of that pi_bin, so read
+ * them once that stream's work has completed. */
 typedef struct pi_cells_view {
     int64_t n;                /* particles binned by the last pi_bin */
     int64_t n_cells;
@@ -123,7 +127,7 @@ typedef struct pi_cells_view {
     const int32_t *max_per_cell;    /* [1] */
 } pi_cells_view;
 
-pi_status pi_cells_get_view(const pi_cells *cells, pi_cells_view *out);
+pi_status pi_cells_get_view(pi_cells *cells, pi_cells_view *out);
 
 /* Accumulation precision of the sweep. */
 #define PI_PREC_COMPENSATED 0 /* FP32 terms with an error-free h^2 - r^2 for
@@ -253,7 +257,7 @@ pi_status pi_batch_run(pi_ctx *ctx, pi_batch *batch, int32_t nsys, const pi_syst
  * `cell` are local to their system; counts/offsets are indexed by global
  * cell = cell_base[s] + local cell).  cell_base (host, max_sys entries) may
  * be NULL. */
-pi_status pi_batch_get_view(const pi_batch *batch, pi_cells_view *out, int64_t *cell_base, int32_t max_sys);
+pi_status pi_batch_get_view(pi_batch *batch, pi_cells_view *out, int64_t *cell_base, int32_t max_sys);
 /* pi_sync for a batch. */
 pi_status pi_batch_sync(pi_ctx *ctx, pi_batch *batch, pi_stream stream);
 

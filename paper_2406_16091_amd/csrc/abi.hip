@@ -248,6 +248,7 @@ static int list_buffers(pi_cells *c, BufRef *out)
     add((void **)&c->ys, BUF_N, 4);
     add((void **)&c->zs, BUF_N, 4);
     add((void **)&c->ws, BUF_N, 4);
+    add((void **)&c->xyzw, BUF_N, 16);
     for (int b = 0; b < 2; ++b) {
         add((void **)&c->skv[b], BUF_N, 8);
         add((void **)&c->sp[b], BUF_N, 16);
@@ -335,10 +336,12 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     return PI_OK;
 }
 
-extern "C" pi_status pi_cells_get_view(const pi_cells *c, pi_cells_view *v)
+extern "C" pi_status pi_cells_get_view(pi_cells *c, pi_cells_view *v)
 {
     if (!c || !v) return PI_EINVAL;
     if (!c->binned) return PI_ESTATE;
+    const pi_status st = pi_split_records(c->ctx, c);
+    if (st != PI_OK) return st;
     v->n = c->n;
     v->n_cells = c->n_cells;
     v->grid = c->grid;

@@ -278,7 +278,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     return PI_OK;
 }
 
-extern "C" pi_status pi_batch_get_view(const pi_batch *b, pi_cells_view *out, int64_t *cell_base, int32_t max_sys)
+extern "C" pi_status pi_batch_get_view(pi_batch *b, pi_cells_view *out, int64_t *cell_base, int32_t max_sys)
 {
     if (!b || !out) return PI_EINVAL;
     pi_status st = pi_cells_get_view(b->cells, out);

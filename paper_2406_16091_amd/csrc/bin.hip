@@ -509,7 +509,10 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
 // at the start of a run finds the run's end as the next run start, from the
 // chunks' start masks (wave ballots), or past the wavefront's range by
 // galloping over the sorted ids (only the last run of a range can cross it).
-constexpr int kRunChunks = 8;
+#ifndef PI_FINAL_CHUNKS
+#define PI_FINAL_CHUNKS 2
+#endif
+constexpr int kRunChunks = PI_FINAL_CHUNKS; // 64-id chunks per wavefront
 
 struct FinalArgs {
     int32_t n;
@@ -519,7 +522,7 @@ struct FinalArgs {
     const uint2 *kv;   // sorted (global cell id, original index)
     const float4 *p;   // sorted payload
     int32_t *cell, *perm;
-    float *xs, *ys, *zs, *ws;
+    float4 *xyzw;      // sorted cell-relative (x, y, z, w)
     int32_t *counts;   // indexed by global cell id
 };
 
@@ -622,14 +625,24 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f)
         if (e >= n) continue;
         f.cell[e] = (int32_t)kv[r].x;
         f.perm[e] = (int32_t)kv[r].y;
-        f.xs[e] = pv[r].x;
-        f.ys[e] = pv[r].y;
-        f.zs[e] = pv[r].z;
-        f.ws[e] = pv[r].w;
+        f.xyzw[e] = pv[r];
         if (mine[r]) f.counts[gk[r]] = runlen[r];
     }
 }
 
+
+// The sorted coordinates as four arrays, from the records (in order).
+__global__ __launch_bounds__(kBlock) void k_split_records(int32_t n, const float4 *__restrict__ p, float *xs,
+                                                          float *ys, float *zs, float *ws)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n) return;
+    const float4 q = p[e];
+    xs[e] = q.x;
+    ys[e] = q.y;
+    zs[e] = q.z;
+    ws[e] = q.w;
+}
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -722,16 +735,14 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
         f.p = cells->sp[(passes - 1) & 1];
         f.cell = cells->cell;
         f.perm = cells->perm;
-        f.xs = cells->xs;
-        f.ys = cells->ys;
-        f.zs = cells->zs;
-        f.ws = cells->ws;
+        f.xyzw = cells->xyzw;
         f.counts = cells->counts;
         const int64_t waves = (n + 64 * kRunChunks - 1) / (64 * kRunChunks);
         const dim3 fgrid(nblocks(waves * 64, kBlock));
         if (batch) PI_LAUNCH(ctx, "k_finalize", k_finalize<true>, fgrid, dim3(kBlock), 0, stream, f);
         else PI_LAUNCH(ctx, "k_finalize", k_finalize<false>, fgrid, dim3(kBlock), 0, stream, f);
     }
+    cells->soa_stale = n > 0;
     launch_scan(ctx, cells->counts, nc, cells->offsets, cells->offsets + nc, cells->max_per_cell, cells->tile_sum,
                 cells->tile_max, stream);
     PI_CHECK_HIP(hipGetLastError());
@@ -768,4 +779,16 @@ extern "C" pi_status pi_bin(pi_ctx *ctx, pi_cells *cells, const float *x, const 
     grid_set_magic(g);
 
     return pi_bin_systems(ctx, cells, x, y, z, w, n, nc, 0, nullptr, g, stream);
+}
+
+pi_status pi_split_records(pi_ctx *ctx, pi_cells *cells)
+{
+    if (!cells->soa_stale) return PI_OK;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    const int64_t n = cells->n;
+    PI_LAUNCH(ctx, "k_split_records", k_split_records, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, cells->last_stream,
+              (int32_t)n, (const float4 *)cells->xyzw, cells->xs, cells->ys, cells->zs, cells->ws);
+    PI_CHECK_HIP(hipGetLastError());
+    cells->soa_stale = false;
+    return PI_OK;
 }

@@ -70,6 +70,8 @@ struct pi_cells {
     int32_t *perm;      // [cap_n] stable sorted order
     int32_t *cell;      // [cap_n] cell of sorted slot
     float *xs, *ys, *zs, *ws;   // [cap_n]
+    float4 *xyzw;       // [cap_n] sorted cell-relative (x, y, z, w) records
+    bool soa_stale;     // xs .. ws not yet written from the records of the last bin
     // radix-sort ping-pong buffers: key, original index, x, y, z, w
     uint2 *skv[2];       // radix ping-pong records (cell id, original index)
     float4 *sp[2];       // payload records (x, y, z, w)
@@ -203,6 +205,10 @@ pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDe
 
 // Host-side binning of a concatenated set of systems (bin.hip): one radix
 // sort over global cell ids; sorted arrays hold local cell ids.
+// Write the SoA arrays xs, ys, zs, ws of a binned system from its records
+// (bin.hip), on the stream of its last binning.
+pi_status pi_split_records(pi_ctx *ctx, pi_cells *cells);
+
 pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const float *y, const float *z,
                          const float *w, int64_t n_total, int64_t cells_total, int32_t nsys,
                          const SysDev *d_sys, const GridDev &g0, hipStream_t stream);

@@ -28,7 +28,7 @@ struct SweepArgs {
     const int32_t *off;
     const int32_t *cell;
     const int32_t *perm;
-    const float *xs, *ys, *zs, *ws;
+    const float4 *p4; // sorted cell-relative (x, y, z, w), one record per slot
     int64_t nc;
     int32_t n;
     int32_t nx, ny, nz;
@@ -188,8 +188,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
     if (active) {
         const int32_t c = a.cell[k];
         const int32_t ix = c % a.nx, iy = (c / a.nx) % a.ny, iz = c / (a.nx * a.ny);
-        const float xi = a.xs[k], yi = a.ys[k], zi = a.zs[k];
-        wi = a.ws[k];
+        const float4 pk = a.p4[k];
+        const float xi = pk.x, yi = pk.y, zi = pk.z;
+        wi = pk.w;
         const float W = a.k.w;
         for (int dz = -1; dz <= 1; ++dz) {
             const int32_t cz = iz + dz;
@@ -206,10 +207,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
                     const float tx = xi - (float)dx * W;
                     const int32_t j0 = a.off[rb + cx], j1 = a.off[rb + cx + 1];
                     for (int32_t j = j0; j < j1; ++j) {
-                        const float ddx = tx - a.xs[j], ddy = ty - a.ys[j], ddz = tz - a.zs[j];
+                        const float4 s = a.p4[j];
+                        const float ddx = tx - s.x, ddy = ty - s.y, ddz = tz - s.z;
                         const float t = sq_dist(ddx, ddy, ddz);
                         if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k))
-                            T.accept(ddx, ddy, ddz, t, a.ws[j], a.k);
+                            T.accept(ddx, ddy, ddz, t, s.w, a.k);
                     }
                 }
             }
@@ -231,17 +233,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
 // about ten instructions, the evaluation of an accepted pair about a
 // hundred, and at several particles per cell some lane of a wavefront
 // accepts on nearly every step.  Nothing is staged, so the organisation
-// works at any occupancy.  Each lane first writes its target's non-empty
-// row segments (neighbour rows in canonical (dz, dy) order, the reach test
-// of the tiles trimming the outer cells) into an LDS table as global index
-// ranges with their inner cell boundaries, from which the x shift of a
-// source follows.
+// works at any occupancy.  Each lane walks its neighbour rows in canonical
+// (dz, dy) order, a row being one global index range (its up to three cells,
+// the outer ones trimmed by the reach test of the tiles) whose inner cell
+// boundaries give each source's x shift.  The next row's range is loaded
+// when the lane enters the current one, so a row change does not wait for
+// memory, and the LDS holds only the queues (high occupancy).
 template <int Q, int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
 {
     static_assert((Q & (Q - 1)) == 0, "FIFO depth must be a power of two");
-    __shared__ int4 segtab[9][kBlock];             // [e0, e1) dx = -1, [e1, e2) dx = 0, [e2, e3) dx = +1
-    __shared__ uint8_t segcode[9][kBlock];         // row: (dy + 1) << 2 | (dz + 1)
     __shared__ int32_t fifo[kBlock / 64][Q][64];   // accepted source: sorted index
     __shared__ uint8_t fcode[kBlock / 64][Q][64];  // its shifts: (dx + 1) | row << 2
 
@@ -260,49 +261,59 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
     const float W = a.k.w;
     const float reach2 = a.k.reach2;
     float xi = 0.f, yi = 0.f, zi = 0.f, wi = 0.f;
-    int nseg = 0;
+    int32_t ix = 0, iy = 0, iz = 0;
     if (active) {
         const int32_t c = a.cell[k];
-        const int32_t ix = c % a.nx, iy = (c / a.nx) % a.ny, iz = c / (a.nx * a.ny);
-        xi = a.xs[k];
-        yi = a.ys[k];
-        zi = a.zs[k];
-        wi = a.ws[k];
-        const float gxl = xi * xi, gxr = (W - xi) * (W - xi);
-        const float gyl = yi * yi, gyr = (W - yi) * (W - yi);
-        const float gzl = zi * zi, gzr = (W - zi) * (W - zi);
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int32_t cz = iz + dz;
-            if (cz < 0 || cz >= a.nz) continue;
-            const float gz = dz < 0 ? gzl : (dz > 0 ? gzr : 0.f);
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int32_t cy = iy + dy;
-                if (cy < 0 || cy >= a.ny) continue;
-                const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + gz;
-                if (gyz >= reach2) continue; // the whole row is out of reach
-                const bool left = ix > 0 && gxl + gyz < reach2;
-                const bool right = ix + 1 < a.nx && gxr + gyz < reach2;
-                const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz) + ix;
-                const int32_t e1 = a.off[rb], e2 = a.off[rb + 1];
-                const int32_t e0 = left ? a.off[rb - 1] : e1;
-                const int32_t e3 = right ? a.off[rb + 2] : e2;
-                if (e3 > e0) {
-                    segtab[nseg][tid] = make_int4(e0, e1, e2, e3);
-                    segcode[nseg][tid] = (uint8_t)(((dy + 1) << 2) | (dz + 1));
-                    ++nseg;
-                }
-            }
-        }
+        ix = c % a.nx;
+        iy = (c / a.nx) % a.ny;
+        iz = c / (a.nx * a.ny);
+        const float4 pk = a.p4[k];
+        xi = pk.x;
+        yi = pk.y;
+        zi = pk.z;
+        wi = pk.w;
     }
+    const float gxl = xi * xi, gxr = (W - xi) * (W - xi);
+    const float gyl = yi * yi, gyr = (W - yi) * (W - yi);
+    const float gzl = zi * zi, gzr = (W - zi) * (W - zi);
     // target coordinate shifted into the frame of a neighbour cell:
     // x - dx W for dx = -1, 0, 1 (the same roundings as the subtraction)
     const float xm = xi + W, xp = xi - W, ym = yi + W, yp = yi - W, zm = zi + W, zp = zi - W;
     auto sel = [](int q, float m, float o, float p) { return q == 0 ? m : (q == 1 ? o : p); };
 
+    // rows q = 0 .. 8: dz = q / 3 - 1, dy = q % 3 - 1; fetch_row finds the
+    // next usable row from qn on and starts the loads of its range
+    int qn = 0;
+    bool nvalid = false;
+    int32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+    int nrow = 0;
+    auto fetch_row = [&]() {
+        nvalid = false;
+        while (qn < 9) {
+            const int dz = qn / 3 - 1, dy = qn % 3 - 1;
+            ++qn;
+            const int32_t cz = iz + dz, cy = iy + dy;
+            if (cz < 0 || cz >= a.nz || cy < 0 || cy >= a.ny) continue;
+            const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + (dz < 0 ? gzl : (dz > 0 ? gzr : 0.f));
+            if (gyz >= reach2) continue; // the whole row is out of reach
+            const bool left = ix > 0 && gxl + gyz < reach2;
+            const bool right = ix + 1 < a.nx && gxr + gyz < reach2;
+            const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz) + ix;
+            n1 = a.off[rb];
+            n2 = a.off[rb + 1];
+            n0 = left ? a.off[rb - 1] : n1;
+            n3 = right ? a.off[rb + 2] : n2;
+            nrow = ((dy + 1) << 2) | (dz + 1);
+            nvalid = true;
+            break;
+        }
+    };
+    if (active) fetch_row();
+
     Target<PREC, INV> T;
     int32_t *myq = &fifo[wid][0][lane];
     uint8_t *myc = &fcode[wid][0][lane];
-    int seg = 0, qh = 0, qc = 0, row = 0;
+    int qh = 0, qc = 0, row = 0;
     int32_t j = 0, jend = 0, b1 = 0, b2 = 0;
     float ty = 0.f, tz = 0.f;
     auto pop = [&]() {
@@ -310,28 +321,30 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
         const int c = myc[qh * 64];
         qh = (qh + 1) & (Q - 1);
         --qc;
-        const float ddx = sel(c & 3, xm, xi, xp) - a.xs[jj];
-        const float ddy = sel((c >> 4) & 3, ym, yi, yp) - a.ys[jj];
-        const float ddz = sel((c >> 2) & 3, zm, zi, zp) - a.zs[jj];
-        T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), a.ws[jj], a.k);
+        const float4 s = a.p4[jj];
+        const float ddx = sel(c & 3, xm, xi, xp) - s.x;
+        const float ddy = sel((c >> 4) & 3, ym, yi, yp) - s.y;
+        const float ddz = sel((c >> 2) & 3, zm, zi, zp) - s.z;
+        T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
     };
     while (true) {
-        if (j >= jend && seg < nseg) {
-            const int4 sg = segtab[seg][tid];
-            row = segcode[seg][tid];
-            ++seg;
-            j = sg.x;
-            b1 = sg.y;
-            b2 = sg.z;
-            jend = sg.w;
+        if (j >= jend && nvalid) {
+            // enter the prefetched row, and prefetch the one after it
+            j = n0;
+            b1 = n1;
+            b2 = n2;
+            jend = n3;
+            row = nrow;
             ty = sel(row >> 2, ym, yi, yp);
             tz = sel(row & 3, zm, zi, zp);
+            fetch_row();
         }
         const bool have = j < jend;
-        if (!__any(have)) break;
+        if (!__any(have || nvalid)) break;
         if (have) {
             const int dxc = j < b1 ? 0 : (j < b2 ? 1 : 2);
-            const float ddx = sel(dxc, xm, xi, xp) - a.xs[j], ddy = ty - a.ys[j], ddz = tz - a.zs[j];
+            const float4 s = a.p4[j];
+            const float ddx = sel(dxc, xm, xi, xp) - s.x, ddy = ty - s.y, ddz = tz - s.z;
             const float t = sq_dist(ddx, ddy, ddz);
             bool acc = t < a.k.lo;
             if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
@@ -414,10 +427,11 @@ __device__ __forceinline__ void walk_cells_global(const SweepArgs &a, int32_t k,
                 const float tx = xi - (float)dx * W;
                 const int32_t j0 = a.off[rb + cx], j1 = a.off[rb + cx + 1];
                 for (int32_t j = j0; j < j1; ++j) {
-                    const float ddx = tx - a.xs[j], ddy = ty - a.ys[j], ddz = tz - a.zs[j];
+                    const float4 s = a.p4[j];
+                    const float ddx = tx - s.x, ddy = ty - s.y, ddz = tz - s.z;
                     const float t = sq_dist(ddx, ddy, ddz);
                     if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k))
-                        T.accept(ddx, ddy, ddz, t, a.ws[j], a.k);
+                        T.accept(ddx, ddy, ddz, t, s.w, a.k);
                 }
             }
         }
@@ -519,12 +533,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             const int32_t y = y0 + lo % TY, z = z0 + lo / TY;
             const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
             Target<PREC, INV> T;
-            walk_cells_global(a, k, ix, y, z, a.xs[k], a.ys[k], a.zs[k], T);
+            const float4 pk = a.p4[k];
+            walk_cells_global(a, k, ix, y, z, pk.x, pk.y, pk.z, T);
             write_target(a, k, T);
             if (INV) {
                 long long c1;
                 double a1, a2, a3, a4, a5;
-                target_invariants(T, a.ws[k], c1, a1, a2, a3, a4, a5);
+                target_invariants(T, pk.w, c1, a1, a2, a3, a4, a5);
                 icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
             }
         }
@@ -553,9 +568,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         }
         const int32_t g = gstart[lo] + (f - rstart[lo]);
         const int32_t cx = a.cell[g] - rbase[lo];
-        sp[f] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, a.xs[g]),
-                            __builtin_fmaf((float)(lo % HY), W, a.ys[g]),
-                            __builtin_fmaf((float)(lo / HY), W, a.zs[g]), a.ws[g]);
+        const float4 q = a.p4[g];
+        sp[f] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, q.x), __builtin_fmaf((float)(lo % HY), W, q.y),
+                            __builtin_fmaf((float)(lo / HY), W, q.z), q.w);
     }
     __syncthreads();
 
@@ -582,7 +597,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             const float4 p = sp[self];
             xt = p.x; yt = p.y; zt = p.z; wi = p.w;
             // cell-relative position of the target, for the reach test
-            const float xc = a.xs[k], yc = a.ys[k], zc = a.zs[k];
+            const float4 pk = a.p4[k];
+            const float xc = pk.x, yc = pk.y, zc = pk.z;
             const float gxl = xc * xc, gxr = (W - xc) * (W - xc);
             const float gyl = yc * yc, gyr = (W - yc) * (W - yc);
             const float gzl = zc * zc, gzr = (W - zc) * (W - zc);
@@ -988,10 +1004,7 @@ pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDe
     a.off = cells->offsets;
     a.cell = cells->cell;
     a.perm = cells->perm;
-    a.xs = cells->xs;
-    a.ys = cells->ys;
-    a.zs = cells->zs;
-    a.ws = cells->ws;
+    a.p4 = cells->xyzw;
     a.n = (int32_t)cells->n;
     a.orig_order = o.order == PI_ORDER_ORIGINAL;
     a.rho = rho;
@@ -1122,10 +1135,7 @@ extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t
         a.off = cells->offsets;
         a.cell = cells->cell;
         a.perm = cells->perm;
-        a.xs = cells->xs;
-        a.ys = cells->ys;
-        a.zs = cells->zs;
-        a.ws = cells->ws;
+        a.p4 = cells->xyzw;
         a.nc = cells->n_cells;
         a.n = (int32_t)n;
         a.nx = cells->grid.dims[0];
@@ -1182,10 +1192,7 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
     a.off = cells->offsets;
     a.cell = cells->cell;
     a.perm = cells->perm;
-    a.xs = cells->xs;
-    a.ys = cells->ys;
-    a.zs = cells->zs;
-    a.ws = cells->ws;
+    a.p4 = cells->xyzw;
     a.nc = cells->n_cells;
     a.n = (int32_t)n;
     a.nx = cells->grid.dims[0];
