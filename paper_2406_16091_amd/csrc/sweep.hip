@@ -860,7 +860,10 @@ const TileCfg kTiles[] = {
     {10, 7, 7, 5, 768, PI_SWEEP_SUBBOX},
 };
 
-constexpr int kFifo = 8;
+#ifndef PI_FIFO_DEPTH
+#define PI_FIFO_DEPTH 4
+#endif
+constexpr int kFifo = PI_FIFO_DEPTH; // pair queue entries per lane
 constexpr int kStreamId = 9; // organisation id of the FIFO stream sweep
 constexpr int kMaxOrgId = 10; // organisation ids are 0 .. kMaxOrgId
 
@@ -1036,8 +1039,10 @@ uint64_t tune_key(int prec, int64_t n, double ppc, bool batch)
 
 // Time every compiled organisation on this system (second of two runs,
 // without invariants) and return the fastest; the outputs in `a` are
-// overwritten.
-int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, hipStream_t s)
+// overwritten.  The static default is timed first and a later organisation
+// displaces the current best only when it is faster by more than 5%, so that
+// near-ties (within run-to-run noise) resolve the same way every time.
+int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, hipStream_t s)
 {
     SweepArgs a = a0;
     a.partials = nullptr;
@@ -1051,7 +1056,9 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, hipStream_t s)
     ctx->timing_on = 0;
     int best = -1;
     float best_ms = 0.f;
-    for (int cand = 0; cand <= kMaxOrgId; ++cand) {
+    for (int i = -1; i <= kMaxOrgId; ++i) {
+        const int cand = i < 0 ? first : i;
+        if (i >= 0 && cand == first) continue;
         unsigned nblk = 0;
         float ms = 0.f;
         bool ok = true;
@@ -1061,7 +1068,7 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, hipStream_t s)
             ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
                  hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
         }
-        if (ok && (best < 0 || ms < best_ms)) {
+        if (ok && (best < 0 || ms < 0.95f * best_ms)) {
             best = cand;
             best_ms = ms;
         }
@@ -1088,7 +1095,7 @@ pi_status tuned_tile(pi_ctx *ctx, const SweepArgs &a, int prec, int64_t n, doubl
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PI_OK;
-    const int best = time_candidates(ctx, a, prec, s);
+    const int best = time_candidates(ctx, a, prec, *tile, s);
     if (best < 0) return PI_EDEVICE;
     std::lock_guard<std::mutex> g(t->mu);
     t->choice[key] = best;
