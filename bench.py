@@ -50,16 +50,16 @@ def algorithmic_bytes(name: str, n: int, nc: int, orig_order: bool) -> float:
     written once, at 4 bytes per int32/float32 element."""
     if name == "k_fill_i32":
         return 4.0 * nc
-    if name == "k_bin_count":
-        return 12.0 * n + 8.0 * n + 8.0 * nc          # x,y,z in; cell,slot out; counts RMW
-    if name in ("k_scan_reduce",):
+    if name == "k_radix_hist":
+        return 4.0 * n                                # one key per particle (12 B on the first pass)
+    if name == "k_radix_scatter":
+        return 48.0 * n                               # records in and out (40 B on the first pass)
+    if name == "k_count_runs":
+        return 4.0 * n + 4.0 * nc                     # sorted ids in, counts out
+    if name == "k_scan_reduce":
         return 4.0 * nc
     if name == "k_scan_down":
         return 8.0 * nc                               # counts in, offsets out
-    if name == "k_bin_scatter":
-        return 12.0 * n + 4.0 * nc                    # cell,slot in, perm_u out; offsets
-    if name == "k_bin_finalize":
-        return 48.0 * n + 4.0 * nc                    # perm_u,cell_in,x,y,z,w in; 6 arrays out
     if name.startswith("k_sweep"):
         return 40.0 * n + 4.0 * nc + (4.0 * n if orig_order else 0.0)
     return 0.0

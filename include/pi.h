@@ -206,7 +206,11 @@ pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream);
  * and reuses the fastest for that class afterwards (per context).  Tuning
  * runs the sweep once per candidate and waits for the stream.  In
  * PI_TUNE_STATIC mode (or with PI_AUTOTUNE=off in the environment) AUTO uses
- * a fixed rule on the mean occupancy instead.
+ * a fixed rule on the mean occupancy instead: the 6x6x6 sub-box while its
+ * staged halo is expected to fit in LDS (mean + 6 standard deviations of a
+ * Poisson count, up to about 1.2 particles per cell), then 4x4x4 (up to
+ * about 6), then no LDS.  The same fit test picks the tile of PI_SWEEP_PENCIL
+ * and PI_SWEEP_SUBBOX when tile[] is zero.
  */
 #define PI_TUNE_STATIC 0
 #define PI_TUNE_TIMED  1

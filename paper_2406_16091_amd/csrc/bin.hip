@@ -278,9 +278,16 @@ struct SortArgs {
     // index) and the payload (x, y, z, w)
     const uint2 *kv_in;
     const float4 *p_in;
-    // every pass writes records of the same two kinds (ping-pong buffers)
+    // every pass but the last writes records of the same two kinds
+    // (ping-pong buffers)
     uint2 *kv_out;
     float4 *p_out;
+    // the last pass writes the final arrays in sorted order: local cell id,
+    // original index, cell-relative (x, y, z) and w; in batch mode also the
+    // global cell ids (for the run count)
+    int32_t *cell, *perm;
+    float4 *xyzw;
+    uint32_t *ids;
     const int32_t *gbase; // per digit: exclusive scan of its per-tile counts
     const int32_t *dtot;  // per digit: total count
     int32_t *hist;
@@ -344,9 +351,32 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t valid)
     return m;
 }
 
+// Local cell id of global key `key` and the position relative to that
+// cell's low corner, fma(-i, w, x - o) per axis (the cell coordinates come
+// from the id by two exact multiply-high divisions).
+template <bool BATCH>
+__device__ __forceinline__ uint32_t to_cell_relative(const SortArgs &a, uint32_t key, float &x, float &y, float &z)
+{
+    GridDev g = a.g;
+    uint32_t lc = key;
+    if (BATCH) {
+        const SysDev &sd = a.sys[sys_of_cell(a.sys, a.nsys, key)];
+        lc = key - (uint32_t)sd.cell_base;
+        g = sd.g;
+    }
+    const int32_t iz = (int32_t)div_by(lc, g.mxy);
+    const int32_t rem = (int32_t)lc - iz * g.nx * g.ny;
+    const int32_t iy = (int32_t)div_by((uint32_t)rem, g.mx);
+    const int32_t ix = rem - iy * g.nx;
+    x = __builtin_fmaf(-(float)ix, g.w, x - g.ox);
+    y = __builtin_fmaf(-(float)iy, g.w, y - g.oy);
+    z = __builtin_fmaf(-(float)iz, g.w, z - g.oz);
+    return lc;
+}
+
 // (LDS allows two workgroups, i.e. 4 wavefronts per SIMD: registers are
 // budgeted for that, so the prefetched tile stays in registers)
-template <bool FIRST, bool BATCH>
+template <bool FIRST, bool LAST, bool BATCH>
 __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_radix_scatter(SortArgs a)
 {
     constexpr int W = kSBlock / 64;      // wavefronts per block
@@ -480,84 +510,97 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
     __syncthreads();
 
     // 4. the (key, index) records, then the payload, reordered through LDS
-    //    and written out in runs
-    uint2 *lb8 = reinterpret_cast<uint2 *>(lbuf);
+    //    and written out in runs; the last pass writes the final arrays
+    //    instead (local cell id and index, cell-relative payload)
+    if (LAST && BATCH) {
+        uint4 *lb16 = reinterpret_cast<uint4 *>(lbuf);
 #pragma unroll
-    for (int r = 0; r < kSItems; ++r) lb8[pos[r]] = make_uint2(key[r], (uint32_t)pidx[r]);
-    __syncthreads();
+        for (int r = 0; r < kSItems; ++r) {
+            const uint32_t lc = to_cell_relative<BATCH>(a, key[r], px[r], py[r], pz[r]);
+            lb16[pos[r]] = make_uint4(lc, (uint32_t)pidx[r], key[r], 0u);
+        }
+        __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kSItems; ++k) {
-        const int p = tid + k * kSBlock;
-        if (p < nvalid) a.kv_out[dst[k]] = lb8[p];
+        for (int k = 0; k < kSItems; ++k) {
+            const int p = tid + k * kSBlock;
+            if (p < nvalid) {
+                const uint4 c = lb16[p];
+                a.cell[dst[k]] = (int32_t)c.x;
+                a.perm[dst[k]] = (int32_t)c.y;
+                a.ids[dst[k]] = c.z;
+            }
+        }
+    } else {
+        uint2 *lb8 = reinterpret_cast<uint2 *>(lbuf);
+#pragma unroll
+        for (int r = 0; r < kSItems; ++r) {
+            const uint32_t k0 = LAST ? to_cell_relative<BATCH>(a, key[r], px[r], py[r], pz[r]) : key[r];
+            lb8[pos[r]] = make_uint2(k0, (uint32_t)pidx[r]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSItems; ++k) {
+            const int p = tid + k * kSBlock;
+            if (p < nvalid) {
+                const uint2 c = lb8[p];
+                if (LAST) {
+                    a.cell[dst[k]] = (int32_t)c.x;
+                    a.perm[dst[k]] = (int32_t)c.y;
+                } else {
+                    a.kv_out[dst[k]] = c;
+                }
+            }
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSItems; ++r) lbuf[pos[r]] = make_float4(px[r], py[r], pz[r], pw[r]);
     __syncthreads();
+    float4 *pout = LAST ? a.xyzw : a.p_out;
 #pragma unroll
     for (int k = 0; k < kSItems; ++k) {
         const int p = tid + k * kSBlock;
-        if (p < nvalid) a.p_out[dst[k]] = lbuf[p];
+        if (p < nvalid) pout[dst[k]] = lbuf[p];
     }
 }
 
-// After the last pass: the final arrays in sorted order (local cell id,
-// original index, cell-relative position fma(-i, w, x - o), weight), read
-// and written in order, and the per-cell counts from the runs of equal ids
-// -- one plain store per occupied cell and no atomics (counts start at
-// zero).  A wavefront takes 8 consecutive chunks of 64 ids at once; the lane
-// at the start of a run finds the run's end as the next run start, from the
-// chunks' start masks (wave ballots), or past the wavefront's range by
-// galloping over the sorted ids (only the last run of a range can cross it).
-#ifndef PI_FINAL_CHUNKS
-#define PI_FINAL_CHUNKS 2
+// After the last pass: the per-cell counts from the runs of equal ids in
+// the sorted global cell ids -- one plain store per occupied cell and no
+// atomics (counts start at zero).  A wavefront takes a few consecutive
+// chunks of 64 ids at once; the lane at the start of a run finds the run's
+// end as the next run start, from the chunks' start masks (wave ballots), or
+// past the wavefront's range by galloping over the sorted ids (only the last
+// run of a range can cross it).
+#ifndef PI_COUNT_CHUNKS
+#define PI_COUNT_CHUNKS 4
 #endif
-constexpr int kRunChunks = PI_FINAL_CHUNKS; // 64-id chunks per wavefront
+constexpr int kRunChunks = PI_COUNT_CHUNKS; // 64-id chunks per wavefront
 
-struct FinalArgs {
-    int32_t n;
-    GridDev g;
-    const SysDev *sys; // batch mode
-    int32_t nsys;
-    const uint2 *kv;   // sorted (global cell id, original index)
-    const float4 *p;   // sorted payload
-    int32_t *cell, *perm;
-    float4 *xyzw;      // sorted cell-relative (x, y, z, w)
-    int32_t *counts;   // indexed by global cell id
-};
-
-template <bool BATCH>
-__global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f)
+__global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t *__restrict__ ids,
+                                                       int32_t *__restrict__ counts)
 {
     const int lane = threadIdx.x & 63;
     const int64_t wbase = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * (64 * kRunChunks);
-    if (wbase >= f.n) return; // uniform over the wavefront
-    const int32_t n = f.n;
+    if (wbase >= n) return; // uniform over the wavefront
     const int64_t last = (int64_t)n - 1;
     const int64_t wend = wbase + 64 * kRunChunks; // first id past the range
-    uint2 kv[kRunChunks];
-    float4 pv[kRunChunks];
+    uint32_t id[kRunChunks];
 #pragma unroll
-    for (int r = 0; r < kRunChunks; ++r) {
-        const int64_t e = min(wbase + r * 64 + lane, last);
-        kv[r] = f.kv[e];
-        pv[r] = f.p[e];
-    }
-    const uint32_t before = f.kv[wbase > 0 ? wbase - 1 : 0].x; // id before the range
+    for (int r = 0; r < kRunChunks; ++r) id[r] = ids[min(wbase + r * 64 + lane, last)];
+    const uint32_t before = ids[wbase > 0 ? wbase - 1 : 0]; // id before the range
 
-    // counts first (all loads, including the rare galloping ones, before
-    // any store: a load waits for every earlier memory operation of the
-    // wavefront): run starts of every chunk, then each run's length
+    // run starts of every chunk, then each run's length (every load, the
+    // rare galloping ones included, before the first store)
     uint64_t starts[kRunChunks];
     bool mine[kRunChunks];
     int32_t runlen[kRunChunks];
 #pragma unroll
     for (int r = 0; r < kRunChunks; ++r) {
         const int64_t k = wbase + r * 64 + lane;
-        const uint32_t up = __shfl_up(kv[r].x, 1);
-        const uint32_t p63 = r > 0 ? __shfl(kv[r > 0 ? r - 1 : 0].x, 63) : before;
+        const uint32_t up = __shfl_up(id[r], 1);
+        const uint32_t p63 = r > 0 ? __shfl(id[r > 0 ? r - 1 : 0], 63) : before;
         const uint32_t prev = lane == 0 ? p63 : up;
-        mine[r] = k < n && (k == 0 || prev != kv[r].x);
+        mine[r] = k < n && (k == 0 || prev != id[r]);
         starts[r] = __ballot(mine[r]);
     }
 #pragma unroll
@@ -565,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f)
         runlen[r] = 0;
         if (!mine[r]) continue;
         const int64_t k = wbase + r * 64 + lane;
-        const uint32_t c = kv[r].x;
+        const uint32_t c = id[r];
         int64_t end = -1;
         const uint64_t above = starts[r] & ~((2ull << lane) - 1ull); // later starts in this chunk
         if (above) {
@@ -579,7 +622,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f)
             // the run reaches the end of the range: gallop, then bisect, for
             // the first id past it (ids are sorted, so it is the first != c)
             int64_t lo = wend - 1, hi = wend, step = 64; // id lo == c
-            while (hi < n && f.kv[hi].x == c) {
+            while (hi < n && ids[hi] == c) {
                 lo = hi;
                 hi = hi + step;
                 step *= 2;
@@ -587,49 +630,16 @@ __global__ __launch_bounds__(kBlock) void k_finalize(FinalArgs f)
             if (hi > n) hi = n;
             while (hi - lo > 1) {
                 const int64_t mid = lo + (hi - lo) / 2;
-                if (f.kv[mid].x == c) lo = mid; else hi = mid;
+                if (ids[mid] == c) lo = mid; else hi = mid;
             }
             end = hi;
         }
         runlen[r] = (int32_t)(end - k);
     }
-
-    // final values (in batch mode the grid lookups load, so they come
-    // before any store too)
-    uint32_t gk[kRunChunks];
 #pragma unroll
-    for (int r = 0; r < kRunChunks; ++r) {
-        gk[r] = kv[r].x;
-        const uint32_t c = kv[r].x;
-        int32_t lc = (int32_t)c;
-        GridDev g = f.g;
-        if (BATCH) {
-            const SysDev &sd = f.sys[sys_of_cell(f.sys, f.nsys, c)];
-            lc = (int32_t)(c - (uint32_t)sd.cell_base);
-            g = sd.g;
-        }
-        const int32_t iz = (int32_t)div_by((uint32_t)lc, g.mxy);
-        const int32_t rem = lc - iz * g.nx * g.ny;
-        const int32_t iy = (int32_t)div_by((uint32_t)rem, g.mx);
-        const int32_t ix = rem - iy * g.nx;
-        kv[r].x = (uint32_t)lc;
-        pv[r] = make_float4(__builtin_fmaf(-(float)ix, g.w, pv[r].x - g.ox),
-                            __builtin_fmaf(-(float)iy, g.w, pv[r].y - g.oy),
-                            __builtin_fmaf(-(float)iz, g.w, pv[r].z - g.oz), pv[r].w);
-    }
-
-    // stores: the final arrays, and each run's count at its start
-#pragma unroll
-    for (int r = 0; r < kRunChunks; ++r) {
-        const int64_t e = wbase + r * 64 + lane;
-        if (e >= n) continue;
-        f.cell[e] = (int32_t)kv[r].x;
-        f.perm[e] = (int32_t)kv[r].y;
-        f.xyzw[e] = pv[r];
-        if (mine[r]) f.counts[gk[r]] = runlen[r];
-    }
+    for (int r = 0; r < kRunChunks; ++r)
+        if (mine[r]) counts[id[r]] = runlen[r];
 }
-
 
 // The sorted coordinates as four arrays, from the records (in order).
 __global__ __launch_bounds__(kBlock) void k_split_records(int32_t n, const float4 *__restrict__ p, float *xs,
@@ -706,41 +716,46 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
         a.gbase = cells->hist;
         a.dtot = cells->dtot;
         a.err = cells->d_err;
+        a.cell = cells->cell;
+        a.perm = cells->perm;
+        a.xyzw = cells->xyzw;
+        // the last pass writes no records, so its output record buffer is
+        // free: in batch mode it takes the sorted global ids
+        uint32_t *ids = batch ? reinterpret_cast<uint32_t *>(cells->skv[(passes - 1) & 1])
+                              : reinterpret_cast<uint32_t *>(cells->cell);
+        a.ids = ids;
         for (int p = 0; p < passes; ++p) {
-            const bool first = p == 0;
+            const bool first = p == 0, last = p == passes - 1;
             const int src = (p + 1) & 1, dst = p & 1;
             a.shift = p * kRadixBits;
             a.kv_in = cells->skv[src];
             a.p_in = cells->sp[src];
-            a.kv_out = cells->skv[dst];
-            a.p_out = cells->sp[dst];
+            a.kv_out = last ? nullptr : cells->skv[dst];
+            a.p_out = last ? nullptr : cells->sp[dst];
             const dim3 grid(ntiles), block(kBlock);
             if (first && batch) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, true>), grid, block, 0, stream, a);
             else if (first) PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<true, false>), grid, block, 0, stream, a);
             else PI_LAUNCH(ctx, "k_radix_hist", (k_radix_hist<false, false>), grid, block, 0, stream, a);
             PI_LAUNCH(ctx, "k_digit_scan", k_digit_scan, dim3(kRadix), dim3(kBlock), 0, stream, cells->hist, ntiles,
                       cells->dtot);
-            const dim3 sblock(kSBlock);
-            if (first && batch) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<true, true>), grid, sblock, 0, stream, a);
-            else if (first) PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<true, false>), grid, sblock, 0, stream, a);
-            else PI_LAUNCH(ctx, "k_radix_scatter", (k_radix_scatter<false, false>), grid, sblock, 0, stream, a);
+            const dim3 sb(kSBlock);
+            const char *nm = "k_radix_scatter";
+            if (first && last) {
+                if (batch) PI_LAUNCH(ctx, nm, (k_radix_scatter<true, true, true>), grid, sb, 0, stream, a);
+                else PI_LAUNCH(ctx, nm, (k_radix_scatter<true, true, false>), grid, sb, 0, stream, a);
+            } else if (first) {
+                if (batch) PI_LAUNCH(ctx, nm, (k_radix_scatter<true, false, true>), grid, sb, 0, stream, a);
+                else PI_LAUNCH(ctx, nm, (k_radix_scatter<true, false, false>), grid, sb, 0, stream, a);
+            } else if (last) {
+                if (batch) PI_LAUNCH(ctx, nm, (k_radix_scatter<false, true, true>), grid, sb, 0, stream, a);
+                else PI_LAUNCH(ctx, nm, (k_radix_scatter<false, true, false>), grid, sb, 0, stream, a);
+            } else {
+                PI_LAUNCH(ctx, nm, (k_radix_scatter<false, false, false>), grid, sb, 0, stream, a);
+            }
         }
-        FinalArgs f;
-        memset(&f, 0, sizeof(f));
-        f.n = (int32_t)n;
-        f.g = g0;
-        f.sys = d_sys;
-        f.nsys = nsys;
-        f.kv = cells->skv[(passes - 1) & 1];
-        f.p = cells->sp[(passes - 1) & 1];
-        f.cell = cells->cell;
-        f.perm = cells->perm;
-        f.xyzw = cells->xyzw;
-        f.counts = cells->counts;
         const int64_t waves = (n + 64 * kRunChunks - 1) / (64 * kRunChunks);
-        const dim3 fgrid(nblocks(waves * 64, kBlock));
-        if (batch) PI_LAUNCH(ctx, "k_finalize", k_finalize<true>, fgrid, dim3(kBlock), 0, stream, f);
-        else PI_LAUNCH(ctx, "k_finalize", k_finalize<false>, fgrid, dim3(kBlock), 0, stream, f);
+        PI_LAUNCH(ctx, "k_count_runs", k_count_runs, dim3(nblocks(waves * 64, kBlock)), dim3(kBlock), 0, stream,
+                  (int32_t)n, (const uint32_t *)ids, cells->counts);
     }
     cells->soa_stale = n > 0;
     launch_scan(ctx, cells->counts, nc, cells->offsets, cells->offsets + nc, cells->max_per_cell, cells->tile_sum,

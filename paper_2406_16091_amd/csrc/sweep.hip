@@ -934,9 +934,29 @@ void launch_sweep_prec(pi_ctx *ctx, int prec, bool inv, int tile_id, const Sweep
     }
 }
 
+const TileCfg &tile_cfg(int id)
+{
+    for (const TileCfg &t : kTiles)
+        if (t.id == id) return t;
+    return kTiles[0];
+}
+
+// Whether tile `id`'s staged halo is expected to fit its LDS capacity at
+// mean occupancy ppc: the halo count is about Poisson, so its mean plus six
+// standard deviations must stay within the capacity (a tile that overflows
+// still gives the same results, from the slower global walk).
+bool halo_fits(int id, double ppc)
+{
+    const TileCfg &t = tile_cfg(id);
+    const double m = (double)(t.tx + 2) * (t.ty + 2) * (t.tz + 2) * ppc;
+    return m + 6.0 * sqrt(m) <= (double)t.cap;
+}
+
+// Static rule: the 6x6x6 sub-box while its halo fits (up to about 1.2 per
+// cell), then 4x4x4 (up to about 6), then no LDS.
 int pick_tile_default(double ppc)
 {
-    return ppc <= 2.0 ? 5 : (ppc <= 5.0 ? 6 : 0);
+    return halo_fits(5, ppc) ? 5 : (halo_fits(6, ppc) ? 6 : 0);
 }
 
 } // namespace
@@ -965,8 +985,8 @@ int pi_pick_tile(const pi_interact_opts &o, double ppc)
                 if (t.sweep == o.sweep && t.tx == o.tile[0] && t.ty == o.tile[1] && t.tz == o.tile[2]) return t.id;
             return -1;
         }
-        if (o.sweep == PI_SWEEP_PENCIL) return ppc <= 2.0 ? 1 : (ppc <= 5.0 ? 2 : 3);
-        return ppc <= 2.0 ? 5 : (ppc <= 5.0 ? 6 : 7);
+        if (o.sweep == PI_SWEEP_PENCIL) return halo_fits(1, ppc) ? 1 : (halo_fits(2, ppc) ? 2 : 3);
+        return halo_fits(5, ppc) ? 5 : (halo_fits(6, ppc) ? 6 : 7);
     }
     return pick_tile_default(ppc);
 }
