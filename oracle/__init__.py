@@ -44,13 +44,21 @@ def build(force: bool = True) -> str:
 
 _lib = None
 
+# A test that plants mistakes in the oracle (tests/test_oracle_mutants.py)
+# compiles altered copies of oracle.c elsewhere and points this variable at
+# one of them, to show that the pins fail on it.
+_OVERRIDE = "ORACLE_LIBRARY"
+
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get(_OVERRIDE)
+        if not path:
+            path = _LIB
+            if not os.path.exists(path):
+                build()
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         lib.oracle_kernel.argtypes = [ctypes.c_double, ctypes.c_double, P, P]

@@ -248,6 +248,7 @@ def test_cutoff_is_strict_exact(oracle_lib):
     w = np.ones(5, np.float32)
     _, s = _run(x, y, z, w, (8, 8, 8), rc, rc)
     assert s.count.tolist() == [0, 0, 0, 0, 0]
+    assert oracle.brute(x, y, z, w, rc).count.tolist() == [0, 0, 0, 0, 0]
     # one lattice step closer on each: included
     u = 2.0 ** -20
     x2 = x.copy()
@@ -255,6 +256,7 @@ def test_cutoff_is_strict_exact(oracle_lib):
     x2[3] = np.float32(1.625 - u)
     _, s2 = _run(x2, y, z, w, (8, 8, 8), rc, rc)
     assert s2.count.tolist() == [1, 1, 1, 1, 0]
+    assert oracle.brute(x2, y, z, w, rc).count.tolist() == [1, 1, 1, 1, 0]
 
 
 def test_predicate_exact_on_lattice(oracle_lib):
@@ -319,12 +321,16 @@ def test_cells_match_brute(oracle_lib, case):
 
 # ---------------------------------------------------------------- definitions
 
-def test_binning_matches_independent_definition(oracle_lib):
+@pytest.mark.parametrize("shift", [0.0, -3.0])
+def test_binning_matches_independent_definition(oracle_lib, shift):
     s = synth.box_system(5000, 9, seed=12, lattice_log2=18)
-    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    sh = np.float32(shift)
+    x, y, z = (s.x + sh, s.y + 2 * sh, s.z + 3 * sh)   # exact: lattice values
+    origin = (float(sh), float(2 * sh), float(3 * sh))
+    b = oracle.bin_particles(x, y, z, s.w, origin, s.dims, s.cell_w, s.rc)
     # cell: float32 floor((x - o) / w), X fastest
-    ix, iy, iz = (np.floor((v - np.float32(0)) / np.float32(s.cell_w)).astype(np.int64)
-                  for v in (s.x, s.y, s.z))
+    ix, iy, iz = (np.floor((v - np.float32(o)) / np.float32(s.cell_w)).astype(np.int64)
+                  for v, o in ((x, origin[0]), (y, origin[1]), (z, origin[2])))
     cell = ix + s.dims[0] * (iy + s.dims[1] * iz)
     assert (b.cell == cell).all()
     counts = np.bincount(cell, minlength=s.n_cells)
@@ -333,8 +339,10 @@ def test_binning_matches_independent_definition(oracle_lib):
     perm = np.argsort(cell, kind="stable")
     assert (b.perm == perm).all()
     assert b.max_per_cell == counts.max()
-    for rel, v, i in ((b.xs, s.x, ix), (b.ys, s.y, iy), (b.zs, s.z, iz)):
-        want = (v.astype(np.float64) - i * float(s.cell_w))[perm].astype(np.float32)
+    # cell-relative coordinates: exact in float64, and exactly representable
+    # in float32 on this lattice
+    for rel, v, o, i in ((b.xs, x, origin[0], ix), (b.ys, y, origin[1], iy), (b.zs, z, origin[2], iz)):
+        want = (v.astype(np.float64) - o - i * float(s.cell_w))[perm].astype(np.float32)
         assert (rel == want).all()
     assert (b.ws == s.w[perm]).all()
 
