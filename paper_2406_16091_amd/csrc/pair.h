@@ -60,12 +60,36 @@ __device__ __forceinline__ float sq_dist(float dx, float dy, float dz)
     return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
 }
 
-// Kernel value W(r) and W'(r)/r of an accepted pair.
-template <int PREC>
+// Kernel value W(r) and W'(r)/r of an accepted pair.  With SELECT both
+// pieces of the spline are evaluated and one is chosen, with the same
+// values as the branch: where a wavefront evaluates queued pairs together it
+// almost always holds pairs on both sides of q = 1/2, so the branch would
+// run both anyway (and the merge after it costs register copies).  The
+// unchosen piece may be infinite (the outer one at r = 0); it is not used.
+template <int PREC, bool SELECT = false>
 __device__ __forceinline__ void bspline_terms(float dx, float dy, float dz, float t, const KernelConst &k,
                                               float &W, float &Fr)
 {
     const float r = __builtin_amdgcn_sqrtf(t);
+    if (SELECT) {
+        const float q = r * k.inv_h;
+        const float w_in = k.sigma * __builtin_fmaf(q * q, __builtin_fmaf(6.0f, q, -6.0f), 1.0f);
+        const float f_in = k.sig_h2 * __builtin_fmaf(18.0f, q, -12.0f);
+        float omq;
+        if (PREC == PI_PREC_PLAIN) {
+            omq = fmaxf(1.0f - r * k.inv_h, 0.0f);
+        } else {
+            const float D = h2_minus_d2(dx, dy, dz, k);
+            omq = D * __builtin_amdgcn_rcpf(k.h * (k.h + r));
+        }
+        const float omq2 = omq * omq;
+        const float w_out = k.two_sigma * omq2 * omq;
+        const float f_out = -k.six_sig_h * omq2 * __builtin_amdgcn_rsqf(t);
+        const bool inner = t <= k.hh_quarter;
+        W = inner ? w_in : w_out;
+        Fr = inner ? f_in : f_out;
+        return;
+    }
     if (t <= k.hh_quarter) {
         const float q = r * k.inv_h;
         W = k.sigma * __builtin_fmaf(q * q, __builtin_fmaf(6.0f, q, -6.0f), 1.0f);
@@ -158,10 +182,11 @@ struct Target {
         if (t < k.hi && inside_cutoff(dx, dy, dz, t, k)) accept(dx, dy, dz, t, wj, k);
     }
 
+    template <bool SELECT = false>
     __device__ __forceinline__ void accept(float dx, float dy, float dz, float t, float wj, const KernelConst &k)
     {
         float W, Fr;
-        bspline_terms<PREC>(dx, dy, dz, t, k, W, Fr);
+        bspline_terms<PREC, SELECT>(dx, dy, dz, t, k, W, Fr);
         const float f = wj * Fr;
         acc.add(wj * W, f * dx, f * dy, f * dz);
         count += 1;

@@ -438,6 +438,12 @@ __device__ __forceinline__ void walk_cells_global(const SweepArgs &a, int32_t k,
     }
 }
 
+// Staging-area slots [s0, s1) as a packed byte range: start | end << 16.
+__device__ __forceinline__ uint32_t seg_bytes(int32_t s0, int32_t s1)
+{
+    return ((uint32_t)s0 * (uint32_t)sizeof(float4)) | (((uint32_t)s1 * (uint32_t)sizeof(float4)) << 16);
+}
+
 template <int TX, int TY, int TZ, int CAP, int Q, int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx, int32_t nty)
 {
@@ -446,12 +452,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     constexpr int TR = TY * TZ;  // target rows
     static_assert(R <= 64 && TR <= 64, "row tables are scanned by one wavefront");
     static_assert((Q & (Q - 1)) == 0, "FIFO depth must be a power of two");
-    static_assert(CAP < 4096, "segment table packs LDS indices in 12 bits");
+    static_assert(CAP * 16 < 65536, "segment table packs byte offsets in 16 bits");
     __shared__ float4 sp[CAP];
-    __shared__ int32_t fifo[kBlock / 64][Q][64]; // accepted source: LDS index
-    // LDS ranges of the row segments (start | end << 12); the target's own
-    // row is cut in two around the target itself, so at most 10
-    __shared__ int32_t segtab[10][kBlock];
+    // accepted source: its byte offset in the staging area
+    __shared__ uint32_t fifo[kBlock / 64][Q][64];
+    // staging-area byte ranges of the row segments (start | end << 16); the
+    // target's own row is cut in two around the target itself, so at most 10
+    __shared__ uint32_t segtab[10][kBlock];
     __shared__ int32_t cs[R][HX + 1];
     __shared__ int32_t rstart[R + 1];
     __shared__ int32_t gstart[R];
@@ -575,7 +582,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     __syncthreads();
 
     // 4. targets, in rounds of one per thread
-    int32_t *myq = &fifo[wid][0][lane];
+    uint32_t *myq = &fifo[wid][0][lane];
+    const char *spb = reinterpret_cast<const char *>(sp);
+    auto staged = [&](uint32_t byte) { return *reinterpret_cast<const float4 *>(spb + byte); };
     const float reach2 = a.k.reach2; // conservative squared reach
     for (int32_t f0 = 0; f0 < ntarget; f0 += kBlock) {
         const int32_t f = f0 + tid;
@@ -620,59 +629,69 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                     const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
                     if (dy == 0 && dz == 0) {
                         // s0 <= self < s1: the parts before and after it
-                        if (self > s0) segtab[nseg++][tid] = s0 | (self << 12);
-                        if (s1 > self + 1) segtab[nseg++][tid] = (self + 1) | (s1 << 12);
+                        if (self > s0) segtab[nseg++][tid] = seg_bytes(s0, self);
+                        if (s1 > self + 1) segtab[nseg++][tid] = seg_bytes(self + 1, s1);
                     } else if (s1 > s0) {
-                        segtab[nseg][tid] = s0 | (s1 << 12);
+                        segtab[nseg][tid] = seg_bytes(s0, s1);
                         ++nseg;
                     }
                 }
             }
         }
         Target<PREC, INV> T;
-        int seg = 0, qh = 0, qc = 0;
-        int32_t j = 0, jend = 0;
+        int seg = 0;
+        uint32_t j = 0, jend = 0; // byte offsets in the staging area
+        // Queue positions count entries pushed (qt) and popped (qh) in units
+        // of one queue row (64 lanes x 4 bytes), so that (position & kQMask)
+        // is the byte offset of the entry in this lane's column; qlim = qh + Q
+        // rows marks a full queue.
+        constexpr uint32_t kRow = 64u * (uint32_t)sizeof(uint32_t);
+        constexpr uint32_t kQMask = (uint32_t)(Q - 1) * kRow;
+        uint32_t qt = 0, qh = 0, qlim = (uint32_t)Q * kRow;
+        char *myqb = reinterpret_cast<char *>(myq);
         // Evaluate the oldest queued pair of this lane: the differences are
         // recomputed from the same operands, so they are bit-identical to the
         // ones the test used.
         auto pop = [&]() {
-            const int32_t e = myq[qh * 64];
-            qh = (qh + 1) & (Q - 1);
-            --qc;
-            const float4 s = sp[e];
+            const uint32_t e = *reinterpret_cast<const uint32_t *>(myqb + (qh & kQMask));
+            qh += kRow;
+            qlim += kRow;
+            const float4 s = staged(e);
             const float ddx = xt - s.x, ddy = yt - s.y, ddz = zt - s.z;
-            T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
+            T.template accept<true>(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
         };
         while (true) {
             if (j >= jend && seg < nseg) {
-                const int32_t sg = segtab[seg][tid];
+                const uint32_t sg = segtab[seg][tid];
                 ++seg;
-                j = sg & 4095;
-                jend = sg >> 12;
+                j = sg & 0xffffu;
+                jend = sg >> 16;
             }
             const bool have = j < jend;
             if (!__any(have)) break;
             if (have) {
-                const float4 s = sp[j];
+                const float4 s = staged(j);
                 const float ddx = xt - s.x, ddy = yt - s.y, ddz = zt - s.z;
                 const float t = sq_dist(ddx, ddy, ddz);
                 // surely inside below lo; the thin band [lo, hi) takes the
                 // exact test (inside_cutoff, unrolled to keep the step short)
                 bool acc = t < a.k.lo;
-                if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
-                // the slot after the queue's tail is free (qc < Q at every
-                // step), so it is written always and kept if accepted
-                myq[((qh + qc) & (Q - 1)) * 64] = j;
-                qc += acc ? 1 : 0;
-                ++j;
+                const bool below_hi = t < a.k.hi;
+                if (below_hi && !acc) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
+                // the slot after the queue's tail is free (the queue is
+                // never full at this point), so it is written always and
+                // kept if accepted
+                *reinterpret_cast<uint32_t *>(myqb + (qt & kQMask)) = j;
+                qt += acc ? kRow : 0u;
+                j += (uint32_t)sizeof(float4);
             }
-            if (__any(qc == Q)) {
-                if (qc > 0) pop();
+            if (__any(qt == qlim)) {
+                if (qt != qh) pop();
             }
         }
         // drain: as many rounds as the fullest queue holds (a uniform count)
-        for (int left = wave_max(qc); left > 0; --left) {
-            if (qc > 0) pop();
+        for (int left = wave_max((int)((qt - qh) / kRow)); left > 0; --left) {
+            if (qt != qh) pop();
         }
         if (tgt) {
             write_target(a, k, T);
