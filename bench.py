@@ -54,12 +54,8 @@ def algorithmic_bytes(name: str, n: int, nc: int, orig_order: bool) -> float:
         return 4.0 * n                                # one key per particle (12 B on the first pass)
     if name == "k_radix_scatter":
         return 48.0 * n                               # records in and out (40 B on the first pass)
-    if name == "k_count_runs":
-        return 4.0 * n + 4.0 * nc                     # sorted ids in, counts out
-    if name == "k_scan_reduce":
-        return 4.0 * nc
-    if name == "k_scan_down":
-        return 8.0 * nc                               # counts in, offsets out
+    if name == "k_cell_ranges":
+        return 4.0 * n + 8.0 * nc                     # sorted ids in; counts and offsets out
     if name.startswith("k_sweep"):
         return 40.0 * n + 4.0 * nc + (4.0 * n if orig_order else 0.0)
     return 0.0

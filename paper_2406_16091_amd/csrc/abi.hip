@@ -228,7 +228,7 @@ extern "C" pi_status pi_cells_create(pi_ctx *ctx, pi_cells **out)
 
 // Every device buffer of a pi_cells object except the error word, with the
 // capacity class it is sized by.
-enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_TILES, BUF_HIST, BUF_PARTIALS, BUF_RADIX };
+enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_HIST, BUF_PARTIALS, BUF_RADIX };
 
 struct BufRef {
     void **ptr;
@@ -254,8 +254,6 @@ static int list_buffers(pi_cells *c, BufRef *out)
         add((void **)&c->sp[b], BUF_N, 16);
     }
     add((void **)&c->hist, BUF_HIST, 4);
-    add((void **)&c->tile_sum, BUF_TILES, 4);
-    add((void **)&c->tile_max, BUF_TILES, 4);
     add((void **)&c->partials, BUF_PARTIALS, 64);
     add((void **)&c->dtot, BUF_RADIX, 4);
     return k;
@@ -303,7 +301,6 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     const int64_t cap_c = grow_c ? grow(n_cells < 64 ? 64 : n_cells, c->cap_cells) : c->cap_cells;
     const int64_t sort_tiles = (cap_n + 4095) / 4096 + 1;
     const int64_t cap_hist = 256 * sort_tiles;
-    const int64_t cap_tiles = (cap_c + 4095) / 4096 + 1;
     const int64_t cap_parts = 2 * (cap_c + cap_n / 64) + 64;
     BufRef b[40];
     const int nb = list_buffers(c, b);
@@ -315,7 +312,6 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
         case BUF_HIST: count = cap_hist; redo = grow_n; break;
         case BUF_CELLS: count = cap_c; redo = grow_c; break;
         case BUF_CELLS1: count = cap_c + 1; redo = grow_c; break;
-        case BUF_TILES: count = cap_tiles; redo = grow_c; break;
         case BUF_PARTIALS: count = cap_parts; redo = grow_n || grow_c; break;
         case BUF_RADIX: count = 256; redo = false; break;
         }
@@ -330,7 +326,6 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     }
     c->cap_n = cap_n;
     c->cap_cells = cap_c;
-    c->cap_tiles = cap_tiles;
     c->cap_hist = cap_hist;
     c->cap_partials = cap_parts;
     return PI_OK;

@@ -12,17 +12,18 @@
 // Per pass, in launch order on the caller's stream:
 //   k_radix_hist     per 4096-key tile: LDS histogram of the pass's digit,
 //                    stored digit-major (digit * tiles + tile)
-//   k_scan_*         exclusive scan of the histogram -> where each
-//                    (digit, tile) run starts in the pass's output
+//   k_digit_scan     exclusive scan of each digit's per-tile counts (one
+//                    workgroup per digit, wave64 DPP scans) -> where each
+//                    (digit, tile) run starts among that digit's keys
 //   k_radix_scatter  per tile: stable rank of every key among the tile's
 //                    keys with the same digit (wave64 ballots + per-wave
 //                    counters), the tile reordered by digit in LDS, then
 //                    written out in runs (key, index, x, y, z, w)
 // The first pass computes the cell id from the position (float32 decision,
 // see axis_index); the last pass writes the final arrays perm, cell and the
-// cell-relative coordinates.  Counts then come from the runs of equal ids in
-// the sorted cell ids (wave ballots, one store per cell), and the offsets and
-// M_C from the same DPP scan.
+// cell-relative coordinates.  Counts, offsets and M_C then come from the
+// runs of equal ids in the sorted cell ids (k_cell_ranges: wave ballots,
+// each count and offset written once).
 #include <string.h>
 
 #include "pi_internal.h"
@@ -30,8 +31,8 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems; // 4096 entries per scan tile
+constexpr int kScanItems = 16;                 // histogram entries per thread and round (digit scan)
+constexpr int kScanTile = kBlock * kScanItems; // 4096 entries per round
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kBlock * kSortItems; // 4096 keys per sort tile
 constexpr int kRadixBits = 8;
@@ -51,143 +52,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t *p, int64_t n, int3
         *reinterpret_cast<int4 *>(p + i) = make_int4(v, v, v, v);
     } else {
         for (int64_t q = i; q < n; ++q) p[q] = v;
-    }
-}
-
-// ------------------------------------------------------------- scan (DPP)
-
-// Block-wide sum and max of one value per thread (256 threads, 4 waves).
-__device__ __forceinline__ void block_sum_max(int32_t &s, int32_t &m, int32_t *lds)
-{
-    s = wave_sum(s);
-    m = wave_max(m);
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        lds[wid] = s;
-        lds[4 + wid] = m;
-    }
-    __syncthreads();
-    s = lds[0] + lds[1] + lds[2] + lds[3];
-    m = max(max(lds[4], lds[5]), max(lds[6], lds[7]));
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t *__restrict__ in, int64_t nc,
-                                                        int32_t *__restrict__ tile_sum,
-                                                        int32_t *__restrict__ tile_max)
-{
-    __shared__ int32_t lds[8];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    int32_t s = 0, m = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t c = base + j * kBlock + threadIdx.x; // coalesced
-        if (c < nc) {
-            const int32_t v = in[c];
-            s += v;
-            m = max(m, v);
-        }
-    }
-    block_sum_max(s, m, lds);
-    if (threadIdx.x == 0) {
-        tile_sum[blockIdx.x] = s;
-        tile_max[blockIdx.x] = m;
-    }
-}
-
-// Exclusive scan of a block of 1024 values held one per thread (16 waves);
-// returns the exclusive prefix and writes the block total to *total.
-__device__ __forceinline__ int32_t block_excl_scan_1024(int32_t v, int32_t *lds, int32_t *total)
-{
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t inc = wave_incl_scan(v);
-    if (lane == 63) lds[wid] = inc;
-    __syncthreads();
-    if (wid == 0) {
-        const int32_t wv = lane < 16 ? lds[lane] : 0;
-        const int32_t wi = wave_incl_scan(wv);
-        if (lane < 16) lds[16 + lane] = wi - wv; // exclusive per wave
-        if (lane == 15) lds[32] = wi;
-    }
-    __syncthreads();
-    const int32_t r = inc - v + lds[16 + wid];
-    *total = lds[32];
-    __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(1024) void k_scan_tiles(int32_t *__restrict__ tile_sum,
-                                                     const int32_t *__restrict__ tile_max, int32_t ntiles,
-                                                     int32_t *__restrict__ total_out,
-                                                     int32_t *__restrict__ max_out)
-{
-    __shared__ int32_t lds[40];
-    __shared__ int32_t red[32];
-    int32_t carry = 0, m = 0;
-    for (int32_t b = 0; b < ntiles; b += 1024) {
-        const int32_t t = b + (int32_t)threadIdx.x;
-        const int32_t v = t < ntiles ? tile_sum[t] : 0;
-        if (t < ntiles) m = max(m, tile_max[t]);
-        int32_t tot;
-        const int32_t ex = block_excl_scan_1024(v, lds, &tot);
-        if (t < ntiles) tile_sum[t] = carry + ex;
-        carry += tot;
-    }
-    m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t mm = 0;
-        for (int k = 0; k < 16; ++k) mm = max(mm, red[k]);
-        if (max_out) *max_out = mm;
-        *total_out = carry;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t *in, int64_t nc,
-                                                      const int32_t *__restrict__ tile_off,
-                                                      int32_t *out) // may alias `in`
-{
-    __shared__ int32_t lds[8];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int32_t v[kScanItems];
-    if (base + kScanItems <= nc) {
-        const int4 *p = reinterpret_cast<const int4 *>(in + base);
-#pragma unroll
-        for (int q = 0; q < kScanItems / 4; ++q) {
-            const int4 t = p[q];
-            v[4 * q] = t.x;
-            v[4 * q + 1] = t.y;
-            v[4 * q + 2] = t.z;
-            v[4 * q + 3] = t.w;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < kScanItems; ++j) v[j] = (base + j < nc) ? in[base + j] : 0;
-    }
-    int32_t tsum = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) tsum += v[j];
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t inc = wave_incl_scan(tsum);
-    if (lane == 63) lds[wid] = inc;
-    __syncthreads();
-    int32_t wofs = 0;
-    for (int k = 0; k < wid; ++k) wofs += lds[k];
-    int32_t run = tile_off[blockIdx.x] + wofs + inc - tsum;
-    int32_t o[kScanItems];
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        o[j] = run;
-        run += v[j];
-    }
-    if (base + kScanItems <= nc) {
-        int4 *p = reinterpret_cast<int4 *>(out + base);
-#pragma unroll
-        for (int q = 0; q < kScanItems / 4; ++q) p[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
-    } else {
-#pragma unroll
-        for (int j = 0; j < kScanItems; ++j)
-            if (base + j < nc) out[base + j] = o[j];
     }
 }
 
@@ -564,81 +428,127 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
     }
 }
 
-// After the last pass: the per-cell counts from the runs of equal ids in
-// the sorted global cell ids -- one plain store per occupied cell and no
-// atomics (counts start at zero).  A wavefront takes a few consecutive
-// chunks of 64 ids at once; the lane at the start of a run finds the run's
-// end as the next run start, from the chunks' start masks (wave ballots), or
-// past the wavefront's range by galloping over the sorted ids (only the last
-// run of a range can cross it).
-#ifndef PI_COUNT_CHUNKS
-#define PI_COUNT_CHUNKS 4
-#endif
-constexpr int kRunChunks = PI_COUNT_CHUNKS; // 64-id chunks per wavefront
+// After the last pass: the per-cell counts and the exclusive offsets
+// straight from the sorted global cell ids, with no separate scan (Fig. 1:
+// offsets[c] is the number of particles in cells before c, which in sorted
+// order is the position of the first id >= c).  A wavefront takes 256
+// consecutive sorted ids (positions [wbase, wbase + 256)) and owns the cells
+// (before, last]: `before` is the id just before its range (-1 for the
+// first) and `last` the last id in it.  It writes those cells 64 at a time,
+// each lane finding its cell's rank among the wavefront's ids by an 8-step
+// binary search in LDS, so every store is coalesced and every entry is
+// written exactly once:
+//   offsets[c] = wbase + #(ids in range < c)
+//   counts[c]  = #(ids in range == c), except that the run of `last` may
+//                continue past the range: its end is found in the 64 ids
+//                after it, else by galloping over the sorted ids.
+// The wavefront holding position n - 1 also writes the cells after its
+// last id (offset n, count 0) and offsets[nc] = n.  Each wavefront writes its
+// largest count to wmax[wave]; k_max_reduce folds those into M_C.  (An
+// atomicMax per wavefront on M_C itself serialised on that one address: 750
+// µs at 2^24 ids.)
+constexpr int kRunIds = 256; // sorted ids per wavefront
 
-__global__ __launch_bounds__(kBlock) void k_count_runs(int32_t n, const uint32_t *__restrict__ ids,
-                                                       int32_t *__restrict__ counts)
+__global__ __launch_bounds__(kBlock) void k_cell_ranges(int32_t n, int32_t nc, const uint32_t *__restrict__ ids,
+                                                        int32_t *__restrict__ counts, int32_t *__restrict__ offsets,
+                                                        int32_t *__restrict__ wmaxes)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t wbase = (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * (64 * kRunChunks);
-    if (wbase >= n) return; // uniform over the wavefront
-    const int64_t last = (int64_t)n - 1;
-    const int64_t wend = wbase + 64 * kRunChunks; // first id past the range
-    uint32_t id[kRunChunks];
+    __shared__ uint32_t sid[kBlock / 64][kRunIds];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int64_t wbase = wave * kRunIds;
+    if (wbase >= n) return; // uniform over the wavefront (no barriers below)
+    const int64_t lastpos = (int64_t)n - 1;
+    const int64_t wend = wbase + kRunIds; // first position past the range
+    uint32_t *s = sid[wid];
+    // ids past n repeat ids[n-1], which keeps the range sorted
 #pragma unroll
-    for (int r = 0; r < kRunChunks; ++r) id[r] = ids[min(wbase + r * 64 + lane, last)];
-    const uint32_t before = ids[wbase > 0 ? wbase - 1 : 0]; // id before the range
+    for (int r = 0; r < kRunIds / 64; ++r) s[r * 64 + lane] = ids[min(wbase + r * 64 + lane, lastpos)];
+    __builtin_amdgcn_wave_barrier(); // the lanes read each other's entries below
+    const int32_t before = wbase > 0 ? (int32_t)ids[wbase - 1] : -1;
+    const uint32_t after = ids[min(wend + lane, lastpos)];
+    const int32_t last = (int32_t)s[kRunIds - 1];
 
-    // run starts of every chunk, then each run's length (every load, the
-    // rare galloping ones included, before the first store)
-    uint64_t starts[kRunChunks];
-    bool mine[kRunChunks];
-    int32_t runlen[kRunChunks];
-#pragma unroll
-    for (int r = 0; r < kRunChunks; ++r) {
-        const int64_t k = wbase + r * 64 + lane;
-        const uint32_t up = __shfl_up(id[r], 1);
-        const uint32_t p63 = r > 0 ? __shfl(id[r > 0 ? r - 1 : 0], 63) : before;
-        const uint32_t prev = lane == 0 ? p63 : up;
-        mine[r] = k < n && (k == 0 || prev != id[r]);
-        starts[r] = __ballot(mine[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kRunChunks; ++r) {
-        runlen[r] = 0;
-        if (!mine[r]) continue;
-        const int64_t k = wbase + r * 64 + lane;
-        const uint32_t c = id[r];
-        int64_t end = -1;
-        const uint64_t above = starts[r] & ~((2ull << lane) - 1ull); // later starts in this chunk
-        if (above) {
-            end = wbase + r * 64 + (__ffsll((unsigned long long)above) - 1);
-        } else {
-#pragma unroll
-            for (int q = r + 1; q < kRunChunks; ++q)
-                if (end < 0 && starts[q]) end = wbase + q * 64 + (__ffsll((unsigned long long)starts[q]) - 1);
+    // end of the run of `last`: in the 64 ids after the range, else gallop
+    const uint64_t cont = __ballot(wend + lane < n && after == (uint32_t)last);
+    int64_t end;
+    if (cont != ~0ull) {
+        end = wend + (__ffsll((unsigned long long)~cont) - 1);
+    } else {
+        int64_t lo = wend + 63, hi = wend + 64, step = 64; // id lo == last
+        while (hi < n && ids[hi] == (uint32_t)last) {
+            lo = hi;
+            hi = hi + step;
+            step *= 2;
         }
-        if (end < 0) {
-            // the run reaches the end of the range: gallop, then bisect, for
-            // the first id past it (ids are sorted, so it is the first != c)
-            int64_t lo = wend - 1, hi = wend, step = 64; // id lo == c
-            while (hi < n && ids[hi] == c) {
-                lo = hi;
-                hi = hi + step;
-                step *= 2;
-            }
-            if (hi > n) hi = n;
-            while (hi - lo > 1) {
-                const int64_t mid = lo + (hi - lo) / 2;
-                if (ids[mid] == c) lo = mid; else hi = mid;
-            }
-            end = hi;
+        if (hi > n) hi = n;
+        while (hi - lo > 1) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (ids[mid] == (uint32_t)last) lo = mid; else hi = mid;
         }
-        runlen[r] = (int32_t)(end - k);
+        end = hi;
     }
+    if (end > n) end = n;
+
+    // number of ids in the range below c (lower bound over 256 sorted ids)
+    auto rank = [&](int32_t c) {
+        int32_t pos = 0;
 #pragma unroll
-    for (int r = 0; r < kRunChunks; ++r)
-        if (mine[r]) counts[id[r]] = runlen[r];
+        for (int step = kRunIds / 2; step > 0; step >>= 1)
+            if ((int32_t)s[pos + step - 1] < c) pos += step;
+        return pos;
+    };
+    // rounds of 63 cells: lane 63 ranks the cell after the round, so each
+    // count is a difference of neighbouring lanes' ranks
+    int32_t wmax = 0;
+    for (int64_t c0 = (int64_t)before + 1; c0 <= last; c0 += 63) {
+        const int32_t c = (int32_t)min(c0 + lane, (int64_t)last + 1);
+        const int32_t rc = rank(c);
+        const int32_t rnext = __shfl_down(rc, 1);
+        if (lane < 63 && c <= last) {
+            const int32_t cnt = c < last ? rnext - rc : (int32_t)(end - (wbase + rc));
+            offsets[c] = (int32_t)wbase + rc;
+            counts[c] = cnt;
+            wmax = max(wmax, cnt);
+        }
+    }
+    if (lastpos < wend) {
+        // the cells after the last id
+        for (int64_t c = (int64_t)last + 1 + lane; c < nc; c += 64) {
+            offsets[c] = n;
+            counts[c] = 0;
+        }
+        if (lane == 0) offsets[nc] = n;
+    }
+    wmax = wave_max(wmax);
+    if (lane == 0) wmaxes[wave] = wmax;
+}
+
+// out[0] = max of v[0 .. count) (all >= 0), v 16-byte aligned: one
+// workgroup of 1024 threads, 16-byte loads, sixteen in flight per thread.
+__global__ __launch_bounds__(1024) void k_max_reduce(const int32_t *__restrict__ v, int32_t count,
+                                                     int32_t *__restrict__ out)
+{
+    __shared__ int32_t part[16];
+    const int4 *v4 = reinterpret_cast<const int4 *>(v);
+    const int32_t n4 = count / 4;
+    int32_t m = 0;
+    for (int32_t i = threadIdx.x; i < n4; i += 16 * 1024) {
+        int4 q[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) q[u] = i + u * 1024 < n4 ? v4[i + u * 1024] : make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) m = max(m, max(max(q[u].x, q[u].y), max(q[u].z, q[u].w)));
+    }
+    for (int32_t i = 4 * n4 + (int32_t)threadIdx.x; i < count; i += 1024) m = max(m, v[i]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        m = threadIdx.x < 16 ? part[threadIdx.x] : 0;
+        m = wave_max(m);
+        if (threadIdx.x == 0) out[0] = m;
+    }
 }
 
 // The sorted coordinates as four arrays, from the records (in order).
@@ -655,19 +565,6 @@ __global__ __launch_bounds__(kBlock) void k_split_records(int32_t n, const float
 }
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
-
-// Exclusive scan of in[0 .. len) into out[0 .. len); the total goes to
-// *total and the maximum to *maxv (optional).
-void launch_scan(pi_ctx *ctx, const int32_t *in, int64_t len, int32_t *out, int32_t *total, int32_t *maxv,
-                 int32_t *tsum, int32_t *tmax, hipStream_t s)
-{
-    const int32_t ntiles = (int32_t)((len + kScanTile - 1) / kScanTile);
-    PI_LAUNCH(ctx, "k_scan_reduce", k_scan_reduce, dim3(ntiles), dim3(kBlock), 0, s, in, len, tsum, tmax);
-    PI_LAUNCH(ctx, "k_scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, s, tsum, (const int32_t *)tmax, ntiles,
-              total, maxv);
-    PI_LAUNCH(ctx, "k_scan_down", k_scan_down, dim3(ntiles), dim3(kBlock), 0, s, in, len, (const int32_t *)tsum,
-              out);
-}
 
 } // namespace
 
@@ -693,8 +590,6 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
                          const GridDev &g0, hipStream_t stream)
 {
     const bool batch = nsys > 0;
-    PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks((nc + 3) / 4, kBlock)), dim3(kBlock), 0, stream,
-              cells->counts, nc, 0);
     if (n > 0) {
         // 8-bit digits needed to sort keys 0 .. nc-1
         int bits = 1;
@@ -753,13 +648,23 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
                 PI_LAUNCH(ctx, nm, (k_radix_scatter<false, false, false>), grid, sb, 0, stream, a);
             }
         }
-        const int64_t waves = (n + 64 * kRunChunks - 1) / (64 * kRunChunks);
-        PI_LAUNCH(ctx, "k_count_runs", k_count_runs, dim3(nblocks(waves * 64, kBlock)), dim3(kBlock), 0, stream,
-                  (int32_t)n, (const uint32_t *)ids, cells->counts);
+        // the per-wavefront maxima go to the histogram buffer, free after
+        // the last pass (256 entries per 4096 particles, one per 256 needed)
+        const int64_t waves = (n + kRunIds - 1) / kRunIds;
+        PI_LAUNCH(ctx, "k_cell_ranges", k_cell_ranges, dim3(nblocks(waves * 64, kBlock)), dim3(kBlock), 0, stream,
+                  (int32_t)n, (int32_t)nc, (const uint32_t *)ids, cells->counts, cells->offsets, cells->hist);
+        PI_LAUNCH(ctx, "k_max_reduce", k_max_reduce, dim3(1), dim3(1024), 0, stream, (const int32_t *)cells->hist,
+                  (int32_t)waves, cells->max_per_cell);
+    } else {
+        // no particles: every count and offset is zero, and M_C
+        PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks((nc + 3) / 4, kBlock)), dim3(kBlock), 0, stream,
+                  cells->counts, nc, 0);
+        PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(nblocks((nc + 4) / 4, kBlock)), dim3(kBlock), 0, stream,
+                  cells->offsets, nc + 1, 0);
+        PI_LAUNCH(ctx, "k_fill_i32", k_fill_i32, dim3(1), dim3(kBlock), 0, stream, cells->max_per_cell, (int64_t)1,
+                  0);
     }
     cells->soa_stale = n > 0;
-    launch_scan(ctx, cells->counts, nc, cells->offsets, cells->offsets + nc, cells->max_per_cell, cells->tile_sum,
-                cells->tile_max, stream);
     PI_CHECK_HIP(hipGetLastError());
     return PI_OK;
 }

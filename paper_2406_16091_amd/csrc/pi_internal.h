@@ -59,7 +59,6 @@ struct pi_cells {
     pi_grid grid;
     int64_t cap_n;      // capacity in particles
     int64_t cap_cells;  // capacity in cells
-    int64_t cap_tiles;  // scan tile partials (cells)
     int64_t cap_hist;   // radix histogram entries (256 per sort tile)
     hipStream_t last_stream;
     bool binned;
@@ -79,8 +78,6 @@ struct pi_cells {
     // radix histograms (digit-major, 256 x sort tiles) and their scan scratch
     int32_t *hist;        // [cap_hist]
     // cell-scan scratch
-    int32_t *tile_sum;  // [cap_tiles]
-    int32_t *tile_max;  // [cap_tiles]
     int32_t *max_per_cell; // [1]
     uint32_t *d_err;       // [1]
     // invariant partials

@@ -13,7 +13,7 @@ def test_kernel_key_matches_library_and_profiler_names():
     assert bench.kernel_key("k_sweep_tile<6,6,6>") == "k_sweep_tile<6,6,6>"
     assert bench.kernel_key("k_sweep_tile<6, 6, 6, 768, 8, 0, true, false>") == "k_sweep_tile<6,6,6>"
     assert bench.kernel_key("k_radix_scatter<true, false>") == "k_radix_scatter<true,false>"
-    assert bench.kernel_key("k_count_runs") == "k_count_runs"
+    assert bench.kernel_key("k_cell_ranges") == "k_cell_ranges"
 
 
 def test_candidate_count_is_the_clipped_stencil_sum():
