@@ -350,32 +350,28 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
     }
     __syncthreads();
 
-    // 3. tile-local position of every key and the global destination of that
-    //    position (consecutive positions of one digit go to consecutive
-    //    addresses, so the copies below are coalesced runs); keys past the
-    //    end get the spare slot kSortTile, written but never read
-    uint32_t *lb4 = reinterpret_cast<uint32_t *>(lbuf);
+    // 3. tile-local position of every key (consecutive positions of one
+    //    digit go to consecutive addresses, so the copies below are
+    //    coalesced runs); keys past the end get the spare slot kSortTile,
+    //    written but never read
 #pragma unroll
     for (int r = 0; r < kSItems; ++r) {
         const uint32_t dg = (key[r] >> a.shift) & (kRadix - 1);
-        const int32_t within = wcnt[wid][dg] + pos[r];
-        const bool valid = pos[r] >= 0;
-        pos[r] = valid ? lstart[dg] + within : kSortTile;
-        lb4[pos[r]] = (uint32_t)(gdst[dg] + within);
+        pos[r] = pos[r] >= 0 ? lstart[dg] + wcnt[wid][dg] + pos[r] : kSortTile;
     }
     const int32_t nvalid = (int32_t)min((int64_t)kSortTile, (int64_t)a.n - tile_base);
-    __syncthreads();
-    int32_t dst[kSItems];
-#pragma unroll
-    for (int k = 0; k < kSItems; ++k) {
-        const int p = tid + k * kSBlock;
-        dst[k] = p < nvalid ? (int32_t)lb4[p] : 0;
-    }
-    __syncthreads();
 
     // 4. the (key, index) records, then the payload, reordered through LDS
     //    and written out in runs; the last pass writes the final arrays
-    //    instead (local cell id and index, cell-relative payload)
+    //    instead (local cell id and index, cell-relative payload).  The
+    //    reader of position p takes the digit from the record there, and p's
+    //    destination is that digit's global start plus p's offset in the
+    //    digit's tile-local run.
+    auto dest = [&](int p, uint32_t k) {
+        const uint32_t dg = (k >> a.shift) & (kRadix - 1);
+        return gdst[dg] + (p - lstart[dg]);
+    };
+    int32_t dst[kSItems];
     if (LAST && BATCH) {
         uint4 *lb16 = reinterpret_cast<uint4 *>(lbuf);
 #pragma unroll
@@ -387,14 +383,17 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
 #pragma unroll
         for (int k = 0; k < kSItems; ++k) {
             const int p = tid + k * kSBlock;
+            dst[k] = 0;
             if (p < nvalid) {
                 const uint4 c = lb16[p];
+                dst[k] = dest(p, c.z);
                 a.cell[dst[k]] = (int32_t)c.x;
                 a.perm[dst[k]] = (int32_t)c.y;
                 a.ids[dst[k]] = c.z;
             }
         }
     } else {
+        // (in the last pass of one system the local cell id is the key)
         uint2 *lb8 = reinterpret_cast<uint2 *>(lbuf);
 #pragma unroll
         for (int r = 0; r < kSItems; ++r) {
@@ -405,8 +404,10 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
 #pragma unroll
         for (int k = 0; k < kSItems; ++k) {
             const int p = tid + k * kSBlock;
+            dst[k] = 0;
             if (p < nvalid) {
                 const uint2 c = lb8[p];
+                dst[k] = dest(p, c.x);
                 if (LAST) {
                     a.cell[dst[k]] = (int32_t)c.x;
                     a.perm[dst[k]] = (int32_t)c.y;
