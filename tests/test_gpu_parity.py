@@ -93,7 +93,23 @@ SMALL = {
         synth.box_system(4000, 8, seed=36, lattice_log2=18)), (-4.0, 2.0, -1.0), (8, 8, 8), 1.0, 1.0),
     "single": lambda: synth.box_system(1, 3, seed=37, lattice_log2=18),
     "dense_8ppc": lambda: synth.uniform_unit_cube(8 * 16 ** 3, -4, seed=38),
+    # one cell holding 1500 particles (its run crosses several 256-id ranges
+    # of the count kernel and overflows every tile's LDS) among 2000 others
+    "dense_cell": lambda: _dense_cell(),
+    # 1500 particles in 48^3 cells: long empty gaps between runs
+    "sparse": lambda: synth.box_system(1500, 48, seed=42, lattice_log2=18),
 }
+
+
+def _dense_cell():
+    rng = np.random.default_rng(41)
+    g, p = 8, 18
+    bg = rng.integers(0, g << p, size=(3, 2000))
+    hot = rng.integers(0, 1 << p, size=(3, 1500)) + np.array([[3 << p], [4 << p], [2 << p]])
+    m = np.concatenate([bg, hot], axis=1)[:, rng.permutation(3500)]
+    x, y, z = (m.astype(np.float64) * 2.0 ** -p).astype(np.float32)
+    w = (0.5 + rng.random(3500) * 0.5).astype(np.float32)
+    return synth.System("dense_cell", x, y, z, w, (0.0, 0.0, 0.0), (g, g, g), 1.0, 1.0)
 
 
 @pytest.mark.parametrize("case", list(SMALL))
