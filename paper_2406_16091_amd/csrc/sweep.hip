@@ -395,8 +395,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
 // which pairs are accepted or their order.
 //
 // Candidate testing and pair evaluation are decoupled: each lane walks its
-// segments in lockstep with the wavefront and pushes the LDS index of every
-// accepted source into a private FIFO of Q entries in LDS; whenever some
+// segments in lockstep with the wavefront and pushes the staging-area byte
+// offset of every accepted source into a private FIFO of Q entries in LDS
+// (segments and queue entries are byte offsets, so no step scales an index);
+// whenever some
 // lane's FIFO is full, the wavefront pops one entry per non-empty lane and
 // evaluates the kernel.  Otherwise the wavefront would run the long
 // evaluation on almost every candidate step (about one candidate in six is
