@@ -440,12 +440,6 @@ __device__ __forceinline__ void walk_cells_global(const SweepArgs &a, int32_t k,
     }
 }
 
-// Staging-area slots [s0, s1) as a packed byte range: start | end << 16.
-__device__ __forceinline__ uint32_t seg_bytes(int32_t s0, int32_t s1)
-{
-    return ((uint32_t)s0 * (uint32_t)sizeof(float4)) | (((uint32_t)s1 * (uint32_t)sizeof(float4)) << 16);
-}
-
 template <int TX, int TY, int TZ, int CAP, int Q, int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx, int32_t nty)
 {
@@ -461,7 +455,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     // staging-area byte ranges of the row segments (start | end << 16); the
     // target's own row is cut in two around the target itself, so at most 10
     __shared__ uint32_t segtab[10][kBlock];
+    // staging-area byte offset of every halo cell's first particle
     __shared__ int32_t cs[R][HX + 1];
+    // halo row of every staged slot, and target row of every target
+    __shared__ uint8_t hrow[CAP];
+    __shared__ uint8_t trow[CAP];
     __shared__ int32_t rstart[R + 1];
     __shared__ int32_t gstart[R];
     __shared__ int32_t rbase[R];
@@ -505,6 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             rstart[tid] = inc - cnt;
             gstart[tid] = gs;
             rbase[tid] = rb32;
+            for (int32_t f = inc - cnt; f < min(inc, CAP); ++f) hrow[f] = (uint8_t)tid;
         }
         if (tid == R - 1) rstart[R] = inc;
 
@@ -521,6 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         if (tid < TR) {
             tstart[tid] = tinc - tc;
             tfirst[tid] = tf;
+            for (int32_t f = tinc - tc; f < min(tinc, CAP); ++f) trow[f] = (uint8_t)tid;
         }
         if (tid == TR - 1) tstart[TR] = tinc;
     }
@@ -563,18 +563,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         int32_t v = 0;
         if (jj <= ncx && y >= 0 && y < a.ny && z >= 0 && z < a.nz)
             v = a.off[(int64_t)rbase[r] + cxlo + jj] - gstart[r] + rstart[r];
-        cs[r][jj] = v;
+        cs[r][jj] = v * (int32_t)sizeof(float4);
     }
     // 3. stage the halo particles in tile-relative coordinates: offsets from
     //    the corner of the halo box (cell (cxlo, y0 - 1, z0 - 1)), so that a
     //    difference of two staged positions is the pair's difference vector
     //    with no per-row shift
     for (int32_t f = tid; f < total; f += kBlock) {
-        int lo = 0, hi = R; // rstart[lo] <= f < rstart[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (rstart[mid] <= f) lo = mid; else hi = mid;
-        }
+        const int lo = hrow[f]; // rstart[lo] <= f < rstart[lo + 1]
         const int32_t g = gstart[lo] + (f - rstart[lo]);
         const int32_t cx = a.cell[g] - rbase[lo];
         const float4 q = a.p4[g];
@@ -594,17 +590,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         int32_t k = 0, self = -1, nseg = 0;
         float xt = 0.f, yt = 0.f, zt = 0.f, wi = 0.f;
         if (tgt) {
-            int lo = 0, hi = TR;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (tstart[mid] <= f) lo = mid; else hi = mid;
-            }
+            const int lo = trow[f]; // tstart[lo] <= f < tstart[lo + 1]
             k = tfirst[lo] + (f - tstart[lo]);
             const int32_t ty_ = lo % TY, tz_ = lo / TY;
             const int32_t y = y0 + ty_, z = z0 + tz_;
             const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
             const int hr = (ty_ + 1) + HY * (tz_ + 1);
             self = rstart[hr] + (k - gstart[hr]);
+            const int32_t selfb = self * (int32_t)sizeof(float4);
             const float4 p = sp[self];
             xt = p.x; yt = p.y; zt = p.z; wi = p.w;
             // cell-relative position of the target, for the reach test
@@ -629,12 +622,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                     const int r = (ty_ + 1 + dy) + HY * (tz_ + 1 + dz);
                     const int32_t s0 = cs[r][jc - (left ? 1 : 0)];
                     const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
+                    // (byte offsets: start | end << 16)
                     if (dy == 0 && dz == 0) {
                         // s0 <= self < s1: the parts before and after it
-                        if (self > s0) segtab[nseg++][tid] = seg_bytes(s0, self);
-                        if (s1 > self + 1) segtab[nseg++][tid] = seg_bytes(self + 1, s1);
+                        const int32_t after = selfb + (int32_t)sizeof(float4);
+                        if (selfb > s0) segtab[nseg++][tid] = (uint32_t)s0 | ((uint32_t)selfb << 16);
+                        if (s1 > after) segtab[nseg++][tid] = (uint32_t)after | ((uint32_t)s1 << 16);
                     } else if (s1 > s0) {
-                        segtab[nseg][tid] = seg_bytes(s0, s1);
+                        segtab[nseg][tid] = (uint32_t)s0 | ((uint32_t)s1 << 16);
                         ++nseg;
                     }
                 }
