@@ -248,6 +248,40 @@ def test_overflowing_tile_falls_back(dev):
         _check_floats(ds.results(), ref)
 
 
+def test_cells_reused_across_sizes_and_grids(dev):
+    """One pi_cells object binned again and again: a smaller system on
+    another grid, an empty one, then a larger one (its buffers grow).  Every
+    count and offset is rewritten each time, so nothing of an earlier
+    binning survives into a later one."""
+    from paper_2406_16091_amd import pi
+    e = np.zeros(0, np.float32)
+    systems = [SMALL["dense_8ppc"](), SMALL["ragged"](),
+               synth.System("empty", e, e, e, e, (0.0, 0.0, 0.0), (5, 4, 3), 1.0, 1.0),
+               synth.uniform_unit_cube(3 * 32 ** 3, -5, seed=43)]
+    handle = None
+    try:
+        for s in systems:
+            _say(f"[reuse] n={s.n} dims={s.dims}")
+            ds = dev.DeviceSystem(s)
+            if handle is None:
+                handle = ds.cells
+            else:
+                pi.pi_cells_destroy(ds.cells)
+                ds.cells = handle
+            ds.bin()
+            ds.interact(order="original")
+            ds.sync()
+            b = _oracle_bin(s)
+            _check_bin(ds, s, b)
+            if s.n:
+                _check_floats(ds.results(), oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b))
+            assert ds.invariants()["pairs"] == int(oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b).count.sum())
+            ds.cells = None  # the shared object is destroyed below, once
+    finally:
+        if handle is not None:
+            pi.pi_cells_destroy(handle)
+
+
 def test_empty_system(dev):
     e = np.zeros(0, np.float32)
     s = synth.System("empty", e, e, e, e, (0.0, 0.0, 0.0), (4, 3, 2), 1.0, 1.0)
