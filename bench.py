@@ -392,7 +392,7 @@ def main():
         bin_us = sum(v[1] for k, v in kt.items() if not k.startswith(("k_sweep", "k_inv"))) * 1e3 / args.steps
         sw = [(k, v) for k, v in kt.items() if k.startswith("k_sweep")]
         sweep_us = sum(v[1] for _, v in sw) * 1e3 / args.steps
-        bin_bytes = 48.0 * n + 16.0 * nc
+        bin_bytes = 40.0 * n + 8.0 * nc
         stages = {"bin_us": round(bin_us, 2), "sweep_us": round(sweep_us, 2),
                   "bin_hbm_frac_algorithmic": round(bin_bytes / (bin_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                   "sweep_fp32_frac": round((FLOP_PER_CANDIDATE * cand + FLOP_PER_PAIR_COMPENSATED * pairs)
