@@ -607,18 +607,22 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             const float gyl = yc * yc, gyr = (W - yc) * (W - yc);
             const float gzl = zc * zc, gzr = (W - zc) * (W - zc);
             const int32_t jc = ix - cxlo;
+            // the left (right) cell of a row is kept iff gyz < tl (tr): the
+            // same test as gx + gyz < reach2 up to one rounding, which the
+            // 16u margin of reach2 covers (a missing neighbour cell: -1)
+            const float tl = ix > 0 ? reach2 - gxl : -1.0f;
+            const float tr = ix + 1 < a.nx ? reach2 - gxr : -1.0f;
+            const bool zlo = z > 0, zhi = z + 1 < a.nz, ylo = y > 0, yhi = y + 1 < a.ny;
             // segments in canonical (dz, dy) order
             for (int dz = -1; dz <= 1; ++dz) {
-                const int32_t cz = z + dz;
-                if (cz < 0 || cz >= a.nz) continue;
+                if (dz < 0 ? !zlo : (dz > 0 && !zhi)) continue;
                 const float gz = dz < 0 ? gzl : (dz > 0 ? gzr : 0.f);
                 for (int dy = -1; dy <= 1; ++dy) {
-                    const int32_t cy = y + dy;
-                    if (cy < 0 || cy >= a.ny) continue;
+                    if (dy < 0 ? !ylo : (dy > 0 && !yhi)) continue;
                     const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + gz;
                     if (gyz >= reach2) continue; // the whole row is out of reach
-                    const bool left = ix > 0 && gxl + gyz < reach2;
-                    const bool right = ix + 1 < a.nx && gxr + gyz < reach2;
+                    const bool left = gyz < tl;
+                    const bool right = gyz < tr;
                     const int r = (ty_ + 1 + dy) + HY * (tz_ + 1 + dz);
                     const int32_t s0 = cs[r][jc - (left ? 1 : 0)];
                     const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
