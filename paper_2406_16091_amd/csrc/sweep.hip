@@ -613,6 +613,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
             const float tl = ix > 0 ? reach2 - gxl : -1.0f;
             const float tr = ix + 1 < a.nx ? reach2 - gxr : -1.0f;
             const bool zlo = z > 0, zhi = z + 1 < a.nz, ylo = y > 0, yhi = y + 1 < a.ny;
+            // the target's own cell in its own halo row; a neighbour row is a
+            // compile-time offset from it
+            const int32_t *own = &cs[(ty_ + 1) + HY * (tz_ + 1)][jc];
+            uint32_t *segp = &segtab[0][tid];
             // segments in canonical (dz, dy) order
             for (int dz = -1; dz <= 1; ++dz) {
                 if (dz < 0 ? !zlo : (dz > 0 && !zhi)) continue;
@@ -623,21 +627,28 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                     if (gyz >= reach2) continue; // the whole row is out of reach
                     const bool left = gyz < tl;
                     const bool right = gyz < tr;
-                    const int r = (ty_ + 1 + dy) + HY * (tz_ + 1 + dz);
-                    const int32_t s0 = cs[r][jc - (left ? 1 : 0)];
-                    const int32_t s1 = cs[r][jc + 1 + (right ? 1 : 0)];
+                    const int32_t *row = own + (dy + HY * dz) * (HX + 1);
+                    const int32_t s0 = row[left ? -1 : 0];
+                    const int32_t s1 = row[right ? 2 : 1];
                     // (byte offsets: start | end << 16)
                     if (dy == 0 && dz == 0) {
                         // s0 <= self < s1: the parts before and after it
                         const int32_t after = selfb + (int32_t)sizeof(float4);
-                        if (selfb > s0) segtab[nseg++][tid] = (uint32_t)s0 | ((uint32_t)selfb << 16);
-                        if (s1 > after) segtab[nseg++][tid] = (uint32_t)after | ((uint32_t)s1 << 16);
+                        if (selfb > s0) {
+                            *segp = (uint32_t)s0 | ((uint32_t)selfb << 16);
+                            segp += kBlock;
+                        }
+                        if (s1 > after) {
+                            *segp = (uint32_t)after | ((uint32_t)s1 << 16);
+                            segp += kBlock;
+                        }
                     } else if (s1 > s0) {
-                        segtab[nseg][tid] = (uint32_t)s0 | ((uint32_t)s1 << 16);
-                        ++nseg;
+                        *segp = (uint32_t)s0 | ((uint32_t)s1 << 16);
+                        segp += kBlock;
                     }
                 }
             }
+            nseg = (int32_t)((segp - &segtab[0][tid]) / kBlock);
         }
         Target<PREC, INV> T;
         int seg = 0;
