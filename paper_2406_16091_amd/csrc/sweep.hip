@@ -168,7 +168,11 @@ __device__ __forceinline__ void target_invariants(const Target<PREC, INV> &T, fl
 // ------------------------------------------------------------------ no LDS
 // One thread per sorted target; sources read through L1/L2 (Algorithm 1,
 // Par-Part-NoLoop, with targets in cell-sorted order so that a wavefront's
-// neighbour rows overlap in cache).
+// neighbour rows overlap in cache).  Each neighbour X-row is walked as one
+// index range over its (up to) three cells, so a wavefront's loop runs as
+// long as its longest row rather than its longest cell, three times a row;
+// cells beyond the cutoff's reach are trimmed as in the tiles.  The sources
+// and their order are those of the 27-cell walk, so the results are too.
 template <int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
 {
@@ -192,27 +196,40 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
         const float xi = pk.x, yi = pk.y, zi = pk.z;
         wi = pk.w;
         const float W = a.k.w;
+        const float reach2 = a.k.reach2;
+        // the target in the frame of its left and right neighbour cells
+        const float xm = xi - (float)(-1) * W, xp = xi - (float)(1) * W;
+        // the reach test of the tiles: a neighbour cell whose nearest face is
+        // surely beyond the cutoff is skipped (no pair there is accepted), and
+        // the left (right) cell of a row is kept iff gyz < tl (tr)
+        const float gyl = yi * yi, gyr = (W - yi) * (W - yi);
+        const float gzl = zi * zi, gzr = (W - zi) * (W - zi);
+        const float tl = ix > 0 ? reach2 - xi * xi : -1.0f;
+        const float tr = ix + 1 < a.nx ? reach2 - (W - xi) * (W - xi) : -1.0f;
+        // each X-row's (up to) three cells are one index range, walked in
+        // one loop; the two inner cell boundaries give each source's shift
         for (int dz = -1; dz <= 1; ++dz) {
             const int32_t cz = iz + dz;
             if (cz < 0 || cz >= a.nz) continue;
             const float tz = zi - (float)dz * W;
+            const float gz = dz < 0 ? gzl : (dz > 0 ? gzr : 0.f);
             for (int dy = -1; dy <= 1; ++dy) {
                 const int32_t cy = iy + dy;
                 if (cy < 0 || cy >= a.ny) continue;
+                const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + gz;
+                if (gyz >= reach2) continue; // the whole row is out of reach
                 const float ty = yi - (float)dy * W;
-                const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz);
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int32_t cx = ix + dx;
-                    if (cx < 0 || cx >= a.nx) continue;
-                    const float tx = xi - (float)dx * W;
-                    const int32_t j0 = a.off[rb + cx], j1 = a.off[rb + cx + 1];
-                    for (int32_t j = j0; j < j1; ++j) {
-                        const float4 s = a.p4[j];
-                        const float ddx = tx - s.x, ddy = ty - s.y, ddz = tz - s.z;
-                        const float t = sq_dist(ddx, ddy, ddz);
-                        if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k))
-                            T.accept(ddx, ddy, ddz, t, s.w, a.k);
-                    }
+                const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz) + ix;
+                const int32_t b1 = a.off[rb], b2 = a.off[rb + 1];
+                const int32_t j0 = gyz < tl ? a.off[rb - 1] : b1;
+                const int32_t j3 = gyz < tr ? a.off[rb + 2] : b2;
+                for (int32_t j = j0; j < j3; ++j) {
+                    const float tx = j < b1 ? xm : (j < b2 ? xi : xp);
+                    const float4 s = a.p4[j];
+                    const float ddx = tx - s.x, ddy = ty - s.y, ddz = tz - s.z;
+                    const float t = sq_dist(ddx, ddy, ddz);
+                    if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k))
+                        T.accept(ddx, ddy, ddz, t, s.w, a.k);
                 }
             }
         }
