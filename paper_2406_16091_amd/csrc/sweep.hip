@@ -245,23 +245,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
 
 // ------------------------------------------------------------------ stream
 // One thread per sorted target with sources read through the caches, as in
-// NOLDS, but with candidate testing decoupled from pair evaluation by the
-// per-lane LDS FIFO of the tiles (see below): the test of one candidate is
-// about ten instructions, the evaluation of an accepted pair about a
+// NOLDS (the same trimmed X-row walk, one row of the 9 at a time for the
+// whole wavefront), but with candidate testing decoupled from pair
+// evaluation by a per-lane LDS FIFO as in the tiles: the test of one
+// candidate is a few instructions, the evaluation of an accepted pair about a
 // hundred, and at several particles per cell some lane of a wavefront
-// accepts on nearly every step.  Nothing is staged, so the organisation
-// works at any occupancy.  Each lane walks its neighbour rows in canonical
-// (dz, dy) order, a row being one global index range (its up to three cells,
-// the outer ones trimmed by the reach test of the tiles) whose inner cell
-// boundaries give each source's x shift.  The next row's range is loaded
-// when the lane enters the current one, so a row change does not wait for
-// memory, and the LDS holds only the queues (high occupancy).
+// accepts on nearly every step.  A queue entry is the source's sorted index
+// and a byte code of its cell shift (dx, dy, dz), from which the pop rebuilds
+// the same differences the test used.  Nothing is staged, so the
+// organisation works at any occupancy.
 template <int Q, int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
 {
     static_assert((Q & (Q - 1)) == 0, "FIFO depth must be a power of two");
     __shared__ int32_t fifo[kBlock / 64][Q][64];   // accepted source: sorted index
-    __shared__ uint8_t fcode[kBlock / 64][Q][64];  // its shifts: (dx + 1) | row << 2
+    __shared__ uint8_t fcode[kBlock / 64][Q][64];  // its shift: (dx+1) | (dy+1) << 2 | (dz+1) << 4
 
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     int32_t k, kend;
@@ -290,90 +288,70 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
         zi = pk.z;
         wi = pk.w;
     }
-    const float gxl = xi * xi, gxr = (W - xi) * (W - xi);
+    // the target in the frame of a neighbour cell: x - d W for d = -1, 0, 1
+    // (the same roundings as the no-LDS walk)
+    const float xm = xi - (float)(-1) * W, xp = xi - (float)(1) * W;
+    const float ym = yi - (float)(-1) * W, yp = yi - (float)(1) * W;
+    const float zm = zi - (float)(-1) * W, zp = zi - (float)(1) * W;
+    auto sel = [](int q, float m, float o, float p) { return q == 0 ? m : (q == 1 ? o : p); };
     const float gyl = yi * yi, gyr = (W - yi) * (W - yi);
     const float gzl = zi * zi, gzr = (W - zi) * (W - zi);
-    // target coordinate shifted into the frame of a neighbour cell:
-    // x - dx W for dx = -1, 0, 1 (the same roundings as the subtraction)
-    const float xm = xi + W, xp = xi - W, ym = yi + W, yp = yi - W, zm = zi + W, zp = zi - W;
-    auto sel = [](int q, float m, float o, float p) { return q == 0 ? m : (q == 1 ? o : p); };
-
-    // rows q = 0 .. 8: dz = q / 3 - 1, dy = q % 3 - 1; fetch_row finds the
-    // next usable row from qn on and starts the loads of its range
-    int qn = 0;
-    bool nvalid = false;
-    int32_t n0 = 0, n1 = 0, n2 = 0, n3 = 0;
-    int nrow = 0;
-    auto fetch_row = [&]() {
-        nvalid = false;
-        while (qn < 9) {
-            const int dz = qn / 3 - 1, dy = qn % 3 - 1;
-            ++qn;
-            const int32_t cz = iz + dz, cy = iy + dy;
-            if (cz < 0 || cz >= a.nz || cy < 0 || cy >= a.ny) continue;
-            const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + (dz < 0 ? gzl : (dz > 0 ? gzr : 0.f));
-            if (gyz >= reach2) continue; // the whole row is out of reach
-            const bool left = ix > 0 && gxl + gyz < reach2;
-            const bool right = ix + 1 < a.nx && gxr + gyz < reach2;
-            const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz) + ix;
-            n1 = a.off[rb];
-            n2 = a.off[rb + 1];
-            n0 = left ? a.off[rb - 1] : n1;
-            n3 = right ? a.off[rb + 2] : n2;
-            nrow = ((dy + 1) << 2) | (dz + 1);
-            nvalid = true;
-            break;
-        }
-    };
-    if (active) fetch_row();
+    const float tl = ix > 0 ? reach2 - xi * xi : -1.0f;
+    const float tr = ix + 1 < a.nx ? reach2 - (W - xi) * (W - xi) : -1.0f;
 
     Target<PREC, INV> T;
     int32_t *myq = &fifo[wid][0][lane];
     uint8_t *myc = &fcode[wid][0][lane];
-    int qh = 0, qc = 0, row = 0;
-    int32_t j = 0, jend = 0, b1 = 0, b2 = 0;
-    float ty = 0.f, tz = 0.f;
+    int qh = 0, qc = 0;
     auto pop = [&]() {
         const int32_t jj = myq[qh * 64];
-        const int c = myc[qh * 64];
+        const int cd = myc[qh * 64];
         qh = (qh + 1) & (Q - 1);
         --qc;
         const float4 s = a.p4[jj];
-        const float ddx = sel(c & 3, xm, xi, xp) - s.x;
-        const float ddy = sel((c >> 4) & 3, ym, yi, yp) - s.y;
-        const float ddz = sel((c >> 2) & 3, zm, zi, zp) - s.z;
+        const float ddx = sel(cd & 3, xm, xi, xp) - s.x;
+        const float ddy = sel((cd >> 2) & 3, ym, yi, yp) - s.y;
+        const float ddz = sel((cd >> 4) & 3, zm, zi, zp) - s.z;
         T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
     };
-    while (true) {
-        if (j >= jend && nvalid) {
-            // enter the prefetched row, and prefetch the one after it
-            j = n0;
-            b1 = n1;
-            b2 = n2;
-            jend = n3;
-            row = nrow;
-            ty = sel(row >> 2, ym, yi, yp);
-            tz = sel(row & 3, zm, zi, zp);
-            fetch_row();
-        }
-        const bool have = j < jend;
-        if (!__any(have || nvalid)) break;
-        if (have) {
-            const int dxc = j < b1 ? 0 : (j < b2 ? 1 : 2);
-            const float4 s = a.p4[j];
-            const float ddx = sel(dxc, xm, xi, xp) - s.x, ddy = ty - s.y, ddz = tz - s.z;
-            const float t = sq_dist(ddx, ddy, ddz);
-            bool acc = t < a.k.lo;
-            if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
-            // written always (the slot after the tail is free), kept if accepted
-            const int slot = ((qh + qc) & (Q - 1)) * 64;
-            myq[slot] = j;
-            myc[slot] = (uint8_t)(dxc | (row << 2));
-            qc += (acc && j != k) ? 1 : 0;
-            ++j;
-        }
-        if (__any(qc == Q)) {
-            if (qc > 0) pop();
+    for (int dz = -1; dz <= 1; ++dz) {
+        const float tz = dz < 0 ? zm : (dz > 0 ? zp : zi);
+        const float gz = dz < 0 ? gzl : (dz > 0 ? gzr : 0.f);
+        const bool zok = active && iz + dz >= 0 && iz + dz < a.nz;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const float ty = dy < 0 ? ym : (dy > 0 ? yp : yi);
+            const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + gz;
+            // this lane's range of the row (empty if the row is outside the
+            // grid or out of reach) and its two inner cell boundaries
+            int32_t j = 0, j3 = 0, b1 = 0, b2 = 0;
+            if (zok && iy + dy >= 0 && iy + dy < a.ny && gyz < reach2) {
+                const int64_t rb = (int64_t)a.nx * ((iy + dy) + (int64_t)a.ny * (iz + dz)) + ix;
+                b1 = a.off[rb];
+                b2 = a.off[rb + 1];
+                j = gyz < tl ? a.off[rb - 1] : b1;
+                j3 = gyz < tr ? a.off[rb + 2] : b2;
+            }
+            const int rowcode = ((dy + 1) << 2) | ((dz + 1) << 4);
+            while (__any(j < j3)) {
+                if (j < j3) {
+                    const int dxc = j < b1 ? 0 : (j < b2 ? 1 : 2);
+                    const float4 s = a.p4[j];
+                    const float ddx = sel(dxc, xm, xi, xp) - s.x, ddy = ty - s.y, ddz = tz - s.z;
+                    const float t = sq_dist(ddx, ddy, ddz);
+                    bool acc = t < a.k.lo;
+                    if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
+                    // written always (the slot after the tail is free), kept
+                    // if accepted
+                    const int slot = ((qh + qc) & (Q - 1)) * 64;
+                    myq[slot] = j;
+                    myc[slot] = (uint8_t)(dxc | rowcode);
+                    qc += (acc && j != k) ? 1 : 0;
+                    ++j;
+                }
+                if (__any(qc == Q)) {
+                    if (qc > 0) pop();
+                }
+            }
         }
     }
     for (int left = wave_max(qc); left > 0; --left) {
