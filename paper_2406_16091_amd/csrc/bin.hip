@@ -175,7 +175,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(SortArgs a)
     for (int w = 0; w < 4; ++w) h[w][threadIdx.x] = 0;
     // all of the tile's loads first (indices past the end clamped; their
     // keys are not counted)
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    // (each XCD takes a contiguous run of tiles: neighbouring tiles share
+    // its L2, which merges their partial-line writes of a histogram column)
+    const int32_t tile = (int32_t)xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)tile * kSortTile;
     const int64_t last = (int64_t)a.n - 1;
     uint32_t key[kSortItems];
     if (FIRST) {
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(SortArgs a)
         if (base + q * kBlock + threadIdx.x < a.n) atomicAdd(&h[wid][(key[q] >> a.shift) & (kRadix - 1)], 1);
     __syncthreads();
     const int d = threadIdx.x;
-    a.hist[(int64_t)d * a.ntiles + blockIdx.x] = (h[0][d] + h[1][d]) + (h[2][d] + h[3][d]);
+    a.hist[(int64_t)d * a.ntiles + tile] = (h[0][d] + h[1][d]) + (h[2][d] + h[3][d]);
 }
 
 // Lanes of the wavefront whose digit equals this lane's (among `valid`).
@@ -249,17 +252,22 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
     __shared__ int32_t gdst[kRadix];     // global start of each digit's run
     __shared__ int32_t scan_tmp[4];
     __shared__ int32_t dscan_tmp[4];
-    // reorder buffer: first the destinations (4 bytes per position), then
-    // the (key, index) records (8 bytes), then the payload (16 bytes)
+    // reorder buffer: the (key, index) records (8 bytes per position; 16
+    // in the last pass of a batch, which also carries the global id), then
+    // the payload (16 bytes); plus a spare slot
     __shared__ float4 lbuf[kSortTile + 1];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t tile_base = (int64_t)blockIdx.x * kSortTile;
+    // (each XCD takes a contiguous run of tiles: the two ends of a digit's
+    // run, written by neighbouring tiles, meet in one L2, as do the
+    // per-tile digit offsets they read)
+    const int32_t tile = (int32_t)xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t tile_base = (int64_t)tile * kSortTile;
     for (int i = tid; i < W * kRadix; i += kSBlock) (&wcnt[0][0])[i] = 0;
     // this tile's digit offsets (threads 0..255), loaded with the tile
     const int d = tid & (kRadix - 1);
     const int32_t dt = tid < kRadix ? a.dtot[d] : 0;
-    const int32_t gb = tid < kRadix ? a.gbase[(int64_t)d * a.ntiles + blockIdx.x] : 0;
+    const int32_t gb = tid < kRadix ? a.gbase[(int64_t)d * a.ntiles + tile] : 0;
 
     // 0. the whole tile's keys and payload in registers: every global load
     //    of the tile is issued before the first barrier (indices past the
