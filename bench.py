@@ -32,10 +32,12 @@ FP32_PEAK_TFLOPS = 157.3
 
 # Algorithmic FLOPs of the sweep (FMA = 2, other arithmetic = 1; compares,
 # integer work not counted): every candidate pays 3 sub + 1 mul + 2 FMA = 8;
-# every accepted pair of the compensated path pays 72 on average (see the
-# accounting in the design notes).
+# every accepted pair of the compensated path pays about 60 on average: sqrt
+# 1, the spline 10 (q <= 1/2) or 38 (q > 1/2, 28 of them for the error-free
+# h^2 - r^2) weighted 1:7 by volume, 5 for the weighted terms, 4 Kahan
+# accumulations of 4, and 4 for the invariant scale.
 FLOP_PER_CANDIDATE = 8.0
-FLOP_PER_PAIR_COMPENSATED = 72.0
+FLOP_PER_PAIR_COMPENSATED = 60.0
 
 WORKLOADS = {
     "scale_1ppc": ("uniform 2^24 particles, unit cube, r_c=1/256, 256^3 cells (1 ppc)", "scale_1ppc"),

@@ -129,27 +129,34 @@ struct Acc<PI_PREC_PLAIN> {
     __device__ __forceinline__ float r_gz() const { return gz; }
 };
 
+// Kahan's compensated summation: c is the rounding excess of the running
+// sum so far (what was added minus what was meant), taken off the next
+// term; the error of the result is at most about 2u sum |v_i| (u = 2^-24),
+// for rho (positive terms) 2u rho and for G at most 2u A, against the 1e-5
+// tolerance.  4 operations per term, against 7 for TwoSum with a separate
+// error sum.
 template <>
 struct Acc<PI_PREC_COMPENSATED> {
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
-    __device__ __forceinline__ static void ts(float &s, float &c, float v)
+    __device__ __forceinline__ static void ks(float &s, float &c, float v)
     {
-        const float n = s + v;
-        c += two_sum_err(s, v, n);
+        const float y = v - c;
+        const float n = s + y;
+        c = (n - s) - y;
         s = n;
     }
     __device__ __forceinline__ void add(float a, float bx, float by, float bz)
     {
-        ts(s0, c0, a);
-        ts(s1, c1, bx);
-        ts(s2, c2, by);
-        ts(s3, c3, bz);
+        ks(s0, c0, a);
+        ks(s1, c1, bx);
+        ks(s2, c2, by);
+        ks(s3, c3, bz);
     }
-    __device__ __forceinline__ float r_rho() const { return s0 + c0; }
-    __device__ __forceinline__ float r_gx() const { return s1 + c1; }
-    __device__ __forceinline__ float r_gy() const { return s2 + c2; }
-    __device__ __forceinline__ float r_gz() const { return s3 + c3; }
+    __device__ __forceinline__ float r_rho() const { return s0 - c0; }
+    __device__ __forceinline__ float r_gx() const { return s1 - c1; }
+    __device__ __forceinline__ float r_gy() const { return s2 - c2; }
+    __device__ __forceinline__ float r_gz() const { return s3 - c3; }
 };
 
 template <>
