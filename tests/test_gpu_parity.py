@@ -98,6 +98,9 @@ SMALL = {
     "dense_cell": lambda: _dense_cell(),
     # 1500 particles in 48^3 cells: long empty gaps between runs
     "sparse": lambda: synth.box_system(1500, 48, seed=42, lattice_log2=18),
+    # ten 4096-key sort tiles, the last one ragged: the tile-to-workgroup
+    # map over the 8 XCDs has a remainder (10 = 8 + 2)
+    "ten_sort_tiles": lambda: synth.box_system(9 * 4096 + 123, 26, seed=43, lattice_log2=18),
 }
 
 
