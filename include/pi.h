@@ -351,6 +351,12 @@ typedef struct pi_kernel_time {
 } pi_kernel_time;
 
 pi_status pi_timing_enable(pi_ctx *ctx, int32_t on);
+/* Restrict timing to the launches whose kernel name (as pi_timing_read
+ * reports it) equals `name`; NULL or "" times every launch again.  Each
+ * timed launch adds two event records to its stream, which costs device time
+ * between kernels, so a measurement of one kernel inside a timed loop times
+ * that kernel alone.  Returns PI_EINVAL for a name longer than 47 bytes. */
+pi_status pi_timing_only(pi_ctx *ctx, const char *name);
 /* Fill out[0 .. *n_out) (at most `max` records, in first-launch order). */
 pi_status pi_timing_read(pi_ctx *ctx, pi_kernel_time *out, int32_t max, int32_t *n_out);
 pi_status pi_timing_reset(pi_ctx *ctx);

@@ -24,6 +24,7 @@ struct pi_timing {
     std::vector<double> total_ms;
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
+    std::string only; // if not empty: time only launches of this name
 
     int slot_of(const char *name)
     {
@@ -72,6 +73,10 @@ void *pi_timer_begin(pi_ctx *ctx, hipStream_t s, const char *name)
     if (!p) return nullptr;
     {
         std::lock_guard<std::mutex> g(t->mu);
+        if (!t->only.empty() && t->only != name) {
+            delete p;
+            return nullptr;
+        }
         if (t->pending.size() > 4096) t->drain();
         p->slot = t->slot_of(name);
         p->a = t->get_event();
@@ -107,6 +112,15 @@ extern "C" pi_status pi_timing_enable(pi_ctx *ctx, int32_t on)
 {
     if (!ctx || !ctx->timing) return PI_EINVAL;
     ctx->timing_on = on ? 1 : 0;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_timing_only(pi_ctx *ctx, const char *name)
+{
+    if (!ctx || !ctx->timing) return PI_EINVAL;
+    if (name && strlen(name) >= sizeof(pi_kernel_time::name)) return PI_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->timing->mu);
+    ctx->timing->only = name ? name : "";
     return PI_OK;
 }
 

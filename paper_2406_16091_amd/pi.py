@@ -128,6 +128,7 @@ _SIGS = [
     ("pi_timing_read", ctypes.c_int32, [_P, ctypes.POINTER(pi_kernel_time), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int32)]),
     ("pi_timing_reset", ctypes.c_int32, [_P]),
+    ("pi_timing_only", ctypes.c_int32, [_P, ctypes.c_char_p]),
 ]
 
 # Every symbol include/pi.h declares (checked by the CPU test suite).
@@ -389,6 +390,11 @@ def pi_server_stats(server) -> dict:
 
 def pi_timing_enable(ctx, on=True):
     _check(_lib().pi_timing_enable(ctx, 1 if on else 0), "pi_timing_enable")
+
+
+def pi_timing_only(ctx, name=None):
+    """Time only the launches of kernel `name` (None: every launch)."""
+    _check(_lib().pi_timing_only(ctx, name.encode() if name else None), "pi_timing_only")
 
 
 def pi_timing_reset(ctx):

@@ -412,3 +412,41 @@ def test_full_size_parity(dev, name):
     else:
         assert ds.invariants()["pairs"] == int(res["count"].astype(np.int64).sum())
     ds.close()
+
+
+def test_timing_only_times_one_kernel(dev):
+    """pi_timing_only: with a kernel name set, only that kernel's launches
+    are bracketed by events (the bench's timed steps rely on it)."""
+    from paper_2406_16091_amd import pi
+    s = SMALL["tiny"]()
+    ds = dev.DeviceSystem(s)
+    ctx = ds.ctx.handle
+
+    def step():
+        ds.bin()
+        ds.interact(sweep="nolds", tile=(0, 0, 0), order="original")
+
+    step()
+    ds.sync()
+    pi.pi_timing_reset(ctx)
+    pi.pi_timing_only(ctx, None)
+    pi.pi_timing_enable(ctx, True)
+    step()
+    ds.sync()
+    pi.pi_timing_enable(ctx, False)
+    every = pi.pi_timing_read(ctx)
+    sweep = [k for k in every if k.startswith("k_sweep")]
+    assert len(sweep) == 1 and len(every) > 2, every
+    pi.pi_timing_reset(ctx)
+    pi.pi_timing_only(ctx, sweep[0])
+    pi.pi_timing_enable(ctx, True)
+    for _ in range(3):
+        step()
+    ds.sync()
+    pi.pi_timing_enable(ctx, False)
+    only = pi.pi_timing_read(ctx)
+    pi.pi_timing_only(ctx, None)
+    assert list(only) == sweep and only[sweep[0]][0] == 3 and only[sweep[0]][1] > 0, only
+    with pytest.raises(Exception):
+        pi.pi_timing_only(ctx, "k" * 48)
+    ds.close()
