@@ -118,6 +118,19 @@ __device__ __forceinline__ int sys_of_particle(const SysDev *sys, int nsys, int6
     return lo;
 }
 
+// The same, for e known to lie in one of the systems lo .. hi (particles
+// are stored in system order, so those of one sort tile lie between the
+// systems of its first and last particle, mostly one system: then no load).
+__device__ __forceinline__ int sys_of_particle_in(const SysDev *sys, int lo, int hi, int64_t e)
+{
+    ++hi; // sys[lo].first <= e < sys[hi].first (hi may be one past the table)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sys[mid].first <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // System owning global cell key.
 __device__ __forceinline__ int sys_of_cell(const SysDev *sys, int nsys, uint32_t key)
 {
@@ -158,12 +171,26 @@ struct SortArgs {
     uint32_t *err;
 };
 
-// Global cell key of caller particle e at position (x, y, z).
+// Systems of the first and last particle of the sort tile starting at
+// particle `base` (batch mode).
+struct TileSys {
+    int lo, hi;
+};
+
+__device__ __forceinline__ TileSys tile_systems(const SortArgs &a, int64_t base)
+{
+    const int64_t end = min(base + (int64_t)kSortTile, (int64_t)a.n) - 1;
+    return TileSys{sys_of_particle(a.sys, a.nsys, base), sys_of_particle(a.sys, a.nsys, end)};
+}
+
+// Global cell key of caller particle e (of the tile whose systems are ts)
+// at position (x, y, z).
 template <bool BATCH>
-__device__ __forceinline__ uint32_t key_at(const SortArgs &a, int64_t e, float x, float y, float z)
+__device__ __forceinline__ uint32_t key_at(const SortArgs &a, const TileSys &ts, int64_t e, float x, float y,
+                                           float z)
 {
     if (!BATCH) return cell_key(x, y, z, a.g, a.err);
-    const SysDev &s = a.sys[sys_of_particle(a.sys, a.nsys, e)];
+    const SysDev &s = a.sys[sys_of_particle_in(a.sys, ts.lo, ts.hi, e)];
     return (uint32_t)s.cell_base + cell_key(x, y, z, s.g, a.err);
 }
 
@@ -182,6 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(SortArgs a)
     const int64_t last = (int64_t)a.n - 1;
     uint32_t key[kSortItems];
     if (FIRST) {
+        const TileSys ts = BATCH ? tile_systems(a, base) : TileSys{0, 0};
         float px[kSortItems], py[kSortItems], pz[kSortItems];
 #pragma unroll
         for (int q = 0; q < kSortItems; ++q) {
@@ -192,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(SortArgs a)
         }
 #pragma unroll
         for (int q = 0; q < kSortItems; ++q)
-            key[q] = key_at<BATCH>(a, min(base + q * kBlock + threadIdx.x, last), px[q], py[q], pz[q]);
+            key[q] = key_at<BATCH>(a, ts, min(base + q * kBlock + threadIdx.x, last), px[q], py[q], pz[q]);
     } else {
 #pragma unroll
         for (int q = 0; q < kSortItems; ++q) key[q] = a.kv_in[min(base + q * kBlock + threadIdx.x, last)].x;
@@ -299,8 +327,9 @@ __global__ __launch_bounds__(kSBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
         }
     }
     if (FIRST) {
+        const TileSys ts = BATCH ? tile_systems(a, tile_base) : TileSys{0, 0};
 #pragma unroll
-        for (int r = 0; r < kSItems; ++r) key[r] = key_at<BATCH>(a, min(elem(r), last_e), px[r], py[r], pz[r]);
+        for (int r = 0; r < kSItems; ++r) key[r] = key_at<BATCH>(a, ts, min(elem(r), last_e), px[r], py[r], pz[r]);
     }
     __syncthreads();
 
