@@ -29,6 +29,8 @@ struct pi_batch {
     SysDev *d_sys;              // binning table, caller's order
     SysDev *d_sweep;            // sweep table, grouped by organisation
     KernelConst *d_kcs;         // kernel constants, sweep-table order
+    int32_t *d_hint;            // coarse cell-to-system index (binning)
+    int64_t cap_hint;
     int32_t cap_sys;
     int32_t nsys;
     std::vector<SysDev> h_sys;
@@ -77,6 +79,7 @@ extern "C" pi_status pi_batch_destroy(pi_batch *b)
     if (b->d_sys) (void)hipFree(b->d_sys);
     if (b->d_sweep) (void)hipFree(b->d_sweep);
     if (b->d_kcs) (void)hipFree(b->d_kcs);
+    if (b->d_hint) (void)hipFree(b->d_hint);
     pi_cells_destroy(b->cells);
     delete b;
     return PI_OK;
@@ -96,7 +99,8 @@ pi_status launch_all(pi_batch *b, const float *x, const float *y, const float *z
 {
     GridDev g0;
     memset(&g0, 0, sizeof(g0));
-    pi_status st = pi_bin_systems(b->ctx, b->cells, x, y, z, w, n_total, cells_total, b->nsys, b->d_sys, g0, stream);
+    pi_status st = pi_bin_systems(b->ctx, b->cells, x, y, z, w, n_total, cells_total, b->nsys, b->d_sys, b->d_hint,
+                                  g0, stream);
     if (st != PI_OK) return st;
     for (const BatchGroup &g : b->groups) {
         st = pi_sweep_batch(b->ctx, b->cells, g.count, b->d_sweep + g.first, b->d_kcs + g.first, g.blocks,
@@ -223,6 +227,23 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
             return PI_ENOMEM;
         b->cap_sys = nsys;
     }
+    // coarse cell-to-system index: entry k is the system owning global cell
+    // k << kCellHintShift (the last system past the end)
+    const int64_t nhint = ((cells_total + (1 << kCellHintShift) - 1) >> kCellHintShift) + 1;
+    std::vector<int32_t> hint((size_t)nhint);
+    for (int64_t k = 0, s = 0; k < nhint; ++k) {
+        const int64_t cell = k << kCellHintShift;
+        while (s + 1 < nsys && b->cell_base[s + 1] <= cell) ++s;
+        hint[k] = (int32_t)s;
+    }
+    if (nhint > b->cap_hint) {
+        PI_CHECK_HIP(hipStreamSynchronize(stream));
+        if (b->d_hint) (void)hipFree(b->d_hint);
+        b->d_hint = nullptr;
+        b->cap_hint = 0;
+        if (hipMalloc((void **)&b->d_hint, sizeof(int32_t) * (size_t)nhint) != hipSuccess) return PI_ENOMEM;
+        b->cap_hint = nhint;
+    }
     pi_cells *c = b->cells;
     pi_status st = pi_ensure_capacity(c, n_total, cells_total, stream);
     if (st != PI_OK) return st;
@@ -243,6 +264,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     PI_CHECK_HIP(hipMemcpy(b->d_sys, b->h_sys.data(), sizeof(SysDev) * (size_t)nsys, hipMemcpyHostToDevice));
     PI_CHECK_HIP(hipMemcpy(b->d_sweep, b->h_sweep.data(), sizeof(SysDev) * (size_t)nsys, hipMemcpyHostToDevice));
     PI_CHECK_HIP(hipMemcpy(b->d_kcs, kcs.data(), sizeof(KernelConst) * (size_t)nsys, hipMemcpyHostToDevice));
+    PI_CHECK_HIP(hipMemcpy(b->d_hint, hint.data(), sizeof(int32_t) * (size_t)nhint, hipMemcpyHostToDevice));
     c->n = n_total;
     c->n_cells = cells_total;
     memset(&c->grid, 0, sizeof(c->grid));

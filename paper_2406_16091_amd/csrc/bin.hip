@@ -131,10 +131,13 @@ __device__ __forceinline__ int sys_of_particle_in(const SysDev *sys, int lo, int
     return lo;
 }
 
-// System owning global cell key.
-__device__ __forceinline__ int sys_of_cell(const SysDev *sys, int nsys, uint32_t key)
+// System owning global cell key, between the two coarse-index entries
+// around it (systems have at least one cell, so a block of 2^10 cells spans
+// few of them).
+__device__ __forceinline__ int sys_of_cell(const SysDev *sys, const int32_t *hint, uint32_t key)
 {
-    int lo = 0, hi = nsys;
+    const uint32_t blk = key >> kCellHintShift;
+    int lo = hint[blk], hi = hint[blk + 1] + 1; // sys[lo].cell_base <= key < sys[hi].cell_base
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if ((uint32_t)sys[mid].cell_base <= key) lo = mid; else hi = mid;
@@ -149,6 +152,7 @@ struct SortArgs {
     GridDev g;
     const SysDev *sys; // batch mode: system table (nsys entries), else null
     int32_t nsys;
+    const int32_t *cell_hint; // batch mode: coarse cell-to-system index
     // the first pass reads the caller's arrays
     const float *x, *y, *z, *w;
     // later passes read the previous pass's records: (cell id, original
@@ -255,7 +259,7 @@ __device__ __forceinline__ uint32_t to_cell_relative(const SortArgs &a, uint32_t
     GridDev g = a.g;
     uint32_t lc = key;
     if (BATCH) {
-        const SysDev &sd = a.sys[sys_of_cell(a.sys, a.nsys, key)];
+        const SysDev &sd = a.sys[sys_of_cell(a.sys, a.cell_hint, key)];
         lc = key - (uint32_t)sd.cell_base;
         g = sd.g;
     }
@@ -625,7 +629,7 @@ bool pi_grid_valid(const pi_grid *g)
 // systems with cells_total cells in all.
 pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const float *y, const float *z,
                          const float *w, int64_t n, int64_t nc, int32_t nsys, const SysDev *d_sys,
-                         const GridDev &g0, hipStream_t stream)
+                         const int32_t *d_cell_hint, const GridDev &g0, hipStream_t stream)
 {
     const bool batch = nsys > 0;
     if (n > 0) {
@@ -640,6 +644,7 @@ pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const flo
         a.ntiles = ntiles;
         a.g = g0;
         a.sys = d_sys;
+        a.cell_hint = d_cell_hint;
         a.nsys = nsys;
         a.x = x;
         a.y = y;
@@ -736,7 +741,7 @@ extern "C" pi_status pi_bin(pi_ctx *ctx, pi_cells *cells, const float *x, const 
     g.pad = 0;
     grid_set_magic(g);
 
-    return pi_bin_systems(ctx, cells, x, y, z, w, n, nc, 0, nullptr, g, stream);
+    return pi_bin_systems(ctx, cells, x, y, z, w, n, nc, 0, nullptr, nullptr, g, stream);
 }
 
 pi_status pi_split_records(pi_ctx *ctx, pi_cells *cells)

@@ -206,6 +206,12 @@ pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDe
 // (bin.hip), on the stream of its last binning.
 pi_status pi_split_records(pi_ctx *ctx, pi_cells *cells);
 
+// Coarse cell-to-system index of a batch: entry b is the system owning
+// global cell b << kCellHintShift (entries 0 .. ceil(cells_total / 2^shift)
+// inclusive, the last ones the last system), so the system of cell c lies
+// between entries c >> shift and (c >> shift) + 1.
+constexpr int kCellHintShift = 10;
+
 pi_status pi_bin_systems(pi_ctx *ctx, pi_cells *cells, const float *x, const float *y, const float *z,
                          const float *w, int64_t n_total, int64_t cells_total, int32_t nsys,
-                         const SysDev *d_sys, const GridDev &g0, hipStream_t stream);
+                         const SysDev *d_sys, const int32_t *d_cell_hint, const GridDev &g0, hipStream_t stream);
