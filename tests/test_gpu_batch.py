@@ -136,3 +136,32 @@ def test_batch_of_512_systems_pair_counts(dev):
         assert inv[i]["pairs"] == int(ref.count.sum()), i
         if i % 64 == 0:
             _check(res[i], ref)
+
+
+def test_batch_of_many_tiny_systems(dev):
+    """600 systems of 1 or 8 cells holding 0-12 particles: one 1024-cell
+    block of the cell-to-system index, and one 4096-particle sort tile, span
+    hundreds of systems.  Binning and sweep checked system by system."""
+    rng = np.random.default_rng(80)
+    systems = []
+    for k in range(600):
+        g = 1 if k % 3 else 2
+        n = int(rng.integers(0, 13))
+        systems.append(synth.box_system(n, g, seed=8000 + k, lattice_log2=18))
+    _say(f"[tiny600] particles {sum(s.n for s in systems)}, cells {sum(s.n_cells for s in systems)}")
+    db = dev.DeviceBatch(systems)
+    db.run()
+    db.sync()
+    res = db.results()
+    inv = db.invariants()
+    binned = db.binned()
+    for i, s in enumerate(systems):
+        b, ref = _ref(s)
+        _check(res[i], ref)
+        assert inv[i]["pairs"] == int(ref.count.sum()), i
+        off, nc, cb = db.offsets[i], s.n_cells, binned["cell_base"][i]
+        assert (binned["counts"][cb:cb + nc] == b.counts).all(), i
+        assert (binned["offsets"][cb:cb + nc + 1] - off == b.offsets).all(), i
+        assert (binned["perm"][off:off + s.n] - off == b.perm).all(), i
+        assert (binned["cell"][off:off + s.n] == b.cell[b.perm]).all(), i
+        assert (binned["xs"][off:off + s.n].view(np.uint32) == b.xs.view(np.uint32)).all(), i
