@@ -44,6 +44,11 @@ struct pi_batch {
     hipGraph_t graph;
     hipGraphExec_t exec;
     hipStream_t graph_stream;
+    // side streams and events that fork the sweep groups off the binning
+    // and join them back (default priority, created on first use)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> done;
+    hipEvent_t binned;
 };
 
 extern "C" pi_status pi_batch_create(pi_ctx *ctx, pi_batch **out)
@@ -80,6 +85,9 @@ extern "C" pi_status pi_batch_destroy(pi_batch *b)
     if (b->d_sweep) (void)hipFree(b->d_sweep);
     if (b->d_kcs) (void)hipFree(b->d_kcs);
     if (b->d_hint) (void)hipFree(b->d_hint);
+    for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+    if (b->binned) (void)hipEventDestroy(b->binned);
     pi_cells_destroy(b->cells);
     delete b;
     return PI_OK;
@@ -93,6 +101,23 @@ void append(std::vector<unsigned char> &v, const void *p, size_t n)
     v.insert(v.end(), c, c + n);
 }
 
+// Side streams and events for the fork of launch_all (created outside any
+// graph capture).
+pi_status ensure_side(pi_batch *b)
+{
+    const size_t ng = b->groups.size();
+    if (!b->binned) PI_CHECK_HIP(hipEventCreateWithFlags(&b->binned, hipEventDisableTiming));
+    while (b->side.size() + 1 < ng) {
+        hipStream_t sst = nullptr;
+        PI_CHECK_HIP(hipStreamCreateWithFlags(&sst, hipStreamNonBlocking));
+        b->side.push_back(sst);
+        hipEvent_t ev = nullptr;
+        PI_CHECK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        b->done.push_back(ev);
+    }
+    return PI_OK;
+}
+
 pi_status launch_all(pi_batch *b, const float *x, const float *y, const float *z, const float *w, int64_t n_total,
                      int64_t cells_total, const pi_interact_opts &o, float *rho, float *gx, float *gy, float *gz,
                      int32_t *count, pi_invariants *inv, hipStream_t stream)
@@ -102,11 +127,31 @@ pi_status launch_all(pi_batch *b, const float *x, const float *y, const float *z
     pi_status st = pi_bin_systems(b->ctx, b->cells, x, y, z, w, n_total, cells_total, b->nsys, b->d_sys, b->d_hint,
                                   g0, stream);
     if (st != PI_OK) return st;
-    for (const BatchGroup &g : b->groups) {
-        st = pi_sweep_batch(b->ctx, b->cells, g.count, b->d_sweep + g.first, b->d_kcs + g.first, g.blocks,
-                            g.part_base, g.tile, o, rho, gx, gy, gz, count, inv, stream);
-        if (st != PI_OK) return st;
+    // The groups write disjoint outputs and partial records, so on a real
+    // stream they run side by side: group 0 on `stream`, the others on side
+    // streams forked after the binning and joined back (small groups then
+    // fill the GPU together instead of one after another).  The null
+    // stream launches them in order.
+    const size_t ng = b->groups.size();
+    const bool fork = stream != nullptr && ng > 1;
+    if (fork) {
+        if (!b->binned || b->side.size() < ng - 1) return PI_EINVAL; // ensure_side() not called
+        PI_CHECK_HIP(hipEventRecord(b->binned, stream));
     }
+    for (size_t i = 0; i < ng; ++i) {
+        const BatchGroup &g = b->groups[i];
+        hipStream_t gs = stream;
+        if (fork && i > 0) {
+            gs = b->side[i - 1];
+            PI_CHECK_HIP(hipStreamWaitEvent(gs, b->binned, 0));
+        }
+        st = pi_sweep_batch(b->ctx, b->cells, g.count, b->d_sweep + g.first, b->d_kcs + g.first, g.blocks,
+                            g.part_base, g.tile, o, rho, gx, gy, gz, count, inv, gs);
+        if (st != PI_OK) return st;
+        if (fork && i > 0) PI_CHECK_HIP(hipEventRecord(b->done[i - 1], gs));
+    }
+    if (fork)
+        for (size_t i = 1; i < ng; ++i) PI_CHECK_HIP(hipStreamWaitEvent(stream, b->done[i - 1], 0));
     return PI_OK;
 }
 
@@ -274,6 +319,8 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     if (!stream) // the null stream cannot be captured: launch directly
         return launch_all(b, x, y, z, w, n_total, cells_total, o, rho, gx, gy, gz, count, inv, stream);
 
+    pi_status sst = ensure_side(b);
+    if (sst != PI_OK) return sst;
     const int was_timing = ctx->timing_on;
     ctx->timing_on = 0; // no event records inside a captured graph
     pi_status lst = PI_OK;

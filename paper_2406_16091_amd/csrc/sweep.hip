@@ -1083,15 +1083,17 @@ uint64_t tune_key(int prec, int64_t n, double ppc, bool batch)
     return (uint64_t)prec + 4ull * (uint64_t)kn + 256ull * (uint64_t)kp + (batch ? (1ull << 30) : 0ull);
 }
 
-// Time every compiled organisation on this system (second of two runs,
-// without invariants) and return the fastest; the outputs in `a` are
-// overwritten.  The static default is timed first and a later organisation
+// Time every compiled organisation on this system (second of two runs, with
+// the invariant partials when the call computes them, since they change the
+// ranking: at 1 per cell the 7x7x5 tile is 5% faster than 6x6x6 without
+// them and 5% slower with them) and return the fastest; the outputs and
+// partial records in `a` are overwritten.  The static default is timed first and a later organisation
 // displaces the current best only when it is faster by more than 5%, so that
 // near-ties (within run-to-run noise) resolve the same way every time.
-int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, hipStream_t s)
+int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, bool inv, hipStream_t s)
 {
     SweepArgs a = a0;
-    a.partials = nullptr;
+    if (!inv) a.partials = nullptr;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1110,7 +1112,7 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, hipSt
         bool ok = true;
         for (int rep = 0; rep < 2 && ok; ++rep) {
             ok = hipEventRecord(e0, s) == hipSuccess;
-            launch_sweep_prec<false>(ctx, prec, false, cand, a, s, nblk);
+            launch_sweep_prec<false>(ctx, prec, inv, cand, a, s, nblk);
             ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
                  hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
         }
@@ -1125,7 +1127,8 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, hipSt
     return best;
 }
 
-pi_status tuned_tile(pi_ctx *ctx, const SweepArgs &a, int prec, int64_t n, double ppc, hipStream_t s, int *tile)
+pi_status tuned_tile(pi_ctx *ctx, const SweepArgs &a, int prec, int64_t n, double ppc, bool inv, hipStream_t s,
+                     int *tile)
 {
     pi_tuner *t = ctx->tuner;
     *tile = pick_tile_default(ppc);
@@ -1141,7 +1144,7 @@ pi_status tuned_tile(pi_ctx *ctx, const SweepArgs &a, int prec, int64_t n, doubl
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PI_OK;
-    const int best = time_candidates(ctx, a, prec, *tile, s);
+    const int best = time_candidates(ctx, a, prec, *tile, inv, s);
     if (best < 0) return PI_EDEVICE;
     std::lock_guard<std::mutex> g(t->mu);
     t->choice[key] = best;
@@ -1199,7 +1202,7 @@ extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t
         a.rho = a.gx = a.gy = a.gz = nullptr;
         a.count = nullptr;
         PI_CHECK_HIP(hipSetDevice(ctx->device));
-        pi_status st = tuned_tile(ctx, a, precision, n, ppc, (hipStream_t)stream, &tile);
+        pi_status st = tuned_tile(ctx, a, precision, n, ppc, false, (hipStream_t)stream, &tile);
         if (st != PI_OK) return st;
     }
     memset(out, 0, sizeof(*out));
@@ -1266,11 +1269,6 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
         return PI_OK;
     }
 
-    if (o.sweep == PI_SWEEP_AUTO) {
-        pi_status ts = tuned_tile(ctx, a, o.precision, n, ppc, stream, &tile);
-        if (ts != PI_OK) return ts;
-    }
-
     // enough partial records for any tiling of this grid
     unsigned nblk = 0;
     const bool want_inv = inv != nullptr;
@@ -1288,6 +1286,10 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
             mc->cap_partials = need;
             a.partials = (InvPartial *)mc->partials;
         }
+    }
+    if (o.sweep == PI_SWEEP_AUTO) {
+        pi_status ts = tuned_tile(ctx, a, o.precision, n, ppc, want_inv, stream, &tile);
+        if (ts != PI_OK) return ts;
     }
     launch_sweep_prec<false>(ctx, o.precision, want_inv, tile, a, stream, nblk);
     if (want_inv) {
