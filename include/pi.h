@@ -103,7 +103,10 @@ pi_status pi_cells_destroy(pi_cells *cells);
  * (returned by pi_sync); the results of that call are then unspecified (the
  * particle is put in the last cell so that every kernel stays in bounds).
  * Buffers may be (re)allocated here; when they grow, the call first waits
- * for the object's previous stream.
+ * for the object's previous stream.  A call that returns an error leaves the
+ * object without a binned system: pi_interact, pi_tuner_choice and
+ * pi_cells_get_view then return PI_ESTATE (and launch nothing) until a
+ * pi_bin on it succeeds.
  */
 pi_status pi_bin(pi_ctx *ctx, pi_cells *cells,
                  const float *x, const float *y, const float *z, const float *w,
@@ -180,8 +183,18 @@ typedef struct pi_invariants {
  * with the cubic B-spline of support h = rc, q = r/h, sigma = 8/(pi h^3):
  *   W = sigma (6q^3 - 6q^2 + 1) for q <= 1/2, 2 sigma (1-q)^3 for q < 1.
  * Terms are accumulated in a fixed canonical order (neighbour cells in
- * (dz, dy, dx) lexicographic order, sources in sorted order), so every sweep
- * organisation gives bit-identical outputs.
+ * (dz, dy, dx) lexicographic order, sources in sorted order).
+ * Exactness.  When the origin, the cell width and every coordinate are
+ * multiples of one power of two 2^-p and every coordinate, measured from the
+ * origin, stays below 2^(24-p) in magnitude, the cell-relative coordinates
+ * and every pair difference are exact in float32: the neighbour counts then
+ * equal the exact predicate r_ij < rc on the float32 inputs, and every sweep
+ * organisation gives bit-identical outputs.  Otherwise each cell-relative
+ * coordinate is rounded once (and once more where a tile stages it relative
+ * to its halo corner): a pair with |r_ij - rc| <= 2^-19 cell_w may then be
+ * counted differently from the exact predicate, and organisations may
+ * differ in the last bits of the float outputs (all within the stated
+ * float tolerance).
  * Outputs are caller-owned device arrays of n entries (n of the last
  * pi_bin); any of rho, gx, gy, gz, count may be NULL only if all the float
  * outputs are NULL together (count-only sweep).  `inv` (optional, device

@@ -2,7 +2,8 @@
 
     python -m paper_2406_16091_amd.build
 
-Compiles every ``csrc/*.hip`` with hipcc for gfx950 only and links them into
+Compiles every ``csrc/*.hip`` with hipcc for gfx950 only (one object per
+source, in parallel, under ``_build/``) and links them into
 ``paper_2406_16091_amd/libpi.so``.  Flags:
   * ``-ffp-contract=off``: no implicit FMA contraction; every FMA in the
     kernels is written out, so float32 results are exactly what the source
@@ -11,6 +12,7 @@ Compiles every ``csrc/*.hip`` with hipcc for gfx950 only and links them into
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import glob
 import os
 import subprocess
@@ -19,12 +21,13 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpi.so")
+OBJ = os.path.join(os.path.dirname(HERE), "_build")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -35,19 +38,40 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+def _quiet(stderr: str) -> str:
+    return "\n".join(ln for ln in (stderr or "").splitlines()
+                     if "packed-fp32-ops" not in ln and ln.strip())
+
+
+def _compile(src: str) -> tuple[str, subprocess.CompletedProcess]:
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    r = subprocess.run([HIPCC, *FLAGS, "-c", src, "-o", obj], capture_output=True, text=True)
+    return obj, r
+
+
 def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *sources()]
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
     if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
+        print(f"{HIPCC} {' '.join(FLAGS)} -c <src> for {len(srcs)} sources", flush=True)
+    jobs = min(len(srcs), max(1, min(os.cpu_count() or 1, 16)))
+    objs, failed = [], False
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        for src, (obj, r) in zip(srcs, ex.map(_compile, srcs)):
+            objs.append(obj)
+            if r.returncode != 0:
+                failed = True
+                sys.stderr.write(f"--- {src}\n{r.stdout}{r.stderr}")
+            elif verbose and _quiet(r.stderr):
+                sys.stderr.write(_quiet(r.stderr) + "\n")
+    if failed:
+        raise RuntimeError("hipcc failed compiling libpi.so sources")
+    tmp = LIB + ".tmp"
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs],
+                       capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libpi.so")
-    err = [ln for ln in (r.stderr or "").splitlines()
-           if "packed-fp32-ops" not in ln and ln.strip()]
-    if verbose and err:
-        sys.stderr.write("\n".join(err) + "\n")
+        raise RuntimeError("hipcc failed linking libpi.so")
     os.replace(tmp, LIB)
     return LIB
 

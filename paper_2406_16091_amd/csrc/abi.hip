@@ -287,7 +287,7 @@ extern "C" pi_status pi_cells_destroy(pi_cells *c)
 {
     if (!c) return PI_EINVAL;
     (void)hipSetDevice(c->ctx->device);
-    if (c->last_stream || c->binned) (void)hipStreamSynchronize(c->last_stream);
+    if (c->perm || c->counts) (void)hipStreamSynchronize(c->last_stream);
     free_buffers(c);
     if (c->d_err) (void)hipFree(c->d_err);
     free(c);
@@ -310,7 +310,9 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     const bool grow_n = n > c->cap_n || !c->perm;
     const bool grow_c = n_cells > c->cap_cells || !c->counts;
     if (!grow_n && !grow_c) return PI_OK;
-    if (c->binned) PI_CHECK_HIP(hipStreamSynchronize(c->last_stream));
+    // (buffers from an earlier binning may still be read by work queued on
+    // that binning's stream, whether or not it succeeded)
+    if (c->perm || c->counts) PI_CHECK_HIP(hipStreamSynchronize(c->last_stream));
     const int64_t cap_n = grow_n ? grow(n < 64 ? 64 : n, c->cap_n) : c->cap_n;
     const int64_t cap_c = grow_c ? grow(n_cells < 64 ? 64 : n_cells, c->cap_cells) : c->cap_cells;
     const int64_t sort_tiles = (cap_n + 4095) / 4096 + 1;
@@ -345,10 +347,24 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     return PI_OK;
 }
 
+void pi_cells_forget(pi_cells *c)
+{
+    c->binned = false;
+    c->n = 0;
+    c->n_cells = 0;
+    c->soa_stale = false;
+}
+
+bool pi_cells_ready(const pi_cells *c)
+{
+    return c->binned && c->counts && c->offsets && c->perm && c->cell && c->xyzw && c->partials &&
+           c->cap_n >= c->n && c->cap_cells >= c->n_cells;
+}
+
 extern "C" pi_status pi_cells_get_view(pi_cells *c, pi_cells_view *v)
 {
     if (!c || !v) return PI_EINVAL;
-    if (!c->binned) return PI_ESTATE;
+    if (!pi_cells_ready(c) || !c->xs) return PI_ESTATE;
     const pi_status st = pi_split_records(c->ctx, c);
     if (st != PI_OK) return st;
     v->n = c->n;

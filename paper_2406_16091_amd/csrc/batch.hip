@@ -291,7 +291,10 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     }
     pi_cells *c = b->cells;
     pi_status st = pi_ensure_capacity(c, n_total, cells_total, stream);
-    if (st != PI_OK) return st;
+    if (st != PI_OK) {
+        pi_cells_forget(c);
+        return st;
+    }
     if (b->total_blocks + 64 > c->cap_partials) {
         PI_CHECK_HIP(hipStreamSynchronize(stream));
         if (c->partials) (void)hipFree(c->partials);
@@ -299,6 +302,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         const int64_t need = b->total_blocks + 64;
         if (hipMalloc(&c->partials, (size_t)need * 64) != hipSuccess) {
             c->cap_partials = 0;
+            pi_cells_forget(c);
             return PI_ENOMEM;
         }
         c->cap_partials = need;

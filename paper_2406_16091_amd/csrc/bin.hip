@@ -716,6 +716,10 @@ extern "C" pi_status pi_bin(pi_ctx *ctx, pi_cells *cells, const float *x, const 
                             const float *w, int64_t n, const pi_grid *grid, pi_stream stream_)
 {
     if (!ctx || !cells || cells->ctx != ctx) return PI_EINVAL;
+    // whatever happens below, the object no longer holds the previous
+    // system: a failed call leaves it unbinned (sweeps and views then return
+    // PI_ESTATE), a successful one marks the new system binned
+    pi_cells_forget(cells);
     if (n < 0 || n >= ((int64_t)1 << 31)) return PI_EINVAL;
     if (n > 0 && (!x || !y || !z || !w)) return PI_EINVAL;
     if (!pi_grid_valid(grid)) return PI_EINVAL;
@@ -728,20 +732,15 @@ extern "C" pi_status pi_bin(pi_ctx *ctx, pi_cells *cells, const float *x, const 
     cells->n_cells = nc;
     cells->grid = *grid;
     cells->last_stream = stream;
+
+    const GridDev g = grid_dev(*grid);
+    st = pi_bin_systems(ctx, cells, x, y, z, w, n, nc, 0, nullptr, nullptr, g, stream);
+    if (st != PI_OK) {
+        pi_cells_forget(cells);
+        return st;
+    }
     cells->binned = true;
-
-    GridDev g;
-    g.ox = grid->origin[0];
-    g.oy = grid->origin[1];
-    g.oz = grid->origin[2];
-    g.w = grid->cell_w;
-    g.nx = grid->dims[0];
-    g.ny = grid->dims[1];
-    g.nz = grid->dims[2];
-    g.pad = 0;
-    grid_set_magic(g);
-
-    return pi_bin_systems(ctx, cells, x, y, z, w, n, nc, 0, nullptr, nullptr, g, stream);
+    return PI_OK;
 }
 
 pi_status pi_split_records(pi_ctx *ctx, pi_cells *cells)

@@ -156,6 +156,21 @@ inline void grid_set_magic(GridDev &g)
     g.mxy = div_magic((int64_t)g.nx * g.ny);
 }
 
+inline GridDev grid_dev(const pi_grid &grid)
+{
+    GridDev g;
+    g.ox = grid.origin[0];
+    g.oy = grid.origin[1];
+    g.oz = grid.origin[2];
+    g.w = grid.cell_w;
+    g.nx = grid.dims[0];
+    g.ny = grid.dims[1];
+    g.nz = grid.dims[2];
+    g.pad = 0;
+    grid_set_magic(g);
+    return g;
+}
+
 __device__ __forceinline__ uint32_t div_by(uint32_t n, uint64_t m)
 {
     return m ? (uint32_t)__umul64hi((uint64_t)n, m) : n;
@@ -173,6 +188,10 @@ __device__ __forceinline__ bool axis_index(float x, float o, float w, int32_t n,
 }
 
 pi_status pi_ensure_capacity(pi_cells *cells, int64_t n, int64_t n_cells, hipStream_t stream);
+// Mark a cell object as holding no binned system (after a failed binning).
+void pi_cells_forget(pi_cells *cells);
+// Whether every buffer a sweep of the object's binned system reads exists.
+bool pi_cells_ready(const pi_cells *cells);
 
 // One system of a batch, as the batched kernels see it.  Systems are
 // concatenated in order: system s owns input (and sorted) particles
@@ -194,11 +213,25 @@ struct pi_interact_opts;
 KernelConst pi_make_kernel_const(float rc, float cell_w);
 bool pi_tile_shape(int tile_id, int *tx, int *ty, int *tz);
 int pi_pick_tile(const pi_interact_opts &o, double ppc);
+void pi_tile_opts(int tile_id, pi_interact_opts *out);
 int pi_auto_tile(pi_ctx *ctx, int precision, int64_t n, double ppc);
 int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys);
 pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
                          int64_t total_blocks, int64_t part_base, int tile_id, const pi_interact_opts &o, float *rho,
                          float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);
+
+// The sweep of pi_interact (sweep.hip) on a binned system whose invariant
+// partial records live in `partials` (cap_partials records of 64 bytes).
+// With no_alloc the call allocates nothing, waits for nothing and runs no
+// timed tuner trials: AUTO takes the tuner's cached choice or the static
+// rule, and a tiling that needs more records than cap_partials gives
+// PI_ENOMEM (AUTO falls back to the no-LDS sweep first).
+pi_status pi_interact_run(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts &o, float *rho, float *gx,
+                          float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream,
+                          void *partials, int64_t cap_partials, bool no_alloc);
+// Host checks of pi_interact's options and output pointers for n particles.
+pi_status pi_check_interact_opts(const pi_interact_opts &o, int64_t n, const float *rho, const float *gx,
+                                 const float *gy, const float *gz, const int32_t *count, const pi_invariants *inv);
 
 // Host-side binning of a concatenated set of systems (bin.hip): one radix
 // sort over global cell ids; sorted arrays hold local cell ids.

@@ -40,32 +40,54 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 
 // Displace every particle by sigma * N(0,1) per axis (Box-Muller on two
 // uniforms drawn from the counter (seed, step, particle, axis)), reflect at
-// the faces of the box [o, o + L), and round down to the lattice (if > 0).
+// the faces of the box [o, o + L), L = n w, and round the offset from o down
+// to the lattice (if > 0).  The stored coordinate o + v is rounded once more
+// when o is large against L; it is then moved by single ulps until the
+// binning's float32 decision (t = (p - o) / w, inside iff 0 <= t < n) keeps
+// it inside the box.
+__device__ __forceinline__ float keep_inside(float p, float o, float w, int32_t n)
+{
+    for (int it = 0; it < 64; ++it) {
+        const float t = (p - o) / w;
+        if (t >= 0.0f && t < (float)n) return p;
+        p = t < 0.0f ? nextafterf(p, INFINITY) : nextafterf(p, -INFINITY);
+    }
+    return o; // t = 0: the low corner is always inside
+}
+
 __global__ __launch_bounds__(256) void k_jitter(int32_t n, float *x, float *y, float *z, uint64_t seed,
                                                 int32_t step, float sigma, float lattice, float ox, float oy,
-                                                float oz, float lx, float ly, float lz)
+                                                float oz, float w, int32_t nx, int32_t ny, int32_t nz)
 {
     const int32_t i = (int32_t)(blockIdx.x * 256 + threadIdx.x);
     if (i >= n) return;
     float *p[3] = {x, y, z};
     const float o[3] = {ox, oy, oz};
-    const float L[3] = {lx, ly, lz};
+    const int32_t dims[3] = {nx, ny, nz};
     for (int a = 0; a < 3; ++a) {
+        const float L = (float)dims[a] * w;
         const uint64_t r = mix64(seed ^ mix64(((uint64_t)step << 40) ^ ((uint64_t)i << 2) ^ (uint64_t)a));
         const float u1 = ((float)(uint32_t)(r >> 40) + 0.5f) * (1.0f / 16777216.0f); // (0, 1)
         const float u2 = (float)(uint32_t)(r & 0xffffffu) * (1.0f / 16777216.0f);     // [0, 1)
         const float g = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
         float v = p[a][i] - o[a] + sigma * g;
         if (v < 0.0f) v = -v;
-        if (v >= L[a]) v = 2.0f * L[a] - v;
+        if (v >= L) v = 2.0f * L - v;
         if (lattice > 0.0f) {
             v = floorf(v / lattice) * lattice;
-            v = fminf(fmaxf(v, 0.0f), L[a] - lattice);
+            v = fminf(fmaxf(v, 0.0f), L - lattice);
         } else {
-            v = fminf(fmaxf(v, 0.0f), L[a] * (1.0f - 1e-7f));
+            v = fminf(fmaxf(v, 0.0f), L * (1.0f - 1e-7f));
         }
-        p[a][i] = o[a] + v;
+        p[a][i] = keep_inside(o[a] + v, o[a], w, dims[a]);
     }
+}
+
+// The device error word of a binned system back to zero (a fill kernel, not
+// a memset, so that the sequence stays capturable).
+__global__ void k_clear_err(uint32_t *err)
+{
+    if (threadIdx.x == 0) err[0] = 0u;
 }
 
 } // namespace
@@ -81,7 +103,8 @@ struct Ticket {
     int slot;
     double t_submit, t_start, t_done;
     // pinned host buffer: the inputs (x, y, z, w) on the way in; then the
-    // outputs rho, gx, gy, gz, count, x, y, z and the per-sweep invariants
+    // outputs rho, gx, gy, gz, count, x, y, z, the per-sweep invariants and
+    // the device error word (pinned_size)
     void *pinned;
     size_t pinned_bytes;
 };
@@ -96,6 +119,7 @@ struct Slot {
     float *d_out = nullptr;          // rho, gx, gy, gz, count (5 x cap)
     pi_invariants *d_inv = nullptr;  // [cap_sweeps]
     int64_t cap = 0, cap_sweeps = 0;
+    pi_status launch_status = PI_OK; // error queuing the request (retired with it)
 };
 
 } // namespace
@@ -126,9 +150,22 @@ int64_t footprint_bytes(int64_t n, int64_t nc, int32_t sweeps)
     return 109 * n + 8 * nc + 2 * 64 * (nc + n / 64) + 64 * (int64_t)sweeps + (1 << 20);
 }
 
+// Pinned host buffer of a request: inputs x, y, z, w on the way in; then
+// rho, gx, gy, gz, count, x, y, z (8 arrays of max(n, 1) words), the
+// per-sweep invariants and the device error word.
 size_t pinned_size(int64_t n, int32_t sweeps)
 {
     return (size_t)std::max<int64_t>(1, n) * 32 + sizeof(pi_invariants) * (size_t)sweeps + 256;
+}
+
+pi_invariants *pinned_invariants(void *pin, int64_t n)
+{
+    return (pi_invariants *)((float *)pin + 8 * std::max<int64_t>(n, 1));
+}
+
+uint32_t *pinned_err(void *pin, int64_t n, int32_t sweeps)
+{
+    return (uint32_t *)(pinned_invariants(pin, n) + sweeps);
 }
 
 void *pool_get(pi_server *s, size_t bytes)
@@ -167,8 +204,8 @@ pi_status slot_reserve(pi_server *s, Slot &sl, int64_t n, int32_t sweeps)
     return PI_OK;
 }
 
-// Queue a request's whole sequence on its slot's stream and record the
-// slot's completion event after it.
+// Queue a request's whole sequence on its slot's stream (the caller records
+// the slot's completion event after it).
 pi_status launch_request(pi_server *s, Slot &sl, Ticket *t)
 {
     const pi_request &r = t->req;
@@ -194,33 +231,43 @@ pi_status launch_request(pi_server *s, Slot &sl, Ticket *t)
     o.sweep = r.sweep;
     o.order = PI_ORDER_ORIGINAL;
     const pi_grid &g = r.grid;
+    if (o.sweep == PI_SWEEP_AUTO) {
+        // no timed trials on a request's path: the tuner's cached choice for
+        // the request's class if there is one, else the static rule
+        const double nc = (double)g.dims[0] * g.dims[1] * g.dims[2];
+        pi_tile_opts(pi_auto_tile(s->ctx, r.precision, n, (double)n / nc), &o);
+    }
     for (int32_t k = 0; k < r.n_sweeps; ++k) {
         if (k > 0 && r.jitter_sigma > 0.0f && n > 0)
             PI_LAUNCH(s->ctx, "k_jitter", k_jitter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, q, (int32_t)n,
                       dx, dy, dz, r.seed, k, r.jitter_sigma, r.lattice, g.origin[0], g.origin[1], g.origin[2],
-                      g.dims[0] * g.cell_w, g.dims[1] * g.cell_w, g.dims[2] * g.cell_w);
+                      g.cell_w, g.dims[0], g.dims[1], g.dims[2]);
         st = pi_bin(s->ctx, sl.cells, dx, dy, dz, dw, n, &g, q);
         if (st != PI_OK) return st;
         st = pi_interact(s->ctx, sl.cells, &o, rho, gx, gy, gz, cnt, sl.d_inv + k, q);
         if (st != PI_OK) return st;
     }
     // the inputs were consumed by the first copy; the same pinned buffer
-    // receives rho, gx, gy, gz, count, x, y, z and the invariants
+    // receives rho, gx, gy, gz, count, x, y, z, the invariants and the
+    // device error word (cleared on the stream for the next request)
     if (n > 0) {
         const void *src[8] = {rho, gx, gy, gz, cnt, dx, dy, dz};
         for (int a = 0; a < 8; ++a)
             PI_CHECK_HIP(hipMemcpyAsync(h + (size_t)a * n, src[a], b, hipMemcpyDeviceToHost, q));
     }
-    PI_CHECK_HIP(hipMemcpyAsync(h + 8 * (size_t)std::max<int64_t>(n, 1), sl.d_inv,
+    PI_CHECK_HIP(hipMemcpyAsync(pinned_invariants(t->pinned, n), sl.d_inv,
                                 sizeof(pi_invariants) * (size_t)r.n_sweeps, hipMemcpyDeviceToHost, q));
-    PI_CHECK_HIP(hipEventRecord(sl.done, q));
+    PI_CHECK_HIP(hipMemcpyAsync(pinned_err(t->pinned, n, r.n_sweeps), sl.cells->d_err, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, q));
+    PI_LAUNCH(s->ctx, "k_clear_err", k_clear_err, dim3(1), dim3(64), 0, q, sl.cells->d_err);
+    PI_CHECK_HIP(hipGetLastError());
     return PI_OK;
 }
 
-// One scheduling round (lock held): retire finished requests, then admit
-// queued ones while a slot is free and the budget allows.  Returns whether
-// anything changed.
-bool schedule(pi_server *s)
+// Retire finished requests (lock held; never waits).  A request's status
+// comes from its launch, else from the device error word its stream copied
+// into the ticket's pinned buffer before the completion event.
+bool retire(pi_server *s)
 {
     bool changed = false;
     for (Slot &sl : s->slots) {
@@ -228,8 +275,13 @@ bool schedule(pi_server *s)
         const hipError_t q = hipEventQuery(sl.done);
         if (q == hipErrorNotReady) continue;
         Ticket *t = s->tickets[sl.ticket];
-        pi_status st = q == hipSuccess ? PI_OK : PI_EDEVICE;
-        if (st == PI_OK && sl.cells) st = pi_sync(s->ctx, sl.cells, sl.stream);
+        pi_status st = sl.launch_status;
+        if (st == PI_OK && q != hipSuccess) st = PI_EDEVICE;
+        if (st == PI_OK) {
+            const uint32_t err = *(volatile uint32_t *)pinned_err(t->pinned, t->req.n, t->req.n_sweeps);
+            if (err) st = (err & PI_DERR_RANGE) ? PI_ERANGE : PI_EDEVICE;
+        }
+        if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
         t->status = st;
         t->t_done = now_s();
         t->done = true;
@@ -237,6 +289,13 @@ bool schedule(pi_server *s)
         sl.busy = false;
         changed = true;
     }
+    return changed;
+}
+
+// Admit queued requests in arrival order while a slot is free and the
+// budget allows (lock held): the slots are marked busy and listed in `go`.
+void admit(pi_server *s, std::vector<Slot *> &go)
+{
     while (!s->queue.empty()) {
         Ticket *t = s->tickets[s->queue.front()];
         if (s->in_use + t->footprint > s->opts.hbm_budget) break; // first in, first served
@@ -250,30 +309,48 @@ bool schedule(pi_server *s)
         s->queue.pop_front();
         free_slot->busy = true;
         free_slot->ticket = t->id;
+        free_slot->launch_status = PI_OK;
         t->slot = (int)(free_slot - s->slots.data());
         t->t_start = now_s();
         s->in_use += t->footprint;
-        const pi_status st = launch_request(s, *free_slot, t);
-        if (st != PI_OK) {
-            // nothing more is queued for it; retire it at once
-            (void)hipStreamSynchronize(free_slot->stream);
-            t->status = st;
-            t->t_done = now_s();
-            t->done = true;
-            s->in_use -= t->footprint;
-            free_slot->busy = false;
-        }
-        changed = true;
+        go.push_back(free_slot);
     }
-    return changed;
 }
 
+// The scheduler thread.  Requests are queued on their slots' streams with
+// the lock released (allocations, binning set-up and launches take time;
+// pi_submit, pi_poll and pi_wait stay responsive meanwhile).  Only this
+// thread marks slots busy or free, so the admitted slots stay its own while
+// it launches them.
 void worker_loop(pi_server *s)
 {
     (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
+    std::vector<Slot *> go;
     while (!s->stop) {
-        const bool changed = schedule(s);
+        bool changed = retire(s);
+        go.clear();
+        admit(s, go);
+        if (!go.empty()) {
+            std::vector<Ticket *> ts;
+            for (Slot *sl : go) ts.push_back(s->tickets[sl->ticket]);
+            lk.unlock();
+            for (size_t i = 0; i < go.size(); ++i) {
+                Slot &sl = *go[i];
+                pi_status st = launch_request(s, sl, ts[i]);
+                // the completion event follows whatever was queued, so a
+                // failed request is retired only once its stream is idle
+                if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
+                    (void)hipGetLastError();
+                    (void)hipStreamSynchronize(sl.stream);
+                    (void)hipGetLastError();
+                    if (st == PI_OK) st = PI_EDEVICE;
+                }
+                sl.launch_status = st;
+            }
+            lk.lock();
+            changed = true;
+        }
         if (changed) s->cv.notify_all();
         bool busy = !s->queue.empty();
         for (const Slot &sl : s->slots) busy = busy || sl.busy;
@@ -399,7 +476,7 @@ static void fill_result(const Ticket *t, pi_result *out)
     out->x = h + 5 * n;
     out->y = h + 6 * n;
     out->z = h + 7 * n;
-    const pi_invariants *inv = (const pi_invariants *)(h + 8 * std::max<int64_t>(n, 1));
+    const pi_invariants *inv = pinned_invariants(t->pinned, n);
     out->sweeps = t->req.n_sweeps;
     out->invariants = inv;
     int64_t pairs = 0;

@@ -999,6 +999,22 @@ bool pi_tile_shape(int tile_id, int *tx, int *ty, int *tz)
     return false;
 }
 
+// The explicit options (organisation and tile shape) that run organisation
+// `tile`; precision and order are left as they are.
+void pi_tile_opts(int tile, pi_interact_opts *out)
+{
+    int tx = 0, ty = 0, tz = 0;
+    out->tile[0] = out->tile[1] = out->tile[2] = 0;
+    if (tile > 0 && pi_tile_shape(tile, &tx, &ty, &tz)) {
+        out->sweep = (ty == 1 && tz == 1) ? PI_SWEEP_PENCIL : PI_SWEEP_SUBBOX;
+        out->tile[0] = tx;
+        out->tile[1] = ty;
+        out->tile[2] = tz;
+    } else {
+        out->sweep = tile == kStreamId ? PI_SWEEP_STREAM : PI_SWEEP_NOLDS;
+    }
+}
+
 // Tile id for explicit options; -1 if the shape is not compiled in; AUTO
 // returns the static default (the tuner refines it per system).
 int pi_pick_tile(const pi_interact_opts &o, double ppc)
@@ -1180,7 +1196,7 @@ extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t
                                      pi_stream stream)
 {
     if (!ctx || !cells || !out || cells->ctx != ctx) return PI_EINVAL;
-    if (!cells->binned) return PI_ESTATE;
+    if (!pi_cells_ready(cells)) return PI_ESTATE;
     if (precision < PI_PREC_COMPENSATED || precision > PI_PREC_FP64ACC) return PI_EINVAL;
     const int64_t n = cells->n;
     const double ppc = cells->n_cells > 0 ? (double)n / (double)cells->n_cells : 0.0;
@@ -1207,38 +1223,30 @@ extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t
     }
     memset(out, 0, sizeof(*out));
     out->precision = precision;
-    int tx = 0, ty = 0, tz = 0;
-    if (tile > 0 && pi_tile_shape(tile, &tx, &ty, &tz)) {
-        out->sweep = (ty == 1 && tz == 1) ? PI_SWEEP_PENCIL : PI_SWEEP_SUBBOX;
-        out->tile[0] = tx;
-        out->tile[1] = ty;
-        out->tile[2] = tz;
-    } else {
-        out->sweep = tile == kStreamId ? PI_SWEEP_STREAM : PI_SWEEP_NOLDS;
-    }
+    pi_tile_opts(tile, out);
     return PI_OK;
 }
 
-extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts *opts, float *rho,
-                                 float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv,
-                                 pi_stream stream_)
-{
-    if (!ctx || !cells || cells->ctx != ctx) return PI_EINVAL;
-    if (!cells->binned) return PI_ESTATE;
-    pi_interact_opts o;
-    memset(&o, 0, sizeof(o));
-    if (opts) o = *opts;
-    if (o.precision < PI_PREC_COMPENSATED || o.precision > PI_PREC_FP64ACC) return PI_EINVAL;
-    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_STREAM) return PI_EINVAL;
-    if (o.order != PI_ORDER_SORTED && o.order != PI_ORDER_ORIGINAL) return PI_EINVAL;
-    const bool anyf = rho || gx || gy || gz;
-    const bool allf = rho && gx && gy && gz;
-    if (anyf && !allf) return PI_EINVAL;
-    const int64_t n = cells->n;
-    if (n > 0 && !anyf && !count && !inv) return PI_EINVAL;
-    hipStream_t stream = (hipStream_t)stream_;
-    PI_CHECK_HIP(hipSetDevice(ctx->device));
+namespace {
 
+// Workgroups of one sweep launch of organisation `tile` (as launch_sweep
+// computes them).
+int64_t sweep_blocks(int tile, int64_t n, int32_t nx, int32_t ny, int32_t nz)
+{
+    int tx = 0, ty = 0, tz = 0;
+    if (tile > 0 && tile != kStreamId && pi_tile_shape(tile, &tx, &ty, &tz))
+        return (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return b > 0 ? b : 1;
+}
+
+} // namespace
+
+pi_status pi_interact_run(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts &o, float *rho, float *gx,
+                          float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream,
+                          void *partials, int64_t cap_partials, bool no_alloc)
+{
+    const int64_t n = cells->n;
     const double ppc = cells->n_cells > 0 ? (double)n / (double)cells->n_cells : 0.0;
     int tile = pi_pick_tile(o, ppc);
     if (tile < 0) return PI_EINVAL;
@@ -1260,7 +1268,7 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
     a.gy = gy;
     a.gz = gz;
     a.count = count;
-    a.partials = (InvPartial *)cells->partials;
+    a.partials = (InvPartial *)partials;
     a.k = pi_make_kernel_const(cells->grid.rc, cells->grid.cell_w);
 
     if (n == 0) {
@@ -1269,12 +1277,25 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
         return PI_OK;
     }
 
-    // enough partial records for any tiling of this grid
     unsigned nblk = 0;
     const bool want_inv = inv != nullptr;
-    if (want_inv) {
+    // partial records: one per workgroup, then the stage-1 records
+    auto records = [&](int t) {
+        const int64_t b = sweep_blocks(t, n, a.nx, a.ny, a.nz);
+        return b + (b + kInvRun - 1) / kInvRun;
+    };
+    if (no_alloc) {
+        if (o.sweep == PI_SWEEP_AUTO) {
+            // the tuner's cached choice or the static rule (no trials); no
+            // LDS when a tiling needs more partial records than there are
+            tile = pi_auto_tile(ctx, o.precision, n, ppc);
+            if (want_inv && records(tile) > cap_partials) tile = 0;
+        }
+        if (want_inv && records(tile) > cap_partials) return PI_ENOMEM;
+    } else if (want_inv) {
+        // enough partial records for any tiling of this grid
         const int64_t need = 2 * (cells->n_cells + (n + kBlock - 1) / kBlock) + 64;
-        if (need > cells->cap_partials) {
+        if (need > cap_partials) {
             pi_cells *mc = const_cast<pi_cells *>(cells);
             PI_CHECK_HIP(hipStreamSynchronize(stream));
             if (mc->partials) (void)hipFree(mc->partials);
@@ -1287,7 +1308,7 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
             a.partials = (InvPartial *)mc->partials;
         }
     }
-    if (o.sweep == PI_SWEEP_AUTO) {
+    if (!no_alloc && o.sweep == PI_SWEEP_AUTO) {
         pi_status ts = tuned_tile(ctx, a, o.precision, n, ppc, want_inv, stream, &tile);
         if (ts != PI_OK) return ts;
     }
@@ -1303,4 +1324,33 @@ extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_in
     }
     PI_CHECK_HIP(hipGetLastError());
     return PI_OK;
+}
+
+pi_status pi_check_interact_opts(const pi_interact_opts &o, int64_t n, const float *rho, const float *gx,
+                                 const float *gy, const float *gz, const int32_t *count, const pi_invariants *inv)
+{
+    if (o.precision < PI_PREC_COMPENSATED || o.precision > PI_PREC_FP64ACC) return PI_EINVAL;
+    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_STREAM) return PI_EINVAL;
+    if (o.order != PI_ORDER_SORTED && o.order != PI_ORDER_ORIGINAL) return PI_EINVAL;
+    const bool anyf = rho || gx || gy || gz;
+    const bool allf = rho && gx && gy && gz;
+    if (anyf && !allf) return PI_EINVAL;
+    if (n > 0 && !anyf && !count && !inv) return PI_EINVAL;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts *opts, float *rho,
+                                 float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv,
+                                 pi_stream stream_)
+{
+    if (!ctx || !cells || cells->ctx != ctx) return PI_EINVAL;
+    if (!pi_cells_ready(cells)) return PI_ESTATE;
+    pi_interact_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    const pi_status vs = pi_check_interact_opts(o, cells->n, rho, gx, gy, gz, count, inv);
+    if (vs != PI_OK) return vs;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    return pi_interact_run(ctx, cells, o, rho, gx, gy, gz, count, inv, (hipStream_t)stream_, cells->partials,
+                           cells->cap_partials, false);
 }

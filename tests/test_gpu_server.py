@@ -140,6 +140,40 @@ def test_admission_and_errors(lib):
         pi.pi_server_destroy(server)
 
 
+def test_jitter_keeps_particles_in_a_far_box(lib):
+    """A box far from the origin of coordinates ([1000, 1016) x [-500,
+    -484) x [30, 46)): positions near 1000 have a coarser float32 spacing
+    (2^-14) than the requested lattice, so the stored coordinate rounds once
+    more; every jittered particle must still be inside the box by the
+    binning's own float32 decision (no PI_ERANGE), and the results must
+    match the oracle on the final positions."""
+    pi, device = lib
+    ctx = device.Context.get(0).handle
+    base = synth.box_system(6000, 16, seed=96, lattice_log2=14)
+    o = (1000.0, -500.0, 30.0)
+    x, y, z = (np.float32(o[0]) + base.x, np.float32(o[1]) + base.y, np.float32(o[2]) + base.z)
+    s = synth.System("far", x.astype(np.float32), y.astype(np.float32), z.astype(np.float32), base.w, o,
+                     base.dims, 1.0, 1.0)
+    server = pi.pi_server_create(ctx, max_slots=2, n_streams=2)
+    try:
+        # large steps (half a cell) push many particles against the far faces
+        t = pi.pi_submit(server, pi.make_request(s, n_sweeps=6, jitter_sigma=0.5, lattice=2.0 ** -16, seed=7))
+        res = pi.pi_wait(server, t)
+        assert res["status"] == pi.PI_OK
+        for v, oo, d in ((res["x"], o[0], 16), (res["y"], o[1], 16), (res["z"], o[2], 16)):
+            t32 = (v - np.float32(oo)) / np.float32(1.0)
+            assert np.all(t32 >= 0) and np.all(t32 < d)
+        fs = synth.System("final", res["x"], res["y"], res["z"], s.w, o, s.dims, 1.0, 1.0)
+        b = oracle.bin_particles(fs.x, fs.y, fs.z, fs.w, fs.origin, fs.dims, fs.cell_w, fs.rc)
+        ref = oracle.sweep(fs.x, fs.y, fs.z, fs.w, fs.dims, fs.rc, b)
+        assert (res["count"].astype(np.int64) == ref.count).all()
+        assert np.all(np.abs(res["rho"].astype(np.float64) - ref.rho) <= TOL * ref.rho)
+        assert res["pairs_per_sweep"][-1] == int(ref.count.sum())
+        pi.pi_release(server, t)
+    finally:
+        pi.pi_server_destroy(server)
+
+
 def test_tuner_choice_is_what_auto_runs(lib):
     pi, device = lib
     s = synth.uniform_unit_cube(1 << 17, -5, seed=95)   # 4 per cell
