@@ -43,10 +43,13 @@
  * Precision: every float input is widened to double.  On inputs that lie on
  * a common power-of-two lattice (all workloads used here) the coordinate
  * differences and r^2 are exact in double, so the cutoff test r^2 < r_c^2 is
- * the exact real predicate.  The cell index is a float32 decision, taken in
- * float32 exactly as the GPU path takes it: t = (x - o) / w rounded to
- * float32, cell = floor(t), and the particle is inside the box iff
- * 0 <= t < n on that axis.
+ * the exact real predicate.  The cell index follows the reading taken of the
+ * paper's "cell from its physical position" (Sec. 2) together with its
+ * statement that every computation is done in single precision (Sec. 7.1):
+ * the axis index is a float32 decision, t = (x - o) / w with each operation
+ * rounded to float32, cell = floor(t), and the particle is inside the box
+ * iff 0 <= t < n on that axis.  Fig. 1's geometry, whose cell width is not a
+ * power of two, pins it.
  */
 #include <math.h>
 #include <stdint.h>
