@@ -190,11 +190,16 @@ typedef struct pi_invariants {
  * and every pair difference are exact in float32: the neighbour counts then
  * equal the exact predicate r_ij < rc on the float32 inputs, and every sweep
  * organisation gives bit-identical outputs.  Otherwise each cell-relative
- * coordinate is rounded once (and once more where a tile stages it relative
- * to its halo corner): a pair with |r_ij - rc| <= 2^-19 cell_w may then be
- * counted differently from the exact predicate, and organisations may
- * differ in the last bits of the float outputs (all within the stated
- * float tolerance).
+ * coordinate is rounded once, and the pair differences once or twice more
+ * in the frame the organisation computes in: the results are then those of
+ * the method on positions displaced by a small delta per pair, with, per
+ * axis, delta <= 4 ulp(cell_w) for NOLDS and STREAM and
+ * delta <= 2 ulp(cell_w) + ulp(E) for a tile whose halo box spans E cell
+ * widths on that axis (T + 2 for a tile of T cells; a 254-cell pencil thus
+ * loses about 8 bits along x).  A pair with |r_ij - rc| <= |delta| may be
+ * counted differently from the exact predicate, and the floats may move by
+ * what such a displacement changes (|delta| A_i for rho_i) beyond the
+ * accuracy stated for exact inputs.
  * Outputs are caller-owned device arrays of n entries (n of the last
  * pi_bin); any of rho, gx, gy, gz, count may be NULL only if all the float
  * outputs are NULL together (count-only sweep).  `inv` (optional, device
