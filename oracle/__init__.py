@@ -12,7 +12,10 @@ Functions follow the paper (arXiv 2406.16091):
     the cubic B-spline kernel, over all targets or a subset;
   * :func:`brute` -- the plain O(N^2) definition of Sec. 2 (all pairs i != j
     with r_ij < r_c), no grid;
-  * :func:`kernel` -- the B-spline W(r) and dW/dr.
+  * :func:`kernel` -- the B-spline W(r) and dW/dr;
+  * :func:`sweep_pairfn` / :func:`brute_pairfn` -- the kernels of the paper's
+    timing experiments (Sec. 7.1 Lennard-Jones with softening, Fig. 8's low-
+    and high-FLOP kernels) over every candidate of the 27-cell stencil.
 """
 from __future__ import annotations
 
@@ -74,6 +77,12 @@ def _load():
         lib.oracle_brute.argtypes = [I64, P, P, P, P, ctypes.c_float, I64, P,
                                      P, P, P, P, P, P, ctypes.c_int]
         lib.oracle_brute.restype = ctypes.c_int
+        lib.oracle_sweep_pairfn.argtypes = [ctypes.c_int, I64, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, P, P, P, I64, P, P, P, P, ctypes.c_int]
+        lib.oracle_sweep_pairfn.restype = ctypes.c_int
+        lib.oracle_brute_pairfn.argtypes = [ctypes.c_int, I64, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, P, I64, P, P, P, P, ctypes.c_int]
+        lib.oracle_brute_pairfn.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -190,6 +199,53 @@ def brute(x, y, z, w, rc, targets=None, nthreads: int = 0) -> SweepOut:
     if st != OK:
         raise OracleError(st)
     return SweepOut(rho, gx, gy, gz, a, cnt, None)
+
+
+PAIRFN = {"lj": 1, "lowflop": 2, "highflop": 3}
+
+
+@dataclass
+class PairfnOut:
+    v: np.ndarray       # float64 [t]  sum_j K(i, j) over the candidates
+    ascale: np.ndarray  # float64 [t]  sum_j |terms| (condition scale)
+    cand: np.ndarray    # int64 [t]    candidates j != i in the clipped 27-cell stencil
+
+
+def sweep_pairfn(kind, x, y, z, dims, sigma, eps, e0, binned: Binned, targets=None,
+                 nthreads: int = 0) -> PairfnOut:
+    """The paper's timing-experiment kernels (Sec. 7.1 Lennard-Jones with
+    softening; Fig. 8's low- and high-FLOP kernels) over every candidate of
+    the 27-cell stencil, cell-list order."""
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.shape[0]
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    v, a = np.empty(nt, np.float64), np.empty(nt, np.float64)
+    cand = np.empty(nt, np.int64)
+    st = _load().oracle_sweep_pairfn(PAIRFN[kind], n, _p(x), _p(y), _p(z), _p(d), float(sigma), float(eps),
+                                     float(e0), _p(binned.cell), _p(binned.offsets), _p(binned.perm),
+                                     nt, _p(tg), _p(v), _p(a), _p(cand), int(nthreads))
+    if st != OK:
+        raise OracleError(st)
+    return PairfnOut(v, a, cand)
+
+
+def brute_pairfn(kind, x, y, z, dims, sigma, eps, e0, cell, targets=None, nthreads: int = 0) -> PairfnOut:
+    """The same sums from the neighbour-cell definition, O(N^2), no cell list."""
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.shape[0]
+    d = np.ascontiguousarray(dims, dtype=np.int32)
+    c = np.ascontiguousarray(cell, dtype=np.int32)
+    tg = None if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    nt = n if tg is None else tg.shape[0]
+    v, a = np.empty(nt, np.float64), np.empty(nt, np.float64)
+    cand = np.empty(nt, np.int64)
+    st = _load().oracle_brute_pairfn(PAIRFN[kind], n, _p(x), _p(y), _p(z), _p(d), float(sigma), float(eps),
+                                     float(e0), _p(c), nt, _p(tg), _p(v), _p(a), _p(cand), int(nthreads))
+    if st != OK:
+        raise OracleError(st)
+    return PairfnOut(v, a, cand)
 
 
 def invariants(w, out: SweepOut):

@@ -337,6 +337,151 @@ int oracle_brute(int64_t n, const float *x, const float *y, const float *z, cons
     return ORACLE_OK;
 }
 
+/*
+ * The pair kernels of the paper's timing experiments (Sec. 7.1, Fig. 8),
+ * evaluated on every candidate pair: every source j != i whose cell lies in
+ * the clipped 27-cell neighbourhood of the target's cell.  The interactions
+ * those experiments count are exactly these candidates (Table 1's first
+ * column; the x axis of the performance figure is interactions computed per
+ * particle), so no cutoff test is applied.
+ *
+ *   kind 1, Lennard-Jones with softening (Sec. 7.1): with
+ *       u = sigma^2 / (r^2 + eps^2),
+ *       K = 4 e0 (u^6 - u^3)        [= 4 e0 ((sigma/s)^12 - (sigma/s)^6),
+ *                                     s^2 = r^2 + eps^2]
+ *     and condition scale A = 4 e0 (u^6 + u^3) (sum of the magnitudes).
+ *   kind 2, the low-FLOP kernel of Fig. 8, a sum of the positions:
+ *       K = (x_i - x_j) + (y_i - y_j) + (z_i - z_j),
+ *       A = |x_i - x_j| + |y_i - y_j| + |z_i - z_j|.
+ *   kind 3, the high-FLOP kernel of Fig. 8, Lennard-Jones followed by 150
+ *     more FLOP: 75 multiply-adds y <- y a + b on the Lennard-Jones value
+ *     with run-time a = 1, b = 0 (so K and A equal those of kind 1).
+ * v_i = sum_j K(i, j); a_i = sum_j A(i, j); cand_i = number of such j.
+ */
+#define PAIRFN_LJ 1
+#define PAIRFN_LOWFLOP 2
+#define PAIRFN_HIGHFLOP 3
+
+typedef struct {
+    double sigma, eps, e0; /* Lennard-Jones length, softening and depth */
+    double a, b;           /* the high-FLOP kernel's multiply-add constants */
+} pairfn_params;
+
+static void pairfn_value(int kind, double dx, double dy, double dz, const pairfn_params *p,
+                         double *K, double *A)
+{
+    if (kind == PAIRFN_LOWFLOP) {
+        *K = dx + dy + dz;
+        *A = fabs(dx) + fabs(dy) + fabs(dz);
+        return;
+    }
+    const double s2 = dx * dx + dy * dy + dz * dz + p->eps * p->eps;
+    const double u = p->sigma * p->sigma / s2;
+    const double u3 = u * u * u;
+    double k = 4.0 * p->e0 * (u3 * u3 - u3);
+    *A = 4.0 * fabs(p->e0) * (u3 * u3 + u3);
+    if (kind == PAIRFN_HIGHFLOP)
+        for (int t = 0; t < 75; ++t) k = fma(k, p->a, p->b);
+    *K = k;
+}
+
+/* Cell-list form: the 27 cells of each target in (dz, dy, dx) order, the
+ * sources of a cell in sorted order (offsets/perm/cell from oracle_bin). */
+int oracle_sweep_pairfn(int kind, int64_t n, const float *x, const float *y, const float *z,
+                        const int32_t dims[3], double sigma, double eps, double e0,
+                        const int32_t *cell, const int32_t *offsets, const int32_t *perm,
+                        int64_t n_targets, const int64_t *targets,
+                        double *v, double *ascale, int64_t *cand, int nthreads)
+{
+    if (n < 0 || kind < PAIRFN_LJ || kind > PAIRFN_HIGHFLOP) return ORACLE_EINVAL;
+    const pairfn_params p = {sigma, eps, e0, 1.0, 0.0};
+    const int64_t nt = targets ? n_targets : n;
+    const int32_t nx = dims[0], ny = dims[1], nz = dims[2];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = targets ? targets[t] : t;
+        const int32_t c = cell[i];
+        const int32_t ix = c % nx, iy = (c / nx) % ny, iz = c / (nx * ny);
+        const double xi = x[i], yi = y[i], zi = z[i];
+        double r_v = 0.0, r_a = 0.0;
+        int64_t r_cand = 0;
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int32_t cz = iz + dz;
+            if (cz < 0 || cz >= nz) continue;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int32_t cy = iy + dy;
+                if (cy < 0 || cy >= ny) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int32_t cx = ix + dx;
+                    if (cx < 0 || cx >= nx) continue;
+                    const int64_t nc = cx + (int64_t)nx * (cy + (int64_t)ny * cz);
+                    for (int64_t k = offsets[nc]; k < offsets[nc + 1]; ++k) {
+                        const int64_t j = perm[k];
+                        if (j == i) continue;
+                        double K, A;
+                        pairfn_value(kind, xi - (double)x[j], yi - (double)y[j], zi - (double)z[j], &p, &K, &A);
+                        r_v += K;
+                        r_a += A;
+                        r_cand += 1;
+                    }
+                }
+            }
+        }
+        v[t] = r_v;
+        if (ascale) ascale[t] = r_a;
+        if (cand) cand[t] = r_cand;
+    }
+    return ORACLE_OK;
+}
+
+/* The same sums from the definition with no cell list: every j != i whose
+ * cell (oracle_cells) differs from the target's by at most one on each axis,
+ * sources in ascending original index.  O(N^2). */
+int oracle_brute_pairfn(int kind, int64_t n, const float *x, const float *y, const float *z,
+                        const int32_t dims[3], double sigma, double eps, double e0, const int32_t *cell,
+                        int64_t n_targets, const int64_t *targets,
+                        double *v, double *ascale, int64_t *cand, int nthreads)
+{
+    if (n < 0 || kind < PAIRFN_LJ || kind > PAIRFN_HIGHFLOP) return ORACLE_EINVAL;
+    const pairfn_params p = {sigma, eps, e0, 1.0, 0.0};
+    const int64_t nt = targets ? n_targets : n;
+    const int32_t nx = dims[0], ny = dims[1];
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = targets ? targets[t] : t;
+        const int32_t ix = cell[i] % nx, iy = (cell[i] / nx) % ny, iz = cell[i] / (nx * ny);
+        const double xi = x[i], yi = y[i], zi = z[i];
+        double r_v = 0.0, r_a = 0.0;
+        int64_t r_cand = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const int32_t jx = cell[j] % nx, jy = (cell[j] / nx) % ny, jz = cell[j] / (nx * ny);
+            if (abs(jx - ix) > 1 || abs(jy - iy) > 1 || abs(jz - iz) > 1) continue;
+            double K, A;
+            pairfn_value(kind, xi - (double)x[j], yi - (double)y[j], zi - (double)z[j], &p, &K, &A);
+            r_v += K;
+            r_a += A;
+            r_cand += 1;
+        }
+        v[t] = r_v;
+        if (ascale) ascale[t] = r_a;
+        if (cand) cand[t] = r_cand;
+    }
+    return ORACLE_OK;
+}
+
 /* Number of OpenMP threads a parallel region started now would use. */
 int oracle_max_threads(void)
 {

@@ -31,7 +31,7 @@ MUTANTS = [
     ("one_minus_q_missing_factor", "(h * h - d2) / (h * (h + r))", "(h * h - d2) / (h * h)", 0, 1),
     ("sweep_cutoff_not_strict", "if (!(d2 < rc2)) continue;", "if (!(d2 <= rc2)) continue;", 0, 2),
     ("brute_cutoff_not_strict", "if (!(d2 < rc2)) continue;", "if (!(d2 <= rc2)) continue;", 1, 2),
-    ("sweep_lost_lower_z_layer", "for (int dz = -1; dz <= 1; ++dz) {", "for (int dz = 0; dz <= 1; ++dz) {", 0, 1),
+    ("sweep_lost_lower_z_layer", "for (int dz = -1; dz <= 1; ++dz) {", "for (int dz = 0; dz <= 1; ++dz) {", 0, 2),
     ("sweep_self_not_excluded", "if (j == i) continue;\n                        r_cand += 1;",
      "r_cand += 1;", 0, 1),
     ("sweep_gradient_sign", "const double ddx = xi - (double)x[j];", "const double ddx = (double)x[j] - xi;", 0, 2),
@@ -45,8 +45,28 @@ MUTANTS = [
     ("brute_ascale_signed", "r_a += wj * fabs(dW);", "r_a += wj * dW;", 1, 2),
     ("sweep_target_weight", "const double wj = (double)w[j];", "const double wj = (double)w[i];", 0, 2),
     ("sweep_gradient_not_over_r", "const double f = wj * dW / r;", "const double f = wj * dW;", 0, 2),
-    ("sweep_cell_decode_axes_swapped", "iy = (c / nx) % ny", "iy = (c / ny) % nx", 0, 1),
+    ("sweep_cell_decode_axes_swapped", "iy = (c / nx) % ny", "iy = (c / ny) % nx", 0, 2),
     ("max_per_cell_ignored", "if (counts[c] > mc) mc = counts[c];", "if (counts[c] > mc) mc = 1;", 0, 1),
+    # the timing-experiment kernels (Lennard-Jones, low- and high-FLOP)
+    ("lj_attractive_sign", "double k = 4.0 * p->e0 * (u3 * u3 - u3);", "double k = 4.0 * p->e0 * (u3 * u3 + u3);",
+     0, 1),
+    ("lj_missing_four", "double k = 4.0 * p->e0 *", "double k = p->e0 *", 0, 1),
+    ("lj_no_softening", " + p->eps * p->eps;", ";", 0, 1),
+    ("lj_cube_as_square", "const double u3 = u * u * u;", "const double u3 = u * u;", 0, 1),
+    ("lowflop_sign", "*K = dx + dy + dz;", "*K = dx + dy - dz;", 0, 1),
+    ("lowflop_ascale_signed", "*A = fabs(dx) + fabs(dy) + fabs(dz);", "*A = dx + dy + dz;", 0, 1),
+    ("highflop_changes_value", "k = fma(k, p->a, p->b);", "k = fma(k, p->a, p->a);", 0, 1),
+    ("pairfn_sweep_self_included", "if (j == i) continue;\n                        double K, A;", "double K, A;",
+     0, 1),
+    ("pairfn_sweep_lost_upper_x_cell", "for (int dx = -1; dx <= 1; ++dx) {\n                    const int32_t cx = ix + dx;\n"
+     "                    if (cx < 0 || cx >= nx) continue;\n                    const int64_t nc = cx + (int64_t)nx * (cy + (int64_t)ny * cz);\n"
+     "                    for (int64_t k = offsets[nc]; k < offsets[nc + 1]; ++k) {\n                        const int64_t j = perm[k];\n"
+     "                        if (j == i) continue;\n                        double K, A;",
+     "for (int dx = -1; dx <= 0; ++dx) {\n                    const int32_t cx = ix + dx;\n"
+     "                    if (cx < 0 || cx >= nx) continue;\n                    const int64_t nc = cx + (int64_t)nx * (cy + (int64_t)ny * cz);\n"
+     "                    for (int64_t k = offsets[nc]; k < offsets[nc + 1]; ++k) {\n                        const int64_t j = perm[k];\n"
+     "                        if (j == i) continue;\n                        double K, A;", 0, 1),
+    ("pairfn_brute_reach_two_cells", "abs(jx - ix) > 1", "abs(jx - ix) > 2", 0, 1),
 ]
 
 

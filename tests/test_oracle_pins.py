@@ -420,3 +420,137 @@ def test_uniform_statistics_tiny(oracle_lib):
     assert o.rho[inner].mean() == pytest.approx((n - 1) * 1.0, rel=0.02)
     assert o.count.sum() == pytest.approx(1.325e5, rel=0.02)
     assert o.cand.mean() == pytest.approx((n - 1) * ((3 * 32 - 2) / 32 ** 2) ** 3, rel=0.01)
+
+
+# ---------------------------------------------------------------- timing-experiment kernels
+# Sec. 7.1 (Lennard-Jones with softening) and Fig. 8 (5- and 168-FLOP
+# kernels), evaluated on every candidate of the 27-cell stencil.
+
+K6 = 2.0 ** -6
+
+
+def _pair_system(points, dims=(8, 8, 8), cw=2.0 ** -3):
+    p = np.array(points, np.float64)
+    x, y, z = (p.T).astype(np.float32)
+    assert np.all(np.float64(x) == p[:, 0])  # exact in float32
+    w = np.ones(len(p), np.float32)
+    b = oracle.bin_particles(x, y, z, w, (0, 0, 0), dims, cw, cw)
+    return x, y, z, dims, b
+
+
+def _lj(kind, pts, sigma, eps, e0, **kw):
+    x, y, z, dims, b = _pair_system(pts, **kw)
+    return oracle.sweep_pairfn(kind, x, y, z, dims, sigma, eps, e0, b)
+
+
+def test_lj_zero_where_softened_distance_is_sigma(oracle_lib):
+    """3-4-5: r = 4k on an axis, eps = 3k, sigma = 5k gives r^2 + eps^2 =
+    sigma^2, u = 1 and K = 4 e0 (1 - 1) = 0; the condition scale is 8 e0."""
+    base = np.array([3, 3, 3]) * 2.0 ** -3 + 2.0 ** -5
+    for ax in range(3):
+        pts = [base, base.copy()]
+        pts[1][ax] += 4 * K6
+        o = _lj("lj", pts, 5 * K6, 3 * K6, 0.75)
+        assert o.v.tolist() == [0.0, 0.0]
+        assert o.ascale.tolist() == [6.0, 6.0]
+        assert o.cand.tolist() == [1, 1]
+
+
+def test_lj_closed_form_value(oracle_lib):
+    """r = k, eps = k, sigma = 2k: u = 4k^2 / 2k^2 = 2 and
+    K = 4 e0 (2^6 - 2^3) = 224 e0, A = 4 e0 (2^6 + 2^3) = 288 e0."""
+    base = np.array([2, 5, 1]) * 2.0 ** -3 + 2.0 ** -4
+    pts = [base, base + np.array([0, 0, K6])]
+    o = _lj("lj", pts, 2 * K6, K6, 0.75)
+    assert o.v.tolist() == [224 * 0.75] * 2
+    assert o.ascale.tolist() == [288 * 0.75] * 2
+
+
+def test_lj_softening_keeps_coincident_pairs_finite(oracle_lib):
+    """r = 0: u = sigma^2 / eps^2 = 4, K = 4 e0 (4096 - 64) = 16128 e0."""
+    base = np.array([1, 1, 1]) * 2.0 ** -3 + 2.0 ** -5
+    o = _lj("lj", [base, base], 2 * K6, K6, 1.0)
+    assert o.v.tolist() == [16128.0, 16128.0]
+
+
+def test_lj_minimum_depth_and_place(oracle_lib):
+    """K(s) = 4 e0 ((sigma/s)^12 - (sigma/s)^6) with s^2 = r^2 + eps^2 has
+    its minimum -e0 at s = 2^(1/6) sigma: sample two-particle systems
+    across r and find both."""
+    sigma, eps, e0 = 0.04, 0.01, 1.25
+    rs = np.arange(1, 4000) * 2.0 ** -16      # r in (0, 0.061], exact in float32
+    base = np.array([2, 2, 2]) * 2.0 ** -3
+    vals = []
+    for r in rs:
+        o = _lj("lj", [base, base + np.array([r, 0, 0])], sigma, eps, e0)
+        vals.append(o.v[0])
+    vals = np.array(vals)
+    k = int(np.argmin(vals))
+    s_min = math.sqrt(rs[k] ** 2 + eps ** 2)
+    assert abs(s_min - 2.0 ** (1 / 6) * sigma) < 2.0 ** -15
+    assert vals[k] == pytest.approx(-e0, rel=1e-6)
+    # repulsive inside s = sigma, attractive outside, tending to 0
+    s = np.sqrt(rs ** 2 + eps ** 2)
+    assert np.all(vals[s < sigma * (1 - 1e-6)] > 0) and np.all(vals[s > sigma * (1 + 1e-6)] < 0)
+    assert np.all(np.diff(vals[k:]) > 0) and np.all(np.diff(vals[:k + 1]) < 0)
+
+
+def test_lj_equilateral_triangle(oracle_lib):
+    """k (1,1,0), k (1,0,1), k (0,1,1) are pairwise sqrt(2) k apart: each
+    target sums two equal terms; with eps = k, sigma = 2k: s^2 = 3k^2,
+    u = 4/3, v = 2 * 4 e0 ((4/3)^6 - (4/3)^3)."""
+    from fractions import Fraction
+    base = np.array([3, 4, 5]) * 2.0 ** -3 + 2.0 ** -5
+    pts = [base + K6 * np.array(d) for d in ((1, 1, 0), (1, 0, 1), (0, 1, 1))]
+    o = _lj("lj", pts, 2 * K6, K6, 1.0)
+    u = Fraction(4, 3)
+    expect = float(2 * 4 * (u ** 6 - u ** 3))
+    assert np.allclose(o.v, expect, rtol=1e-14, atol=0)
+
+
+def test_lowflop_closed_form_and_antisymmetry(oracle_lib):
+    """v_i = sum_j (x_i - x_j) + (y_i - y_j) + (z_i - z_j): two particles
+    give +-(dx + dy + dz); over a system the sum of v is exactly 0 (each
+    term is exact in double on the lattice and cancels with its mirror)."""
+    base = np.array([1, 2, 3]) * 2.0 ** -3 + 2.0 ** -5
+    d = np.array([3, -5, 7]) * 2.0 ** -9
+    o = _lj("lowflop", [base, base + d], 1.0, 1.0, 1.0)
+    assert o.v.tolist() == [-(3 - 5 + 7) * 2.0 ** -9, (3 - 5 + 7) * 2.0 ** -9]
+    assert o.ascale.tolist() == [15 * 2.0 ** -9] * 2
+    s = synth.box_system(4000, 9, seed=31, lattice_log2=18)
+    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    o = oracle.sweep_pairfn("lowflop", s.x, s.y, s.z, s.dims, 1, 1, 1, b)
+    assert float(o.v.sum()) == 0.0 and np.abs(o.v).max() > 1.0
+
+
+def test_highflop_equals_lj(oracle_lib):
+    """The high-FLOP kernel's 75 multiply-adds with a = 1, b = 0 leave the
+    Lennard-Jones value unchanged."""
+    s = synth.box_system(3000, 8, seed=32, lattice_log2=18)
+    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    a = oracle.sweep_pairfn("lj", s.x, s.y, s.z, s.dims, 0.45, 0.2, 1.0, b)
+    h = oracle.sweep_pairfn("highflop", s.x, s.y, s.z, s.dims, 0.45, 0.2, 1.0, b)
+    assert (a.v == h.v).all() and (a.ascale == h.ascale).all() and (a.cand == h.cand).all()
+
+
+@pytest.mark.parametrize("case", ["uniform", "clustered", "flat_grid"])
+def test_pairfn_cell_list_equals_neighbour_cell_definition(oracle_lib, case):
+    """The cell-list sweep against the definition with no cell list (every
+    j != i whose cell is within one cell on each axis), and its candidate
+    counts against the B-spline sweep's (pinned by Table 1)."""
+    if case == "uniform":
+        s = synth.box_system(3000, 7, seed=33, lattice_log2=18)
+    elif case == "clustered":
+        s = synth.box_system(3000, 9, seed=34, lattice_log2=18, clustered_blobs=3)
+    else:
+        s0 = synth.box_system(2500, 9, seed=35, lattice_log2=18)
+        keep = s0.z < 2.0
+        s = synth.System("flat", s0.x[keep], s0.y[keep], s0.z[keep], s0.w[keep], (0, 0, 0), (9, 9, 2), 1.0, 1.0)
+    b = oracle.bin_particles(s.x, s.y, s.z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    ref = oracle.sweep(s.x, s.y, s.z, s.w, s.dims, s.rc, b)
+    for kind, (sg, ep) in (("lj", (0.5, 0.25)), ("lowflop", (1, 1)), ("highflop", (0.3, 0.3))):
+        cl = oracle.sweep_pairfn(kind, s.x, s.y, s.z, s.dims, sg, ep, 0.9, b)
+        br = oracle.brute_pairfn(kind, s.x, s.y, s.z, s.dims, sg, ep, 0.9, b.cell)
+        assert (cl.cand == br.cand).all() and (cl.cand == ref.cand).all()
+        assert np.all(np.abs(cl.v - br.v) <= 1e-13 * br.ascale + 1e-300)
+        assert np.allclose(cl.ascale, br.ascale, rtol=1e-13, atol=0)
