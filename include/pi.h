@@ -210,6 +210,33 @@ pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts
                       float *rho, float *gx, float *gy, float *gz, int32_t *count,
                       pi_invariants *inv, pi_stream stream);
 
+/*
+ * pi_interact that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments, outputs and results are those
+ * of pi_interact (bit-identical for the same organisation).  Differences:
+ *   - the FP64 invariant partials (one 64-byte record per sweep workgroup,
+ *     plus one per 1024 of them) go to a fixed device array of
+ *     PI_NOALLOC_SCRATCH_RECORDS records (32 MiB), one copy per GPU the
+ *     library runs on, held until the process ends;
+ *   - a call whose invariants need more records returns PI_ENOMEM and queues
+ *     nothing (a tile sweep takes one workgroup per tile, NOLDS and STREAM
+ *     one per 256 particles); with PI_SWEEP_AUTO the no-LDS sweep is taken
+ *     instead when the tiling would not fit; inv == NULL needs no records;
+ *   - AUTO never runs timed trials (it takes the tuner's cached choice for
+ *     the system's class, else the static rule), the call never waits, and
+ *     it records no timing events (pi_timing_*).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (no record needs to start at zero: each one read is first written
+ * by the same call).  Calls whose work overlaps on one GPU -- on different
+ * streams, or from different threads -- race on the array: queue them on
+ * one stream.
+ */
+#define PI_NOALLOC_SCRATCH_RECORDS (1 << 19)
+pi_status pi_interact_noalloc(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts *opts,
+                              float *rho, float *gx, float *gy, float *gz, int32_t *count,
+                              pi_invariants *inv, pi_stream stream);
+
 /* Wait for `stream` and return the first device-detected error latched on
  * `cells` (PI_ERANGE for out-of-box particles), then clear it.  cells may be
  * NULL (only waits). */

@@ -13,6 +13,8 @@
 
 // ------------------------------------------------------------- kernel timing
 
+thread_local bool pi_tls_no_timing = false;
+
 struct pi_timing {
     struct Pending {
         int slot;
@@ -202,6 +204,13 @@ extern "C" pi_status pi_ctx_create(int32_t device, pi_ctx **out)
         delete c->tuner;
         free(c);
         return PI_ENOMEM;
+    }
+    const pi_status ss = pi_noalloc_scratch_setup(device, &c->scratch);
+    if (ss != PI_OK) {
+        delete c->timing;
+        delete c->tuner;
+        free(c);
+        return ss;
     }
     if (const char *m = getenv("PI_AUTOTUNE")) {
         if (!strcmp(m, "off") || !strcmp(m, "0")) c->tuner->mode = PI_TUNE_STATIC;

@@ -38,7 +38,16 @@ struct pi_ctx {
     volatile int timing_on;
     pi_timing *timing;
     pi_tuner *tuner;
+    void *scratch; // this device's copy of the fixed sweep scratch (sweep.hip)
 };
+
+// Device address of the fixed scratch array of pi_interact_noalloc on
+// `device`, which must be current (looked up once per device and kept).
+pi_status pi_noalloc_scratch_setup(int device, void **out);
+
+// Set on a thread while it queues work that must not record timing events
+// (event records take events from a pool that may need to create one).
+extern thread_local bool pi_tls_no_timing;
 
 // Kernel timing: bracket one launch with events on its stream when enabled.
 void *pi_timer_begin(pi_ctx *ctx, hipStream_t s, const char *name);
@@ -46,7 +55,7 @@ void pi_timer_end(pi_ctx *ctx, hipStream_t s, void *tok);
 
 #define PI_LAUNCH(ctx, name, kern, grid, block, shmem, stream, ...)                 \
     do {                                                                          \
-        void *_tok = (ctx)->timing_on ? pi_timer_begin((ctx), (stream), (name)) : nullptr; \
+        void *_tok = ((ctx)->timing_on && !pi_tls_no_timing) ? pi_timer_begin((ctx), (stream), (name)) : nullptr; \
         hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);         \
         if (_tok) pi_timer_end((ctx), (stream), _tok);                             \
     } while (0)

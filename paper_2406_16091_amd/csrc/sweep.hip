@@ -1339,6 +1339,57 @@ pi_status pi_check_interact_opts(const pi_interact_opts &o, int64_t n, const flo
     return PI_OK;
 }
 
+// ------------------------------------------------------------------ no-alloc sweep
+//
+// The invariant partial records of pi_interact_noalloc live in one fixed
+// array per device, so the call never allocates.  In host code `scratch`
+// names a host-side stand-in, not device memory: kernels get the device
+// address looked up once per device by pi_noalloc_scratch_setup.
+
+static __device__ __align__(256) InvPartial scratch[PI_NOALLOC_SCRATCH_RECORDS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+} // namespace
+
+pi_status pi_noalloc_scratch_setup(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return PI_EINVAL;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return pi_hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                        "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return PI_OK;
+}
+
+extern "C" pi_status pi_interact_noalloc(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts *opts,
+                                         float *rho, float *gx, float *gy, float *gz, int32_t *count,
+                                         pi_invariants *inv, pi_stream stream_)
+{
+    if (!ctx || !cells || cells->ctx != ctx) return PI_EINVAL;
+    if (!ctx->scratch) return PI_ESTATE;
+    if (!pi_cells_ready(cells)) return PI_ESTATE;
+    pi_interact_opts o;
+    memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    const pi_status vs = pi_check_interact_opts(o, cells->n, rho, gx, gy, gz, count, inv);
+    if (vs != PI_OK) return vs;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    pi_tls_no_timing = true;
+    const pi_status st = pi_interact_run(ctx, cells, o, rho, gx, gy, gz, count, inv, (hipStream_t)stream_,
+                                         ctx->scratch, PI_NOALLOC_SCRATCH_RECORDS, true);
+    pi_tls_no_timing = false;
+    return st;
+}
+
 extern "C" pi_status pi_interact(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts *opts, float *rho,
                                  float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv,
                                  pi_stream stream_)

@@ -22,6 +22,7 @@ PI_OK, PI_EINVAL, PI_ENOMEM, PI_ERANGE, PI_EDEVICE, PI_EAGAIN, PI_ENOTFOUND, PI_
 PI_PREC_COMPENSATED, PI_PREC_PLAIN, PI_PREC_FP64ACC = 0, 1, 2
 PI_SWEEP_AUTO, PI_SWEEP_NOLDS, PI_SWEEP_PENCIL, PI_SWEEP_SUBBOX, PI_SWEEP_STREAM = 0, 1, 2, 3, 4
 PI_ORDER_SORTED, PI_ORDER_ORIGINAL = 0, 1
+PI_NOALLOC_SCRATCH_RECORDS = 1 << 19
 
 PRECISIONS = {"compensated": PI_PREC_COMPENSATED, "plain": PI_PREC_PLAIN, "fp64acc": PI_PREC_FP64ACC}
 SWEEPS = {"auto": PI_SWEEP_AUTO, "nolds": PI_SWEEP_NOLDS, "pencil": PI_SWEEP_PENCIL,
@@ -107,6 +108,8 @@ _SIGS = [
     ("pi_bin", ctypes.c_int32, [_P, _P, _P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(pi_grid), _P]),
     ("pi_cells_get_view", ctypes.c_int32, [_P, ctypes.POINTER(pi_cells_view)]),
     ("pi_interact", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_interact_opts), _P, _P, _P, _P, _P, _P, _P]),
+    ("pi_interact_noalloc", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_interact_opts), _P, _P, _P, _P, _P, _P,
+                                             _P]),
     ("pi_sync", ctypes.c_int32, [_P, _P, _P]),
     ("pi_batch_create", ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
     ("pi_batch_destroy", ctypes.c_int32, [_P]),
@@ -242,6 +245,12 @@ def pi_interact(ctx, cells, opts, rho, gx, gy, gz, count, inv=None, stream=None)
     _check(_lib().pi_interact(ctx, cells, ctypes.byref(opts) if opts is not None else None,
                               _ptr(rho), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(count), _ptr(inv),
                               _stream(stream)), "pi_interact")
+
+
+def pi_interact_noalloc(ctx, cells, opts, rho, gx, gy, gz, count, inv=None, stream=None):
+    _check(_lib().pi_interact_noalloc(ctx, cells, ctypes.byref(opts) if opts is not None else None,
+                                      _ptr(rho), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(count), _ptr(inv),
+                                      _stream(stream)), "pi_interact_noalloc")
 
 
 def pi_sync(ctx, cells=None, stream=None):
