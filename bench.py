@@ -18,6 +18,12 @@ each timed launch adds two event records to the stream (about 0.1 ms per
 step over the 13 launches of a step).  The roofline's duration is that
 kernel's mean over the timed steps.  The CPU baseline is the FP64 oracle
 (oracle/) timed on the host.
+
+The same line carries the rest of the metric: `batch` (512 independent
+systems in one captured graph launch against one launch per system) and
+`serve` (the request server: saturation and one-at-a-time rates, and
+p50/p99 latency under Poisson arrivals at fixed rates); --no-batch and
+--no-serve skip them.
 """
 from __future__ import annotations
 
@@ -36,14 +42,16 @@ METRIC = "cutoff pair-interactions/s at 1 ppc (16.8M particles); p99 latency at 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
-# Algorithmic FLOPs of the sweep (FMA = 2, other arithmetic = 1; compares,
-# integer work not counted): every candidate pays 3 sub + 1 mul + 2 FMA = 8;
-# every accepted pair of the compensated path pays about 60 on average: sqrt
-# 1, the spline 10 (q <= 1/2) or 38 (q > 1/2, 28 of them for the error-free
-# h^2 - r^2) weighted 1:7 by volume, 5 for the weighted terms, 4 Kahan
-# accumulations of 4, and 4 for the invariant scale.
+# Algorithmic FLOPs of the sweep (FMA = 2; add, mul, sqrt, rcp, rsq = 1;
+# compares and integer work not counted): every candidate pays 3 sub + 1 mul
+# + 2 FMA = 8; every accepted pair pays about 22 on the plain path (sqrt, q,
+# W, W' with a reciprocal, the weighted terms and 1 + 3 accumulating FMAs),
+# 12 more with compensated accumulation (3 per accumulator), and about 19
+# more where q > 1/2 for the cancellation-free 1 - q, which is 7/8 of the
+# pairs of a uniform distribution (the shell volume beyond half the cutoff).
 FLOP_PER_CANDIDATE = 8.0
-FLOP_PER_PAIR_COMPENSATED = 60.0
+FLOP_PER_PAIR = {"plain": 22.0, "compensated": 34.0 + 19.0 * 7.0 / 8.0,
+                 "fp64acc": 34.0 + 19.0 * 7.0 / 8.0}
 
 WORKLOADS = {
     "scale_1ppc": ("uniform 2^24 particles, unit cube, r_c=1/256, 256^3 cells (1 ppc)", "scale_1ppc"),
@@ -65,7 +73,9 @@ def algorithmic_bytes(name: str, n: int, nc: int, orig_order: bool) -> float:
     if name == "k_cell_ranges":
         return 4.0 * n + 8.0 * nc                     # sorted ids in; counts and offsets out
     if name.startswith("k_sweep"):
-        return 40.0 * n + 4.0 * nc + (4.0 * n if orig_order else 0.0)
+        # sorted x, y, z, w in (16 B), rho, G and count out (20 B), one
+        # offset per cell (4 B); the original-order scatter reads perm
+        return 36.0 * n + 4.0 * nc + (4.0 * n if orig_order else 0.0)
     return 0.0
 
 
@@ -214,26 +224,61 @@ def bench_batch(steps: int, warmup: int, sweep: str = "auto"):
             "speedup": round(t_plain / t_batch, 2)}
 
 
-def bench_serve(n_pool: int = 16, sweeps: int = 8, seconds: float = 3.0, loads=(0.5, 0.8), seed: int = 5):
+def _fresh_requests(pool, count, rng, sweeps, first_seed):
+    """`count` requests drawn from the pool of distinct systems, each a fresh
+    particle set: a random one of the 48 symmetries of its cube (axis
+    permutation and mirror images v -> (g - 2^-16) - v, exact on the 2^-16
+    lattice), and its own displacement seed."""
+    from paper_2406_16091_amd import pi, synth
+    lat = 2.0 ** -16
+    out = []
+    for k in range(count):
+        s = pool[int(rng.integers(len(pool)))]
+        axes = [s.x, s.y, s.z]
+        order = rng.permutation(3)
+        flip = rng.random(3) < 0.5
+        top = np.float32(s.dims[0] - lat)
+        v = [(top - axes[a]).astype(np.float32) if f else axes[a] for a, f in zip(order, flip)]
+        t = synth.System(s.name, v[0], v[1], v[2], s.w, s.origin, s.dims, s.cell_w, s.rc)
+        out.append(pi.make_request(t, n_sweeps=sweeps, jitter_sigma=0.1 * s.rc, lattice=lat,
+                                   seed=first_seed + k))
+    return out
+
+
+def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(0.5, 0.8), seed: int = 5,
+                n_closed: int = 24):
     """Serving: requests of N log-uniform in [1e4, 4e6] particles (uniform or
     8-blob clustered, 1/2/4/8 per cell), each swept `sweeps` times with
-    Gaussian displacements of 0.1 r_c between sweeps.  Measures the
-    saturation rate (all requests submitted at once), the one-request-at-a-
-    time rate, and p50/p99 latency (submit to results in host memory) under
-    Poisson arrivals at fractions of the saturation rate."""
-    import numpy as np
+    Gaussian displacements of 0.1 r_c between sweeps.  Every submission is a
+    fresh particle set (_fresh_requests); no request is submitted twice.
+    Measures the saturation rate (n_closed requests submitted at once), the
+    one-request-at-a-time rate on the same requests, and p50/p99 latency
+    (submit to results in host memory) under Poisson arrivals at fractions of
+    the saturation rate.  AUTO requests take the tuner's cached choice for
+    their class or the static rule; the server never runs timed trials."""
     import torch
     from paper_2406_16091_amd import device, pi, synth
 
     pool = synth.serve_requests(n_pool, seed=seed)
+    rng = np.random.default_rng(seed)
     ctx = device.Context.get(0).handle
-    reqs = [pi.make_request(s, n_sweeps=sweeps, jitter_sigma=0.1 * s.rc, lattice=2.0 ** -16, seed=1000 + k)
-            for k, s in enumerate(pool)]
     torch.cuda.synchronize()
+    next_seed = [100_000]
 
-    def run_all(server, order):
+    def fresh(count, systems=None):
+        r = _fresh_requests(systems or pool, count, rng, sweeps, next_seed[0])
+        next_seed[0] += count
+        return r
+
+    # a server is warmed once with the largest systems it may see, one per
+    # slot, so that its device buffers and pinned staging have their final
+    # sizes before anything is measured (a serving engine sizes its slots
+    # for the largest admissible request)
+    largest = [max(pool, key=lambda t: t.n)]
+
+    def run_all(server, reqs):
         t0 = time.perf_counter()
-        tickets = [pi.pi_submit(server, reqs[i]) for i in order]
+        tickets = [pi.pi_submit(server, r) for r in reqs]
         pairs = 0
         for t in tickets:
             r = pi.pi_wait(server, t, copy=False)
@@ -241,38 +286,45 @@ def bench_serve(n_pool: int = 16, sweeps: int = 8, seconds: float = 3.0, loads=(
             pi.pi_release(server, t)
         return time.perf_counter() - t0, pairs
 
+    # the closed-loop comparison: the same fresh requests through a one-slot
+    # server (one request at a time) and through the full server
+    closed = fresh(n_closed)
     one = pi.pi_server_create(ctx, max_slots=1, n_streams=1)
-    run_all(one, range(len(reqs)))               # warm: buffers, tuner classes
-    t_seq, pairs_seq = run_all(one, range(len(reqs)))
+    run_all(one, fresh(2, largest))
+    t_seq, pairs_seq = run_all(one, closed)
     pi.pi_server_destroy(one)
 
     server = pi.pi_server_create(ctx, max_slots=8, n_streams=4)
-    run_all(server, range(len(reqs)))
-    t_sat, pairs_sat = run_all(server, range(len(reqs)))
-    rate_sat = len(reqs) / t_sat
-    out = {"requests_in_pool": len(reqs), "sweeps_per_request": sweeps,
-           "mean_particles": float(np.mean([s.n for s in pool])),
+    run_all(server, fresh(8, largest))
+    run_all(server, fresh(24))
+    t_sat, pairs_sat = run_all(server, closed)
+    assert pairs_sat == pairs_seq, "a request's results depend on what runs beside it"
+    rate_sat = len(closed) / t_sat
+    out = {"distinct_systems": n_pool, "fresh_request_sets": True, "closed_loop_requests": n_closed,
+           "sweeps_per_request": sweeps, "mean_particles": float(np.mean([s.n for s in pool])),
            "saturation_requests_per_s": round(rate_sat, 2),
            "saturation_pairs_per_s": round(pairs_sat / t_sat, 1),
-           "one_at_a_time_requests_per_s": round(len(reqs) / t_seq, 2),
+           "one_at_a_time_requests_per_s": round(len(closed) / t_seq, 2),
            "one_at_a_time_pairs_per_s": round(pairs_seq / t_seq, 1),
            "speedup_over_one_at_a_time": round(t_seq / t_sat, 2), "loads": []}
-    rng = np.random.default_rng(seed)
+    del closed
     for f in loads:
         lam = f * rate_sat
+        reqs = fresh(int(lam * seconds * 1.3) + 8)
         t_start = time.perf_counter()
         next_t = t_start
         k = 0
         pending = {}
-        lat, pairs = [], 0
+        lat, pairs, refused = [], 0, 0
         while True:
             now = time.perf_counter()
-            if now - t_start < seconds and now >= next_t:
-                i = k % len(reqs)
+            if now - t_start < seconds and now >= next_t and k < len(reqs):
                 t_client = time.perf_counter()
-                st, tk = pi.pi_submit_status(server, reqs[i])
+                st, tk = pi.pi_submit_status(server, reqs[k])
                 if st == pi.PI_OK:
                     pending[tk] = t_client
+                else:
+                    refused += 1
                 k += 1
                 next_t += rng.exponential(1.0 / lam)
                 continue
@@ -282,17 +334,92 @@ def bench_serve(n_pool: int = 16, sweeps: int = 8, seconds: float = 3.0, loads=(
                     lat.append(time.perf_counter() - pending.pop(tk))
                     pairs += r["pairs_total"]
                     pi.pi_release(server, tk)
-            if now - t_start >= seconds and not pending:
+            if (now - t_start >= seconds or k >= len(reqs)) and not pending:
                 break
             time.sleep(0.0002)
         wall = time.perf_counter() - t_start
         lat_ms = np.array(lat) * 1e3
         out["loads"].append({"load": f, "offered_requests_per_s": round(lam, 2), "completed": len(lat),
+                             "refused": refused,
                              "p50_ms": round(float(np.percentile(lat_ms, 50)), 3) if len(lat) else None,
                              "p99_ms": round(float(np.percentile(lat_ms, 99)), 3) if len(lat) else None,
                              "pairs_per_s": round(pairs / wall, 1)})
+        del reqs
     pi.pi_server_destroy(server)
     return out
+
+
+# Table 1 of the paper (Sec. 7.2): seconds per call of its Lennard-Jones
+# kernel (21 FLOP per interaction as Sec. 7.1 counts it) for the no-LDS
+# sweep (Par-Part-NoLoop) and the X-pencil on an A100 and an MI210, per
+# (d, particles per cell).  Context only: other GPUs.
+PAPER_TABLE1_S = {
+    (2, 1): (1.0e-05, 1.1e-05, 8.6e-06, 6.9e-06), (4, 1): (2.0e-05, 1.2e-05, 2.9e-05, 1.9e-05),
+    (8, 1): (2.8e-05, 1.9e-05, 4.3e-05, 4.1e-05), (16, 1): (3.7e-05, 2.0e-05, 1.4e-04, 9.8e-05),
+    (32, 1): (4.2e-05, 3.8e-05, 6.3e-04, 2.3e-04), (2, 10): (3.4e-05, 1.8e-05, 3.2e-05, 4.2e-05),
+    (4, 10): (7.2e-05, 4.6e-05, 1.4e-04, 7.8e-05), (8, 10): (9.1e-05, 5.6e-05, 4.6e-04, 4.6e-04),
+    (16, 10): (1.0e-04, 8.1e-05, 2.2e-03, 1.8e-04), (32, 10): (4.2e-04, 4.0e-04, 9.2e-04, 1.2e-03),
+    (2, 100): (1.6e-04, 1.2e-04, 4.2e-04, 2.7e-04), (4, 100): (5.2e-04, 3.7e-04, 3.9e-03, 2.1e-03),
+    (8, 100): (6.1e-04, 6.1e-04, 7.8e-03, 5.3e-03), (16, 100): (3.2e-03, 3.2e-03, 1.2e-02, 8.0e-03),
+    (32, 100): (2.5e-02, 2.5e-02, 5.1e-02, 5.3e-02),
+}
+# FLOP per interaction of the three kernels as this library evaluates them
+# (FMA = 2; rcp = 1): Lennard-Jones: differences 3, softened s^2 6 (three
+# FMA), rcp 1, times sigma^2 1, u^3 2, 4 e0 (u^6 - u^3) 3, accumulation 1 =
+# 17; low-FLOP: 3 sub, 2 add, accumulation 1 = 6; high-FLOP: 17 + 150.
+PAIRFN_FLOP = {"lj": 17.0, "lowflop": 6.0, "highflop": 167.0}
+
+
+def bench_table1(calls: int = 200, min_s: float = 0.05, kernels=("lj", "lowflop", "highflop")):
+    """The paper's timing experiment on MI355X: d^3 cells (d = 2 .. 32) with
+    1, 10 or 100 particles per cell, uniform in the unit cube, cell width =
+    r_c = 1/d; every candidate pair of the 27-cell stencil evaluated with the
+    Lennard-Jones kernel (plain FP32 sums, no invariants, as the paper times
+    it) and the low-/high-FLOP kernels of Fig. 8.  Time per call = wall time
+    of `calls` back-to-back asynchronous calls / calls (Sec. 7.1), fewer calls
+    (at least 10) once they pass min_s seconds."""
+    import torch
+    from paper_2406_16091_amd import device, synth
+
+    rows = []
+    for p in (1, 10, 100):
+        for d in (2, 4, 8, 16, 32):
+            s = synth.uniform_unit_cube(d ** 3 * p, -int(round(np.log2(d))), seed=900 + d + p, name=f"t1-{d}-{p}")
+            ds = device.DeviceSystem(s)
+            ds.bin()
+            ds.sync()
+            cand = candidates_from_counts(ds.binned()["counts"], s.dims)
+            row = {"d": d, "ppc": p, "n": s.n, "candidates_per_particle": round(cand / s.n, 2),
+                   "paper_A100_nolds_pencil_s": PAPER_TABLE1_S[(d, p)][:2],
+                   "paper_MI210_nolds_pencil_s": PAPER_TABLE1_S[(d, p)][2:]}
+            for kind in kernels:
+                for sweep in ("nolds", "pencil", "subbox", "auto"):
+                    def call():
+                        ds.interact_pairfn(kind, "plain", sweep, "sorted", (0, 0, 0), invariants=False)
+                    for _ in range(3):
+                        call()
+                    torch.cuda.synchronize()
+                    k = 0
+                    t0 = time.perf_counter()
+                    while k < calls:
+                        call()
+                        k += 1
+                        if k >= 10 and k % 10 == 0:
+                            torch.cuda.synchronize()
+                            if time.perf_counter() - t0 >= min_s:
+                                break
+                    torch.cuda.synchronize()
+                    t = (time.perf_counter() - t0) / k
+                    row[f"{kind}_{sweep}_s"] = float(f"{t:.4g}")
+                    if sweep == "auto":
+                        row[f"{kind}_auto_candidate_pairs_per_s"] = float(f"{cand / t:.4g}")
+                        row[f"{kind}_auto_tflops"] = round(cand * PAIRFN_FLOP[kind] / t / 1e12, 3)
+            ds.sync()
+            ds.close()
+            rows.append(row)
+            print(f"[bench] table1 d={d} ppc={p}: lj auto {row['lj_auto_s']:.3g} s/call", file=sys.stderr,
+                  flush=True)
+    return rows
 
 
 def main():
@@ -306,10 +433,12 @@ def main():
     ap.add_argument("--precision", default="compensated")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
-    ap.add_argument("--serve", action="store_true",
-                    help="also measure the request server (saturation, one-at-a-time, Poisson p50/p99)")
-    ap.add_argument("--batch", action="store_true",
-                    help="also measure the 512-system batch (graph launch vs one launch per system)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the request server (saturation, one-at-a-time, Poisson p50/p99)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 512-system batch (graph launch vs one launch per system)")
+    ap.add_argument("--no-table1", action="store_true",
+                    help="skip the paper's timing grid (Lennard-Jones and Fig. 8 kernels on d^3 cells)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times "
                          "(reference kernel for scaling HBM traffic counters), then exit")
@@ -398,29 +527,34 @@ def main():
         avg_s = total_ms * 1e-3 / launches
         by = algorithmic_bytes(name, n, nc, False)
         if name.startswith("k_sweep"):
-            flops = FLOP_PER_CANDIDATE * cand + FLOP_PER_PAIR_COMPENSATED * pairs
+            flops = FLOP_PER_CANDIDATE * cand + FLOP_PER_PAIR[args.precision] * pairs
             t_hbm = by / (HBM_PEAK_GBS * 1e9)
             t_alu = flops / (FP32_PEAK_TFLOPS * 1e12)
             bound = "hbm" if t_hbm >= t_alu else "alu"
         else:
             flops, bound = 0.0, "hbm"
+        traffic = measured_traffic(name)
         if bound == "hbm":
             ach = by / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name), "kernel": name,
-                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": by}
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": name,
+                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_bytes": by,
+                    "algorithmic_flops": flops}
         else:
             ach = flops / avg_s / 1e12
             roof = {"bound": "alu", "achieved": round(ach, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": measured_traffic(name), "kernel": name,
-                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_flops": flops}
+                    "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": name,
+                    "avg_us": round(avg_s * 1e6, 2), "algorithmic_flops": flops, "algorithmic_bytes": by}
+        roof["traffic_over_algorithmic_bytes"] = round(traffic / by, 3) if traffic and by else None
+        if flops:
+            roof["fp32_frac_of_157TF"] = round(flops / avg_s / 1e12 / FP32_PEAK_TFLOPS, 4)
         bin_us = sum(v[1] for k, v in kt.items() if not k.startswith(("k_sweep", "k_inv"))) * 1e3 / nbreak
         sw = [(k, v) for k, v in kt.items() if k.startswith("k_sweep")]
         sweep_us = sum(v[1] for _, v in sw) * 1e3 / nbreak
         bin_bytes = 40.0 * n + 8.0 * nc
         stages = {"bin_us": round(bin_us, 2), "sweep_us": round(sweep_us, 2),
                   "bin_hbm_frac_algorithmic": round(bin_bytes / (bin_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                  "sweep_fp32_frac": round((FLOP_PER_CANDIDATE * cand + FLOP_PER_PAIR_COMPENSATED * pairs)
+                  "sweep_fp32_frac": round((FLOP_PER_CANDIDATE * cand + FLOP_PER_PAIR[args.precision] * pairs)
                                            / (sweep_us * 1e-6) / 1e12 / FP32_PEAK_TFLOPS, 4)}
 
     out = {
@@ -437,6 +571,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "n_cells": nc, "rc": system.rc,
+                   "layout": "inputs SoA; sorted cell-relative positions kept as one float4 (x, y, z, w) "
+                             "record per slot (the SoA view is written on demand, outside the step)",
                    "sweep": args.sweep, "precision": args.precision,
                    "pairs_per_step": pairs, "candidate_pairs_per_step": cand,
                    "candidate_pairs_per_s": round(cand / (ms_per_step * 1e-3), 1)},
@@ -445,12 +581,15 @@ def main():
         "kernels": kernels,
         "kernels_breakdown_steps": nbreak if kt else 0,
     }
-    if args.serve:
-        print("[bench] serving", file=sys.stderr, flush=True)
-        out["serve"] = bench_serve()
-    if args.batch:
+    if not args.no_batch:
         print("[bench] batch of 512 systems", file=sys.stderr, flush=True)
         out["batch"] = bench_batch(max(3, args.steps // 10), 2)
+    if not args.no_serve:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serve"] = bench_serve()
+    if not args.no_table1:
+        print("[bench] table 1 grid", file=sys.stderr, flush=True)
+        out["table1"] = bench_table1()
     if rank == 0 and not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(system)

@@ -237,6 +237,58 @@ pi_status pi_interact_noalloc(pi_ctx *ctx, const pi_cells *cells, const pi_inter
                               float *rho, float *gx, float *gy, float *gz, int32_t *count,
                               pi_invariants *inv, pi_stream stream);
 
+/*
+ * The pair kernels of the paper's timing experiments (Sec. 7.1: the
+ * Lennard-Jones potential with a softening factor; Fig. 8: kernels of 5 and
+ * 168 FLOP per interaction) on a binned system.  They are evaluated on every
+ * candidate pair -- each source j != i whose cell is one of the 27 around
+ * the target's cell, clipped at the grid faces -- since the interactions
+ * those experiments count are the candidates (Table 1, first column); no
+ * cutoff test is applied.  For every binned particle i:
+ *   v[i]     = sum_j K(i, j)                                       (float32)
+ *   count[i] = number of candidates j                               (int32)
+ * with, for s^2 = r_ij^2 + eps^2 and u = sigma^2 / s^2:
+ *   PI_PAIRFN_LJ:       K = 4 e0 (u^6 - u^3) = 4 e0 ((sigma/s)^12 - (sigma/s)^6)
+ *   PI_PAIRFN_LOWFLOP:  K = (x_i - x_j) + (y_i - y_j) + (z_i - z_j)
+ *   PI_PAIRFN_HIGHFLOP: the LJ value passed through 75 multiply-adds
+ *                       y <- y a + b with run-time a = 1, b = 0 (150 more
+ *                       FLOP, the same value)
+ * Terms are accumulated in the canonical order of pi_interact, so every
+ * organisation gives bit-identical outputs on lattice inputs (pi_interact's
+ * exactness condition).  `inv` (optional, device memory): pairs = sum of
+ * count, scale = sum_i sum_j |terms| (4 |e0| (u^6 + u^3), or |dx|+|dy|+|dz|),
+ * rho_sum = sum_i v[i], net = 0.
+ * Options: kernel; precision PI_PREC_COMPENSATED (Kahan sums) or
+ * PI_PREC_PLAIN; sweep PI_SWEEP_NOLDS, PI_SWEEP_PENCIL (tiles of tile[0] x 1
+ * x 1 cells, tile[0] <= 254), PI_SWEEP_SUBBOX (tile[0] x t x t with
+ * t = tile[1] = tile[2] in {2, 4}, tile[0] <= 158 or 94; 0: 4 if its halo
+ * fits, else 2) or PI_SWEEP_AUTO (with the timed tuner mode, every
+ * organisation is timed once per size and occupancy class and the fastest
+ * reused, as in pi_interact; in static mode: no LDS from 6 particles per
+ * cell up, else the widest sub-box whose halo fits).  tile[0] = 0 sizes a
+ * tile for about 384 targets, within the LDS capacity and the grid, and
+ * shortens it while the launch has fewer than two workgroups per compute
+ * unit; with AUTO a tile[0] beyond the chosen shape's limit is clamped to it
+ * (PI_EINVAL for an explicit shape).  sigma, eps, e0: 0
+ * selects rc/2, rc/4 and 1.  v is required (n > 0), count may be NULL.
+ * PI_EINVAL for other options, PI_ESTATE before a successful pi_bin.
+ */
+#define PI_PAIRFN_LJ       1
+#define PI_PAIRFN_LOWFLOP  2
+#define PI_PAIRFN_HIGHFLOP 3
+
+typedef struct pi_pairfn_opts {
+    int32_t kernel;    /* PI_PAIRFN_* */
+    int32_t precision; /* PI_PREC_COMPENSATED or PI_PREC_PLAIN */
+    int32_t sweep;     /* PI_SWEEP_AUTO, _NOLDS, _PENCIL or _SUBBOX */
+    int32_t order;     /* PI_ORDER_* */
+    int32_t tile[3];
+    float sigma, eps, e0;
+} pi_pairfn_opts;
+
+pi_status pi_interact_pairfn(pi_ctx *ctx, const pi_cells *cells, const pi_pairfn_opts *opts,
+                             float *v, int32_t *count, pi_invariants *inv, pi_stream stream);
+
 /* Wait for `stream` and return the first device-detected error latched on
  * `cells` (PI_ERANGE for out-of-box particles), then clear it.  cells may be
  * NULL (only waits). */

@@ -251,7 +251,7 @@ extern "C" pi_status pi_cells_create(pi_ctx *ctx, pi_cells **out)
 
 // Every device buffer of a pi_cells object except the error word, with the
 // capacity class it is sized by.
-enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_HIST, BUF_PARTIALS, BUF_RADIX };
+enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_CELLS64, BUF_HIST, BUF_PARTIALS, BUF_RADIX };
 
 struct BufRef {
     void **ptr;
@@ -278,6 +278,7 @@ static int list_buffers(pi_cells *c, BufRef *out)
     }
     add((void **)&c->hist, BUF_HIST, 4);
     add((void **)&c->partials, BUF_PARTIALS, 64);
+    add((void **)&c->tflag, BUF_CELLS64, 1);
     add((void **)&c->dtot, BUF_RADIX, 4);
     return k;
 }
@@ -303,11 +304,16 @@ extern "C" pi_status pi_cells_destroy(pi_cells *c)
     return PI_OK;
 }
 
+// Capacities grow to the next power of two of what is needed, so that a
+// cell object reused for systems of varied sizes (the server's slots) stops
+// growing after a few steps; growing frees the old buffers, which waits for
+// the device.
 static int64_t grow(int64_t need, int64_t have)
 {
     if (need <= have) return have;
-    int64_t g = have + have / 4;
-    return need > g ? need : g;
+    int64_t g = 64;
+    while (g < need) g <<= 1;
+    return g;
 }
 
 // Grow the per-particle / per-cell buffers to hold n particles on n_cells
@@ -337,6 +343,7 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
         case BUF_HIST: count = cap_hist; redo = grow_n; break;
         case BUF_CELLS: count = cap_c; redo = grow_c; break;
         case BUF_CELLS1: count = cap_c + 1; redo = grow_c; break;
+        case BUF_CELLS64: count = cap_c + 64; redo = grow_c; break;
         case BUF_PARTIALS: count = cap_parts; redo = grow_n || grow_c; break;
         case BUF_RADIX: count = 256; redo = false; break;
         }

@@ -88,10 +88,15 @@ struct pi_cells {
     int32_t *hist;        // [cap_hist]
     // cell-scan scratch
     int32_t *max_per_cell; // [1]
-    uint32_t *d_err;       // [1]
+    uint32_t *d_err;       // 256 bytes: error word [0], max_per_cell [16], the
+                           // epoch of the last tile sweep that overflowed [32]
     // invariant partials
     int64_t cap_partials;
     void *partials;
+    // per tile of a sweep launch: whether its halo overflowed the LDS area
+    // (cap_cells + 64 bytes; a launch has at most one tile per cell)
+    uint8_t *tflag;
+    uint32_t sweep_epoch; // number of the last tile sweep launched on the object
 };
 
 // ------------------------------------------------------------- launch helpers

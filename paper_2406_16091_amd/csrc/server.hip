@@ -168,25 +168,38 @@ uint32_t *pinned_err(void *pin, int64_t n, int32_t sweeps)
     return (uint32_t *)(pinned_invariants(pin, n) + sweeps);
 }
 
-void *pool_get(pi_server *s, size_t bytes)
+// Pinned buffers come in size classes (powers of two from 1 MiB), so that a
+// released buffer serves later requests of any size up to its class: with
+// requests of varied sizes, pinning new host memory (slow, milliseconds per
+// tens of MB) then stops once the pool holds a buffer per request in flight.
+size_t pinned_class(size_t bytes)
+{
+    size_t c = (size_t)1 << 20;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+
+// The smallest pooled buffer of at least `bytes` (lock held), or nullptr.
+void *pool_take(pi_server *s, size_t bytes, size_t *got)
 {
     size_t best = s->pool.size();
     for (size_t i = 0; i < s->pool.size(); ++i)
         if (s->pool[i].first >= bytes && (best == s->pool.size() || s->pool[i].first < s->pool[best].first)) best = i;
-    if (best < s->pool.size()) {
-        void *p = s->pool[best].second;
-        s->pool.erase(s->pool.begin() + (long)best);
-        return p;
-    }
-    void *p = nullptr;
-    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (best == s->pool.size()) return nullptr;
+    void *p = s->pool[best].second;
+    *got = s->pool[best].first;
+    s->pool.erase(s->pool.begin() + (long)best);
     return p;
 }
 
+// Device buffers of a slot grow to the next power of two of the particles
+// they must hold, so that a stream of varied request sizes stops growing
+// them (each growth frees the old buffers, which waits for the device).
 pi_status slot_reserve(pi_server *s, Slot &sl, int64_t n, int32_t sweeps)
 {
     if (n > sl.cap || !sl.d_in) {
-        const int64_t cap = std::max<int64_t>(n, 1024);
+        int64_t cap = 1024;
+        while (cap < n) cap <<= 1;
         if (sl.d_in) (void)hipFree(sl.d_in);
         if (sl.d_out) (void)hipFree(sl.d_out);
         sl.d_in = sl.d_out = nullptr;
@@ -411,14 +424,18 @@ extern "C" pi_status pi_submit(pi_server *s, const pi_request *r, uint64_t *tick
     const int64_t nc = (int64_t)r->grid.dims[0] * r->grid.dims[1] * r->grid.dims[2];
     const int64_t fp = footprint_bytes(r->n, nc, r->n_sweeps);
     if (fp > s->opts.hbm_budget) return PI_ENOMEM;
-    const size_t bytes = pinned_size(r->n, r->n_sweeps);
+    size_t bytes = pinned_size(r->n, r->n_sweeps);
     void *pin;
     {
         std::lock_guard<std::mutex> g(s->mu);
         if ((int64_t)s->queue.size() >= s->opts.queue_capacity) return PI_EAGAIN;
-        pin = pool_get(s, bytes);
+        pin = pool_take(s, bytes, &bytes);
     }
-    if (!pin) return PI_ENOMEM;
+    if (!pin) {
+        // a new buffer, pinned with the lock released
+        bytes = pinned_class(bytes);
+        if (hipHostMalloc(&pin, bytes, hipHostMallocDefault) != hipSuccess) return PI_ENOMEM;
+    }
     // the caller may reuse its arrays as soon as this returns
     float *h = (float *)pin;
     const size_t b = (size_t)r->n * 4;

@@ -9,20 +9,14 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
+#include "inv.h"
 #include "pair.h"
 
 namespace {
 
 constexpr int kBlock = 256;
-
-// One record of FP64 invariant partial sums per workgroup (64 bytes).
-struct InvPartial {
-    long long pairs;
-    double net[3];
-    double scale;
-    double rho_sum;
-    double pad[2];
-};
 
 struct SweepArgs {
     const int32_t *off;
@@ -36,6 +30,14 @@ struct SweepArgs {
     float *rho, *gx, *gy, *gz;
     int32_t *count;
     InvPartial *partials;
+    // single-system tiles: per tile, 1 if its halo overflowed the LDS area
+    // and its targets are left to the dense pass; a word that a launch whose
+    // tiles overflowed sets to its epoch (a number the host gives each tile
+    // launch on a cell object, from the counter at host_epoch)
+    uint8_t *tflag;
+    uint32_t *ovf;
+    uint32_t epoch;
+    uint32_t *host_epoch; // host memory, not read by the kernels
     KernelConst k;
     // batch mode: system table, per-system kernel constants
     const SysDev *sys;
@@ -79,36 +81,7 @@ __device__ __forceinline__ void write_target(const SweepArgs &a, int32_t k, cons
 __device__ __forceinline__ void reduce_invariants(const SweepArgs &a, uint32_t slot, long long cnt, double nx,
                                                   double ny, double nz, double sc, double rs)
 {
-    __shared__ double red[4][6];
-    for (int o = 32; o >= 1; o >>= 1) {
-        cnt += __shfl_xor(cnt, o, 64);
-        nx += __shfl_xor(nx, o, 64);
-        ny += __shfl_xor(ny, o, 64);
-        nz += __shfl_xor(nz, o, 64);
-        sc += __shfl_xor(sc, o, 64);
-        rs += __shfl_xor(rs, o, 64);
-    }
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[wid][0] = (double)cnt;
-        red[wid][1] = nx;
-        red[wid][2] = ny;
-        red[wid][3] = nz;
-        red[wid][4] = sc;
-        red[wid][5] = rs;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        InvPartial p;
-        p.pairs = (long long)(red[0][0] + red[1][0] + red[2][0] + red[3][0]);
-        p.net[0] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
-        p.net[1] = ((red[0][2] + red[1][2]) + red[2][2]) + red[3][2];
-        p.net[2] = ((red[0][3] + red[1][3]) + red[2][3]) + red[3][3];
-        p.scale = ((red[0][4] + red[1][4]) + red[2][4]) + red[3][4];
-        p.rho_sum = ((red[0][5] + red[1][5]) + red[2][5]) + red[3][5];
-        p.pad[0] = p.pad[1] = 0.0;
-        a.partials[slot] = p;
-    }
+    block_reduce_partial(a.partials + slot, cnt, nx, ny, nz, sc, rs);
 }
 
 // The same reduction through LDS for workgroups that have a free LDS area of
@@ -525,6 +498,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     long long icnt = 0;
     double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
 
+    if (!BATCH) {
+        if (tid == 0) a.tflag[lb] = total > CAP ? 1 : 0;
+        if (total > CAP) {
+            // halo too large for LDS: the dense pass (k_sweep_dense) takes
+            // this tile's targets, one thread each across the whole grid,
+            // so a dense region is not left to one workgroup
+            if (tid == 0) *a.ovf = a.epoch;
+            if (INV) reduce_invariants(a, lb, 0, 0.0, 0.0, 0.0, 0.0, 0.0);
+            return;
+        }
+    }
     if (total > CAP) {
         // halo too large for LDS: sweep this tile from global memory
         for (int32_t f = tid; f < ntarget; f += kBlock) {
@@ -561,16 +545,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         cs[r][jj] = v * (int32_t)sizeof(float4);
     }
     // 3. stage the halo particles in tile-relative coordinates: offsets from
-    //    the corner of the halo box (cell (cxlo, y0 - 1, z0 - 1)), so that a
-    //    difference of two staged positions is the pair's difference vector
-    //    with no per-row shift
+    //    the corner of the halo box clipped to the grid (cell (cxlo,
+    //    max(y0 - 1, 0), max(z0 - 1, 0))), so that a difference of two staged
+    //    positions is the pair's difference vector with no per-row shift, and
+    //    every staged coordinate lies inside the grid's extent (exact whenever
+    //    the positions are, measured from the grid's origin)
+    const int yoff = y0 > 0 ? 0 : 1, zoff = z0 > 0 ? 0 : 1;
     for (int32_t f = tid; f < total; f += kBlock) {
         const int lo = hrow[f]; // rstart[lo] <= f < rstart[lo + 1]
         const int32_t g = gstart[lo] + (f - rstart[lo]);
         const int32_t cx = a.cell[g] - rbase[lo];
         const float4 q = a.p4[g];
-        sp[f] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, q.x), __builtin_fmaf((float)(lo % HY), W, q.y),
-                            __builtin_fmaf((float)(lo / HY), W, q.z), q.w);
+        sp[f] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, q.x),
+                            __builtin_fmaf((float)(lo % HY - yoff), W, q.y),
+                            __builtin_fmaf((float)(lo / HY - zoff), W, q.z), q.w);
     }
     __syncthreads();
 
@@ -712,6 +700,55 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     }
     static_assert(sizeof(float4) * CAP >= sizeof(double) * 6 * kBlock, "the staging area parks the partials");
     if (INV) reduce_invariants_lds(a, lb, icnt, inx, iny, inz, isc, irs, reinterpret_cast<double *>(sp));
+}
+
+// The dense pass of a single-system tile sweep: the targets of every tile
+// whose halo overflowed the LDS area, each walked from global memory by one
+// thread (the same walk and order as the tiles, so the same results).  A
+// persistent grid strides over the particles; when the overflow word does
+// not hold this launch's epoch, no tile overflowed and each workgroup only
+// writes an empty partial record.  Tile shape (tx, ty, tz) and tile counts
+// are those of the tile launch.
+template <int PREC, bool INV>
+__global__ __launch_bounds__(kBlock) void k_sweep_dense(SweepArgs a, int32_t tx, int32_t ty, int32_t tz,
+                                                        int32_t ntx, int32_t nty, uint32_t rec0)
+{
+    __shared__ uint32_t any;
+    if (threadIdx.x == 0) any = *(volatile uint32_t *)a.ovf == a.epoch ? 1u : 0u;
+    __syncthreads();
+    if (!any) {
+        if (INV && threadIdx.x == 0) {
+            InvPartial p;
+            p.pairs = 0;
+            p.net[0] = p.net[1] = p.net[2] = 0.0;
+            p.scale = p.rho_sum = 0.0;
+            p.pad[0] = p.pad[1] = 0.0;
+            a.partials[rec0 + blockIdx.x] = p;
+        }
+        return;
+    }
+    long long icnt = 0;
+    double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
+    {
+        const int32_t kend = min(a.off[a.nc], a.n);
+        for (int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x); k < kend; k += (int32_t)(gridDim.x * kBlock)) {
+            const int32_t c = a.cell[k];
+            const int32_t ix = c % a.nx, iy = (c / a.nx) % a.ny, iz = c / (a.nx * a.ny);
+            const int32_t tile = ix / tx + ntx * (iy / ty + nty * (iz / tz));
+            if (!a.tflag[tile]) continue;
+            Target<PREC, INV> T;
+            const float4 pk = a.p4[k];
+            walk_cells_global(a, k, ix, iy, iz, pk.x, pk.y, pk.z, T);
+            write_target(a, k, T);
+            if (INV) {
+                long long c1;
+                double a1, a2, a3, a4, a5;
+                target_invariants(T, pk.w, c1, a1, a2, a3, a4, a5);
+                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
+            }
+        }
+    }
+    if (INV) reduce_invariants(a, rec0 + blockIdx.x, icnt, inx, iny, inz, isc, irs);
 }
 
 // FP64 reduction of the per-workgroup partials in two fixed-order stages
@@ -893,8 +930,19 @@ constexpr int kFifo = PI_FIFO_DEPTH; // pair queue entries per lane
 constexpr int kStreamId = 9; // organisation id of the FIFO stream sweep
 constexpr int kMaxOrgId = 10; // organisation ids are 0 .. kMaxOrgId
 
-// nblk: in single-system mode computed here from the grid; in batch mode
-// given (the sum of the systems' tile counts).
+// Workgroups of the dense pass that follows a single-system tile launch: a
+// persistent grid of up to four per compute unit, one per 256 particles at
+// most.
+unsigned dense_blocks(int64_t n)
+{
+    const int64_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
+}
+
+// nblk: in single-system mode computed here from the grid, and then the
+// count of invariant partial records the launch writes (the tiles', then
+// the dense pass's); in batch mode given (the sum of the systems' tile
+// counts).
 template <int TX, int TY, int TZ, int CAP, int PREC, bool INV, bool BATCH>
 void launch_tile(pi_ctx *ctx, const char *name, const SweepArgs &a, hipStream_t s, unsigned &nblk)
 {
@@ -905,8 +953,20 @@ void launch_tile(pi_ctx *ctx, const char *name, const SweepArgs &a, hipStream_t 
         const int32_t ntz = (a.nz + TZ - 1) / TZ;
         nblk = (unsigned)((int64_t)ntx * nty * ntz);
     }
+    if (BATCH) {
+        PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0,
+                  s, a, ntx, nty);
+        return;
+    }
+    SweepArgs b = a;
+    b.epoch = ++*a.host_epoch;
+    if (b.epoch == 0) b.epoch = ++*a.host_epoch; // 0 is the word's initial value
     PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0, s,
-              a, ntx, nty);
+              b, ntx, nty);
+    const unsigned nd = dense_blocks(a.n);
+    PI_LAUNCH(ctx, "k_sweep_dense", (k_sweep_dense<PREC, INV>), dim3(nd), dim3(kBlock), 0, s, b, TX, TY, TZ, ntx,
+              nty, nblk);
+    nblk += nd;
 }
 
 template <int PREC, bool INV, bool BATCH>
@@ -1214,6 +1274,9 @@ extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t
         a.ny = cells->grid.dims[1];
         a.nz = cells->grid.dims[2];
         a.k = pi_make_kernel_const(cells->grid.rc, cells->grid.cell_w);
+        a.tflag = cells->tflag;
+        a.ovf = cells->d_err + 32;
+        a.host_epoch = &const_cast<pi_cells *>(cells)->sweep_epoch;
         // count-only outputs so that tuning writes nothing the caller owns
         a.rho = a.gx = a.gy = a.gz = nullptr;
         a.count = nullptr;
@@ -1229,18 +1292,35 @@ extern "C" pi_status pi_tuner_choice(pi_ctx *ctx, const pi_cells *cells, int32_t
 
 namespace {
 
-// Workgroups of one sweep launch of organisation `tile` (as launch_sweep
-// computes them).
+// Invariant partial records of one single-system sweep launch of
+// organisation `tile` (as launch_sweep counts them: a tiling's workgroups
+// and those of its dense pass).
 int64_t sweep_blocks(int tile, int64_t n, int32_t nx, int32_t ny, int32_t nz)
 {
     int tx = 0, ty = 0, tz = 0;
     if (tile > 0 && tile != kStreamId && pi_tile_shape(tile, &tx, &ty, &tz))
-        return (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz);
+        return (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz) + dense_blocks(n);
     const int64_t b = (n + kBlock - 1) / kBlock;
     return b > 0 ? b : 1;
 }
 
 } // namespace
+
+void pi_reduce_partials(pi_ctx *ctx, void *partials, unsigned nblk, pi_invariants *inv, hipStream_t stream)
+{
+    if (nblk == 0) {
+        PI_LAUNCH(ctx, "k_inv_zero", k_inv_zero, dim3(1), dim3(64), 0, stream, inv);
+        return;
+    }
+    // stage-1 records go after the sweep's records in the same buffer
+    const int32_t n1 = (int32_t)((nblk + kInvRun - 1) / kInvRun);
+    InvPartial *parts = (InvPartial *)partials;
+    InvPartial *stage = parts + nblk;
+    PI_LAUNCH(ctx, "k_inv_stage1", k_inv_stage1, dim3(n1), dim3(kBlock), 0, stream, (const InvPartial *)parts,
+              (int32_t)nblk, stage);
+    PI_LAUNCH(ctx, "k_inv_stage2", k_inv_stage2, dim3(1), dim3(kBlock), 0, stream, (const InvPartial *)stage, n1,
+              inv);
+}
 
 pi_status pi_interact_run(pi_ctx *ctx, const pi_cells *cells, const pi_interact_opts &o, float *rho, float *gx,
                           float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream,
@@ -1284,6 +1364,9 @@ pi_status pi_interact_run(pi_ctx *ctx, const pi_cells *cells, const pi_interact_
         const int64_t b = sweep_blocks(t, n, a.nx, a.ny, a.nz);
         return b + (b + kInvRun - 1) / kInvRun;
     };
+    a.tflag = cells->tflag;
+    a.ovf = cells->d_err + 32;
+    a.host_epoch = &const_cast<pi_cells *>(cells)->sweep_epoch;
     if (no_alloc) {
         if (o.sweep == PI_SWEEP_AUTO) {
             // the tuner's cached choice or the static rule (no trials); no
@@ -1313,15 +1396,7 @@ pi_status pi_interact_run(pi_ctx *ctx, const pi_cells *cells, const pi_interact_
         if (ts != PI_OK) return ts;
     }
     launch_sweep_prec<false>(ctx, o.precision, want_inv, tile, a, stream, nblk);
-    if (want_inv) {
-        // stage-1 records go after the sweep's records in the same buffer
-        const int32_t n1 = (int32_t)((nblk + kInvRun - 1) / kInvRun);
-        InvPartial *stage = a.partials + nblk;
-        PI_LAUNCH(ctx, "k_inv_stage1", k_inv_stage1, dim3(n1), dim3(kBlock), 0, stream,
-                  (const InvPartial *)a.partials, (int32_t)nblk, stage);
-        PI_LAUNCH(ctx, "k_inv_stage2", k_inv_stage2, dim3(1), dim3(kBlock), 0, stream, (const InvPartial *)stage,
-                  n1, inv);
-    }
+    if (want_inv) pi_reduce_partials(ctx, a.partials, nblk, inv, stream);
     PI_CHECK_HIP(hipGetLastError());
     return PI_OK;
 }

@@ -71,6 +71,14 @@ class DeviceSystem:
                        self.gy if floats else None, self.gz if floats else None,
                        self.count, self.inv if invariants else None, stream)
 
+    def interact_pairfn(self, kernel="lj", precision="compensated", sweep="auto", order="sorted",
+                        tile=(0, 0, 0), sigma=0.0, eps=0.0, e0=0.0, invariants=True, stream=None):
+        """The timing-experiment pair kernels: v into self.rho, candidate
+        counts into self.count."""
+        opts = pi.make_pairfn_opts(kernel, precision, sweep, order, tile, sigma, eps, e0)
+        pi.pi_interact_pairfn(self.ctx.handle, self.cells, opts, self.rho, self.count,
+                              self.inv if invariants else None, stream)
+
     def sync(self, stream=None):
         pi.pi_sync(self.ctx.handle, self.cells, stream)
 

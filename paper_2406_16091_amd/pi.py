@@ -23,6 +23,8 @@ PI_PREC_COMPENSATED, PI_PREC_PLAIN, PI_PREC_FP64ACC = 0, 1, 2
 PI_SWEEP_AUTO, PI_SWEEP_NOLDS, PI_SWEEP_PENCIL, PI_SWEEP_SUBBOX, PI_SWEEP_STREAM = 0, 1, 2, 3, 4
 PI_ORDER_SORTED, PI_ORDER_ORIGINAL = 0, 1
 PI_NOALLOC_SCRATCH_RECORDS = 1 << 19
+PI_PAIRFN_LJ, PI_PAIRFN_LOWFLOP, PI_PAIRFN_HIGHFLOP = 1, 2, 3
+PAIRFNS = {"lj": PI_PAIRFN_LJ, "lowflop": PI_PAIRFN_LOWFLOP, "highflop": PI_PAIRFN_HIGHFLOP}
 
 PRECISIONS = {"compensated": PI_PREC_COMPENSATED, "plain": PI_PREC_PLAIN, "fp64acc": PI_PREC_FP64ACC}
 SWEEPS = {"auto": PI_SWEEP_AUTO, "nolds": PI_SWEEP_NOLDS, "pencil": PI_SWEEP_PENCIL,
@@ -52,6 +54,12 @@ class pi_cells_view(ctypes.Structure):
 class pi_interact_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sweep", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("tile", ctypes.c_int32 * 3)]
+
+
+class pi_pairfn_opts(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("precision", ctypes.c_int32), ("sweep", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("sigma", ctypes.c_float),
+                ("eps", ctypes.c_float), ("e0", ctypes.c_float)]
 
 
 class pi_invariants(ctypes.Structure):
@@ -110,6 +118,7 @@ _SIGS = [
     ("pi_interact", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_interact_opts), _P, _P, _P, _P, _P, _P, _P]),
     ("pi_interact_noalloc", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_interact_opts), _P, _P, _P, _P, _P, _P,
                                              _P]),
+    ("pi_interact_pairfn", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_pairfn_opts), _P, _P, _P, _P]),
     ("pi_sync", ctypes.c_int32, [_P, _P, _P]),
     ("pi_batch_create", ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
     ("pi_batch_destroy", ctypes.c_int32, [_P]),
@@ -251,6 +260,25 @@ def pi_interact_noalloc(ctx, cells, opts, rho, gx, gy, gz, count, inv=None, stre
     _check(_lib().pi_interact_noalloc(ctx, cells, ctypes.byref(opts) if opts is not None else None,
                                       _ptr(rho), _ptr(gx), _ptr(gy), _ptr(gz), _ptr(count), _ptr(inv),
                                       _stream(stream)), "pi_interact_noalloc")
+
+
+def make_pairfn_opts(kernel="lj", precision="compensated", sweep="auto", order="sorted", tile=(0, 0, 0),
+                     sigma=0.0, eps=0.0, e0=0.0):
+    o = pi_pairfn_opts()
+    o.kernel = PAIRFNS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.sweep = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
+    o.order = {"sorted": PI_ORDER_SORTED, "original": PI_ORDER_ORIGINAL}[order] \
+        if isinstance(order, str) else int(order)
+    for a in range(3):
+        o.tile[a] = int(tile[a])
+    o.sigma, o.eps, o.e0 = float(sigma), float(eps), float(e0)
+    return o
+
+
+def pi_interact_pairfn(ctx, cells, opts, v, count=None, inv=None, stream=None):
+    _check(_lib().pi_interact_pairfn(ctx, cells, ctypes.byref(opts), _ptr(v), _ptr(count), _ptr(inv),
+                                     _stream(stream)), "pi_interact_pairfn")
 
 
 def pi_sync(ctx, cells=None, stream=None):

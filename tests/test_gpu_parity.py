@@ -101,6 +101,10 @@ SMALL = {
     # ten 4096-key sort tiles, the last one ragged: the tile-to-workgroup
     # map over the 8 XCDs has a remainder (10 = 8 + 2)
     "ten_sort_tiles": lambda: synth.box_system(9 * 4096 + 123, 26, seed=43, lattice_log2=18),
+    # a grid two cells wide on the 2^-24 lattice of the unit cube: a tile's
+    # halo rows beyond the grid must not widen its staging frame past the
+    # grid's extent, where the lattice is no longer representable
+    "two_cells": lambda: synth.uniform_unit_cube(600, -1, seed=44, name="two_cells"),
 }
 
 
@@ -196,7 +200,7 @@ def test_sorted_order_matches_original(dev):
         assert (a[k][perm].view(np.uint32) == bsort[k].view(np.uint32)).all()
 
 
-@pytest.mark.parametrize("case", ["tiny", "clustered", "dense_8ppc", "ragged"])
+@pytest.mark.parametrize("case", ["tiny", "clustered", "dense_8ppc", "ragged", "two_cells"])
 def test_sweep_organisations_bitwise_equal(dev, case):
     s = SMALL[case]()
     ds = dev.DeviceSystem(s)
