@@ -316,13 +316,14 @@ def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(
         k = 0
         pending = {}
         lat, pairs, refused = [], 0, 0
+        waits, runs, sizes = [], [], []
         while True:
             now = time.perf_counter()
             if now - t_start < seconds and now >= next_t and k < len(reqs):
                 t_client = time.perf_counter()
                 st, tk = pi.pi_submit_status(server, reqs[k])
                 if st == pi.PI_OK:
-                    pending[tk] = t_client
+                    pending[tk] = (t_client, int(reqs[k].n))
                 else:
                     refused += 1
                 k += 1
@@ -331,7 +332,11 @@ def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(
             for tk in list(pending):
                 r = pi.pi_poll(server, tk, copy=False)
                 if r["done"]:
-                    lat.append(time.perf_counter() - pending.pop(tk))
+                    t_client, nk = pending.pop(tk)
+                    lat.append(time.perf_counter() - t_client)
+                    waits.append(r["t_start"] - r["t_submit"])
+                    runs.append(r["t_done"] - r["t_start"])
+                    sizes.append(nk)
                     pairs += r["pairs_total"]
                     pi.pi_release(server, tk)
             if (now - t_start >= seconds or k >= len(reqs)) and not pending:
@@ -339,10 +344,16 @@ def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(
             time.sleep(0.0002)
         wall = time.perf_counter() - t_start
         lat_ms = np.array(lat) * 1e3
+
+        def pct(v, q):
+            return round(float(np.percentile(np.asarray(v) * (1e3 if v is not lat_ms else 1.0), q)), 3) \
+                if len(v) else None
+        small = lat_ms[np.array(sizes) <= np.median(sizes)] if len(sizes) else lat_ms
         out["loads"].append({"load": f, "offered_requests_per_s": round(lam, 2), "completed": len(lat),
-                             "refused": refused,
-                             "p50_ms": round(float(np.percentile(lat_ms, 50)), 3) if len(lat) else None,
-                             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3) if len(lat) else None,
+                             "refused": refused, "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
+                             "p50_admission_wait_ms": pct(waits, 50), "p99_admission_wait_ms": pct(waits, 99),
+                             "p50_on_gpu_ms": pct(runs, 50), "p99_on_gpu_ms": pct(runs, 99),
+                             "p99_ms_smaller_half": pct(small, 99),
                              "pairs_per_s": round(pairs / wall, 1)})
         del reqs
     pi.pi_server_destroy(server)
