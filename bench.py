@@ -345,14 +345,14 @@ def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(
         wall = time.perf_counter() - t_start
         lat_ms = np.array(lat) * 1e3
 
-        def pct(v, q):
-            return round(float(np.percentile(np.asarray(v) * (1e3 if v is not lat_ms else 1.0), q)), 3) \
-                if len(v) else None
+        def pct(v_ms, q):
+            return round(float(np.percentile(v_ms, q)), 3) if len(v_ms) else None
+        wait_ms, run_ms = np.array(waits) * 1e3, np.array(runs) * 1e3
         small = lat_ms[np.array(sizes) <= np.median(sizes)] if len(sizes) else lat_ms
         out["loads"].append({"load": f, "offered_requests_per_s": round(lam, 2), "completed": len(lat),
                              "refused": refused, "p50_ms": pct(lat_ms, 50), "p99_ms": pct(lat_ms, 99),
-                             "p50_admission_wait_ms": pct(waits, 50), "p99_admission_wait_ms": pct(waits, 99),
-                             "p50_on_gpu_ms": pct(runs, 50), "p99_on_gpu_ms": pct(runs, 99),
+                             "p50_admission_wait_ms": pct(wait_ms, 50), "p99_admission_wait_ms": pct(wait_ms, 99),
+                             "p50_on_gpu_ms": pct(run_ms, 50), "p99_on_gpu_ms": pct(run_ms, 99),
                              "p99_ms_smaller_half": pct(small, 99),
                              "pairs_per_s": round(pairs / wall, 1)})
         del reqs
