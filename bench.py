@@ -433,6 +433,52 @@ def bench_table1(calls: int = 200, min_s: float = 0.05, kernels=("lj", "lowflop"
     return rows
 
 
+def bench_step(system, steps: int = 20, warmup: int = 3):
+    """Time stepping on the headline workload: one pi_step = the sweep
+    (compensated, AUTO), the symplectic Euler update with the B-spline as a
+    soft pair potential, and the incremental re-binning; velocities
+    N(0, (0.05 w)^2) per axis, dt = 0.25, kappa = 0.02 r_c^5, positions kept
+    on the 2^-24 lattice.  Reports the step time and the kernels' times, the
+    re-binning (update + offsets scan + placement) beside a full pi_bin."""
+    import torch
+    from paper_2406_16091_amd import device, pi
+
+    ds = device.DeviceSystem(system)
+    ctx = ds.ctx.handle
+    ds.bin()
+    rng = np.random.default_rng(77)
+    vel = [rng.normal(0, 0.05 * system.cell_w, system.n).astype(np.float32) for _ in range(3)]
+    ds.set_velocity(*vel)
+    opts = pi.make_step_opts(0.25, 0.02 * system.rc ** 5, 2.0 ** -24)
+    for _ in range(warmup):
+        pi.pi_step(ctx, ds.cells, opts, ds.inv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pi.pi_step(ctx, ds.cells, opts, ds.inv)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ds.sync()
+    pi.pi_timing_reset(ctx)
+    pi.pi_timing_only(ctx, None)
+    pi.pi_timing_enable(ctx, True)
+    for _ in range(steps):
+        pi.pi_step(ctx, ds.cells, opts, ds.inv)
+    for _ in range(steps):
+        ds.bin()
+    torch.cuda.synchronize()
+    pi.pi_timing_enable(ctx, False)
+    kt = pi.pi_timing_read(ctx)
+    ds.close()
+    per = {k: round(v[1] * 1e3 / steps, 2) for k, v in kt.items()}
+    rebin = sum(per.get(k, 0.0) for k in ("k_step_move", "k_scan_totals", "k_scan_top", "k_scan_apply",
+                                          "k_step_place"))
+    full = sum(v for k, v in per.items() if k.startswith(("k_radix", "k_digit", "k_cell_ranges", "k_max")))
+    return {"workload": "the headline system, stepped", "ms_per_step": round(ms, 4),
+            "update_and_incremental_rebin_us": round(rebin, 2), "full_pi_bin_us": round(full, 2),
+            "kernels_us": per}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,6 +494,8 @@ def main():
                     help="skip the request server (saturation, one-at-a-time, Poisson p50/p99)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 512-system batch (graph launch vs one launch per system)")
+    ap.add_argument("--no-step", action="store_true",
+                    help="skip the time-stepping measurement (sweep + update + incremental re-binning)")
     ap.add_argument("--no-table1", action="store_true",
                     help="skip the paper's timing grid (Lennard-Jones and Fig. 8 kernels on d^3 cells)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -592,6 +640,9 @@ def main():
         "kernels": kernels,
         "kernels_breakdown_steps": nbreak if kt else 0,
     }
+    if not args.no_step:
+        print("[bench] time stepping", file=sys.stderr, flush=True)
+        out["step"] = bench_step(system)
     if not args.no_batch:
         print("[bench] batch of 512 systems", file=sys.stderr, flush=True)
         out["batch"] = bench_batch(max(3, args.steps // 10), 2)

@@ -45,6 +45,8 @@ typedef int32_t pi_status;
 #define PI_EAGAIN     (-5)  /* try again later (queue or slots full) */
 #define PI_ENOTFOUND  (-6)  /* unknown handle or ticket */
 #define PI_ESTATE     (-7)  /* call out of order (e.g. interact before bin) */
+#define PI_ESTEP      (-8)  /* a time step moved a particle further than half a
+                               cell width on an axis (its displacement was cut) */
 
 typedef void *pi_stream; /* hipStream_t */
 
@@ -288,6 +290,54 @@ typedef struct pi_pairfn_opts {
 
 pi_status pi_interact_pairfn(pi_ctx *ctx, const pi_cells *cells, const pi_pairfn_opts *opts,
                              float *v, int32_t *count, pi_invariants *inv, pi_stream stream);
+
+/*
+ * Time stepping (Sec. 2: after the interactions the particles' positions are
+ * updated).  The state of a binned system stays on the GPU in its
+ * cell-sorted order.  With the B-spline as a soft pair potential
+ *   E = (kappa / 2) sum_i sum_{j != i} w_i w_j W(r_ij)
+ * and w_i taken as the mass, the force on i is -kappa w_i G_i (G as
+ * pi_interact computes it), and one pi_step is:
+ *   1. the sweep of pi_interact (opts->precision, opts->sweep) at the
+ *      current positions;
+ *   2. symplectic Euler, per axis: v <- v - dt kappa G; x <- x + dt v, with
+ *      the displacement cut to half a cell width (PI_ESTEP is then latched
+ *      and returned by the next pi_sync: reduce dt), reflection at the box
+ *      faces (the velocity component changes sign), and, when lattice > 0,
+ *      the coordinate measured from the origin rounded down to a multiple of
+ *      it (a power of two keeps lattice inputs on the lattice, so counts stay
+ *      exact);
+ *   3. the re-binning of the new positions, incrementally: the result is
+ *      what pi_bin gives on them (counts, offsets, M_C, the stable order,
+ *      cell-relative records), computed from the previous binning since a
+ *      particle moves to one of the 26 neighbouring cells at most.
+ * pi_state_set_velocity gives the velocities (caller's device arrays in the
+ * input order of the last pi_bin) and must follow every pi_bin before a
+ * pi_step (else PI_ESTATE).  pi_state_get writes positions and velocities in
+ * that input order; positions are origin + cell corner + cell-relative part,
+ * which are the stepped values whenever they lie on a common power-of-two
+ * lattice with the origin and cell width.  With rho .. gz (all or none) it
+ * also writes the sweep outputs of the last step (at the positions before
+ * it; PI_ESTATE before the first step).  The first call allocates about 80
+ * bytes per particle and 12 per cell of stepping buffers on the object.
+ */
+typedef struct pi_step_opts {
+    float dt;         /* time step (>= 0) */
+    float kappa;      /* force scale */
+    float lattice;    /* > 0: positions rounded down to multiples of it; 0: none */
+    int32_t precision;/* PI_PREC_* of the sweep */
+    int32_t sweep;    /* PI_SWEEP_* of the sweep */
+    int32_t tile[3];  /* tile shape of the sweep, as in pi_interact_opts */
+} pi_step_opts;
+
+pi_status pi_state_set_velocity(pi_ctx *ctx, pi_cells *cells, const float *vx, const float *vy,
+                                const float *vz, pi_stream stream);
+/* inv (optional, device memory): the invariants of the step's sweep. */
+pi_status pi_step(pi_ctx *ctx, pi_cells *cells, const pi_step_opts *opts, pi_invariants *inv,
+                  pi_stream stream);
+pi_status pi_state_get(pi_ctx *ctx, pi_cells *cells, float *x, float *y, float *z,
+                       float *vx, float *vy, float *vz, float *rho, float *gx, float *gy, float *gz,
+                       pi_stream stream);
 
 /* Wait for `stream` and return the first device-detected error latched on
  * `cells` (PI_ERANGE for out-of-box particles), then clear it.  cells may be

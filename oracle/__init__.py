@@ -15,7 +15,10 @@ Functions follow the paper (arXiv 2406.16091):
   * :func:`kernel` -- the B-spline W(r) and dW/dr;
   * :func:`sweep_pairfn` / :func:`brute_pairfn` -- the kernels of the paper's
     timing experiments (Sec. 7.1 Lennard-Jones with softening, Fig. 8's low-
-    and high-FLOP kernels) over every candidate of the 27-cell stencil.
+    and high-FLOP kernels) over every candidate of the 27-cell stencil;
+  * :func:`euler_step` / :func:`pair_energy` -- the position update that ends
+    the pipeline of Sec. 2 (one symplectic Euler step with the B-spline as a
+    soft pair potential) and that potential's energy.
 """
 from __future__ import annotations
 
@@ -246,6 +249,46 @@ def brute_pairfn(kind, x, y, z, dims, sigma, eps, e0, cell, targets=None, nthrea
     if st != OK:
         raise OracleError(st)
     return PairfnOut(v, a, cand)
+
+
+def euler_step(x, y, z, vx, vy, vz, gx, gy, gz, dt, kappa, origin, dims, cell_w, lattice=0.0):
+    """One time step (Sec. 2: interactions, then the positions are updated)
+    in FP64 from the FP64 sweep outputs G at the current positions, with the
+    B-spline taken as a soft pair potential E = (kappa/2) sum_i sum_{j!=i}
+    w_i w_j W(r_ij) and w_i the mass: the acceleration is -kappa G_i.
+    Symplectic Euler per axis: v' = v - dt kappa G, displacement dt v' cut to
+    half a cell width, reflection at the box faces (the velocity flips), the
+    coordinate measured from the origin rounded down to the lattice (if > 0)
+    and kept at most one lattice step below the far face.  Returns
+    (positions, velocities, cut) as float64 arrays [3, n] and a bool array of
+    particles whose displacement was cut."""
+    L = np.asarray(dims, np.float64) * float(cell_w)
+    o = np.asarray(origin, np.float64)
+    pos = np.stack([np.asarray(a, np.float64) for a in (x, y, z)])
+    vel = np.stack([np.asarray(a, np.float64) for a in (vx, vy, vz)])
+    acc = -float(kappa) * np.stack([np.asarray(a, np.float64) for a in (gx, gy, gz)])
+    vel = vel + float(dt) * acc
+    d = float(dt) * vel
+    half = 0.5 * float(cell_w)
+    cut = np.abs(d) > half
+    d = np.where(cut, np.copysign(half, d), d)
+    u = pos - o[:, None] + d
+    low = u < 0
+    u = np.where(low, -u, u)
+    vel = np.where(low, -vel, vel)
+    high = u >= L[:, None]
+    u = np.where(high, 2 * L[:, None] - u, u)
+    vel = np.where(high, -vel, vel)
+    if lattice > 0:
+        u = np.floor(u / lattice) * lattice
+        u = np.clip(u, 0.0, L[:, None] - lattice)
+    return o[:, None] + u, vel, cut.any(axis=0)
+
+
+def pair_energy(w, rho, kappa):
+    """E = (kappa/2) sum_i w_i rho_i: the soft pair potential of the time
+    step, from the sweep's rho_i = sum_{j != i} w_j W(r_ij)."""
+    return 0.5 * float(kappa) * float(np.dot(np.asarray(w, np.float64), np.asarray(rho, np.float64)))
 
 
 def invariants(w, out: SweepOut):

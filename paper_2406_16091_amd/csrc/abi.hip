@@ -4,6 +4,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <string>
@@ -174,6 +175,7 @@ extern "C" const char *pi_status_str(pi_status s)
     case PI_EAGAIN: return "PI_EAGAIN: try again";
     case PI_ENOTFOUND: return "PI_ENOTFOUND: unknown handle";
     case PI_ESTATE: return "PI_ESTATE: call out of order";
+    case PI_ESTEP: return "PI_ESTEP: a step moved a particle more than half a cell width (displacement cut)";
     default: return "unknown pi_status";
     }
 }
@@ -251,7 +253,7 @@ extern "C" pi_status pi_cells_create(pi_ctx *ctx, pi_cells **out)
 
 // Every device buffer of a pi_cells object except the error word, with the
 // capacity class it is sized by.
-enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_CELLS64, BUF_HIST, BUF_PARTIALS, BUF_RADIX };
+enum BufClass { BUF_N, BUF_CELLS, BUF_CELLS1, BUF_CELLS64, BUF_HIST, BUF_PARTIALS, BUF_RADIX, BUF_SCAN };
 
 struct BufRef {
     void **ptr;
@@ -280,6 +282,21 @@ static int list_buffers(pi_cells *c, BufRef *out)
     add((void **)&c->partials, BUF_PARTIALS, 64);
     add((void **)&c->tflag, BUF_CELLS64, 1);
     add((void **)&c->dtot, BUF_RADIX, 4);
+    if (c->stepping) {
+        add((void **)&c->vel, BUF_N, 16);
+        add((void **)&c->vel2, BUF_N, 16);
+        add((void **)&c->perm2, BUF_N, 4);
+        add((void **)&c->cell2, BUF_N, 4);
+        add((void **)&c->newcell, BUF_N, 4);
+        add((void **)&c->xyzw2, BUF_N, 16);
+        add((void **)&c->grho, BUF_N, 4);
+        add((void **)&c->ggx, BUF_N, 4);
+        add((void **)&c->ggy, BUF_N, 4);
+        add((void **)&c->ggz, BUF_N, 4);
+        add((void **)&c->offsets2, BUF_CELLS1, 4);
+        add((void **)&c->recv, BUF_CELLS, 4);
+        add((void **)&c->scan, BUF_SCAN, 4);
+    }
     return k;
 }
 
@@ -346,6 +363,7 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
         case BUF_CELLS64: count = cap_c + 64; redo = grow_c; break;
         case BUF_PARTIALS: count = cap_parts; redo = grow_n || grow_c; break;
         case BUF_RADIX: count = 256; redo = false; break;
+        case BUF_SCAN: count = 2 * (cap_c / 1024 + 2); redo = grow_c; break;
         }
         if (!redo && *b[i].ptr) continue;
         if (*b[i].ptr) (void)hipFree(*b[i].ptr);
@@ -363,8 +381,39 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     return PI_OK;
 }
 
+// The time-stepping buffers are the last ones list_buffers names.
+pi_status pi_stepping_enable(pi_cells *c)
+{
+    if (c->stepping) return PI_OK;
+    BufRef b0[40];
+    const int first = list_buffers(c, b0);
+    c->stepping = true;
+    BufRef b[40];
+    const int nb = list_buffers(c, b);
+    for (int i = first; i < nb; ++i) {
+        int64_t count = 0;
+        switch (b[i].cls) {
+        case BUF_N: count = c->cap_n; break;
+        case BUF_CELLS: count = c->cap_cells; break;
+        case BUF_CELLS1: count = c->cap_cells + 1; break;
+        default: count = 2 * (c->cap_cells / 1024 + 2); break;
+        }
+        if (hipMalloc(b[i].ptr, (size_t)std::max<int64_t>(count, 1) * b[i].elem) != hipSuccess) {
+            for (int q = first; q < nb; ++q) {
+                if (*b[q].ptr) (void)hipFree(*b[q].ptr);
+                *b[q].ptr = nullptr;
+            }
+            c->stepping = false;
+            return PI_ENOMEM;
+        }
+    }
+    return PI_OK;
+}
+
 void pi_cells_forget(pi_cells *c)
 {
+    c->vel_valid = false;
+    c->stepped = false;
     c->binned = false;
     c->n = 0;
     c->n_cells = 0;
@@ -410,6 +459,7 @@ extern "C" pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream)
         uint32_t zero = 0;
         PI_CHECK_HIP(hipMemcpy(cells->d_err, &zero, 4, hipMemcpyHostToDevice));
         if (err & PI_DERR_RANGE) return PI_ERANGE;
+        if (err & PI_DERR_STEP) return PI_ESTEP;
         return PI_EDEVICE;
     }
     return PI_OK;

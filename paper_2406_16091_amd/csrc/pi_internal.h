@@ -20,6 +20,8 @@ pi_status pi_hip_fail(hipError_t e, const char *what);
 
 // Device-side error bits latched in pi_cells::d_err.
 #define PI_DERR_RANGE 1u
+#define PI_DERR_STEP 2u   // a step's displacement was cut to half a cell width
+#define PI_DERR_INTERNAL 4u // a kernel found its own invariant broken (no write made)
 
 struct pi_timing; // per-context kernel timing state (abi.hip)
 
@@ -97,7 +99,24 @@ struct pi_cells {
     // (cap_cells + 64 bytes; a launch has at most one tile per cell)
     uint8_t *tflag;
     uint32_t sweep_epoch; // number of the last tile sweep launched on the object
+    // time stepping (allocated once pi_state_set_velocity is first called on
+    // the object; the "2" arrays are the other half of a double buffer whose
+    // halves swap after every step)
+    bool stepping;       // the buffers below exist
+    bool vel_valid;      // vel holds the velocities of the binned system
+    bool stepped;        // a step ran since: grho .. ggz hold its sweep outputs
+    uint32_t step_epoch; // number of the last step
+    float4 *vel, *vel2;  // [cap_n] sorted (vx, vy, vz, 0)
+    int32_t *perm2, *cell2, *newcell; // [cap_n]
+    float4 *xyzw2;       // [cap_n]
+    float *grho, *ggx, *ggy, *ggz; // [cap_n] sorted sweep outputs of the last step
+    int32_t *offsets2;   // [cap_cells + 1]
+    uint32_t *recv;      // [cap_cells] step number of the last step a mover entered the cell
+    int32_t *scan;       // block partials of the offsets scan (2 x (cap_cells / 1024 + 2))
 };
+
+// Allocate the time-stepping buffers of a cell object at its capacities.
+pi_status pi_stepping_enable(pi_cells *cells);
 
 // ------------------------------------------------------------- launch helpers
 
@@ -199,6 +218,20 @@ __device__ __forceinline__ bool axis_index(float x, float o, float w, int32_t n,
     if (!(t >= 0.0f && t < (float)n)) return false;
     out = (int32_t)t; // t >= 0: truncation is floor
     return true;
+}
+
+// A coordinate p meant to lie in the box [o, o + n w) on one axis, moved by
+// single ulps until the binning's float32 decision (axis_index) keeps it
+// inside: o + v rounds once more when o is large against the box, and a
+// reflection at the far face can land on it.
+__device__ __forceinline__ float pi_keep_inside(float p, float o, float w, int32_t n)
+{
+    for (int it = 0; it < 64; ++it) {
+        const float t = (p - o) / w;
+        if (t >= 0.0f && t < (float)n) return p;
+        p = t < 0.0f ? nextafterf(p, INFINITY) : nextafterf(p, -INFINITY);
+    }
+    return o; // t = 0: the low corner is always inside
 }
 
 pi_status pi_ensure_capacity(pi_cells *cells, int64_t n, int64_t n_cells, hipStream_t stream);

@@ -42,18 +42,8 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 // uniforms drawn from the counter (seed, step, particle, axis)), reflect at
 // the faces of the box [o, o + L), L = n w, and round the offset from o down
 // to the lattice (if > 0).  The stored coordinate o + v is rounded once more
-// when o is large against L; it is then moved by single ulps until the
-// binning's float32 decision (t = (p - o) / w, inside iff 0 <= t < n) keeps
-// it inside the box.
-__device__ __forceinline__ float keep_inside(float p, float o, float w, int32_t n)
-{
-    for (int it = 0; it < 64; ++it) {
-        const float t = (p - o) / w;
-        if (t >= 0.0f && t < (float)n) return p;
-        p = t < 0.0f ? nextafterf(p, INFINITY) : nextafterf(p, -INFINITY);
-    }
-    return o; // t = 0: the low corner is always inside
-}
+// when o is large against L; pi_keep_inside then moves it by single ulps
+// until the binning's float32 decision keeps it inside the box.
 
 __global__ __launch_bounds__(256) void k_jitter(int32_t n, float *x, float *y, float *z, uint64_t seed,
                                                 int32_t step, float sigma, float lattice, float ox, float oy,
@@ -79,7 +69,7 @@ __global__ __launch_bounds__(256) void k_jitter(int32_t n, float *x, float *y, f
         } else {
             v = fminf(fmaxf(v, 0.0f), L * (1.0f - 1e-7f));
         }
-        p[a][i] = keep_inside(o[a] + v, o[a], w, dims[a]);
+        p[a][i] = pi_keep_inside(o[a] + v, o[a], w, dims[a]);
     }
 }
 

@@ -1,0 +1,462 @@
+// Time stepping on a binned system (Sec. 2: the interactions are computed,
+// then the particles' positions are updated).  The state stays in the
+// cell-sorted order the binning produced -- positions as cell-relative
+// records, velocities beside them -- and one step is:
+//   1. the sweep (pi_interact's kernels, sorted outputs);
+//   2. the update: with the B-spline as a soft pair potential
+//      E = (kappa / 2) sum_i sum_{j != i} w_i w_j W(r_ij) and w_i the mass,
+//      the force on i is -kappa w_i G_i, so the acceleration is -kappa G_i;
+//      symplectic Euler v <- v - dt kappa G, x <- x + dt v, with reflection
+//      at the box faces and the box-relative coordinate rounded down to a
+//      lattice (optional), so that lattice inputs stay lattice inputs;
+//   3. the re-binning, incremental: a particle that stays in its cell keeps
+//      its rank among the cell's stayers, and only the cells that receive a
+//      particle re-rank against the newcomers, which come from the 26
+//      neighbouring cells (a step moves a particle by at most half a cell
+//      width per axis).  The result is the stable counting sort of the new
+//      positions -- ascending original index inside each cell -- exactly as
+//      pi_bin would produce it, written into the other half of a double
+//      buffer whose halves then swap.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "pi_internal.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanBlock = 1024; // cells per block of the offsets scan
+
+struct StepArgs {
+    int32_t n;
+    int64_t nc;
+    GridDev g;
+    const int32_t *off;  // offsets of the binning before the step
+    const int32_t *cell; // cell of each sorted slot before the step
+    const int32_t *perm;
+    float4 *xyzw;        // records, rewritten in place with the new ones
+    float4 *vel;         // velocities, rewritten in place
+    const float *gx, *gy, *gz;
+    int32_t *counts;     // updated in place to the new counts
+    uint32_t *recv;
+    uint32_t epoch;
+    int32_t *newcell;
+    uint32_t *err;
+    float dk;            // dt * kappa
+    float dt;
+    float half_w;        // largest displacement per axis in one step
+    float lattice;
+    // placement
+    const int32_t *off2; // offsets after the step
+    int32_t *perm2, *cell2;
+    float4 *xyzw2, *vel2;
+};
+
+__device__ __forceinline__ void decode(const GridDev &g, int32_t c, int32_t &ix, int32_t &iy, int32_t &iz)
+{
+    const uint32_t q = div_by((uint32_t)c, g.mx);
+    ix = c - (int32_t)q * g.nx;
+    iz = (int32_t)div_by((uint32_t)c, g.mxy);
+    iy = (int32_t)q - iz * g.ny;
+}
+
+// One axis of the update: the new velocity and box-relative coordinate of a
+// particle at u in [0, L) (rounded to the lattice when one is given), with
+// reflection at both faces.  Returns true when the displacement was cut.
+__device__ __forceinline__ bool advance(float &u, float &v, float gacc, const StepArgs &a, float L)
+{
+    v = __builtin_fmaf(-a.dk, gacc, v);
+    float d = a.dt * v;
+    bool cut = false;
+    if (fabsf(d) > a.half_w) {
+        d = copysignf(a.half_w, d);
+        cut = true;
+    }
+    float x = u + d;
+    if (x < 0.0f) {
+        x = -x;
+        v = -v;
+    }
+    if (x >= L) {
+        x = 2.0f * L - x;
+        v = -v;
+    }
+    if (a.lattice > 0.0f) {
+        x = floorf(x / a.lattice) * a.lattice;
+        x = fminf(fmaxf(x, 0.0f), L - a.lattice);
+    }
+    u = x;
+    return cut;
+}
+
+// 1. Update every particle in place and find its new cell; the counts follow
+// the particles that change cell.
+__global__ __launch_bounds__(kBlock) void k_step_move(StepArgs a)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= a.n) return;
+    const GridDev &g = a.g;
+    const int32_t c = a.cell[k];
+    int32_t ix, iy, iz;
+    decode(g, c, ix, iy, iz);
+    const float4 r = a.xyzw[k];
+    float4 v = a.vel[k];
+    // box-relative coordinates, as the binning measured them
+    float ux = __builtin_fmaf((float)ix, g.w, r.x);
+    float uy = __builtin_fmaf((float)iy, g.w, r.y);
+    float uz = __builtin_fmaf((float)iz, g.w, r.z);
+    bool cut = advance(ux, v.x, a.gx[k], a, (float)g.nx * g.w);
+    cut |= advance(uy, v.y, a.gy[k], a, (float)g.ny * g.w);
+    cut |= advance(uz, v.z, a.gz[k], a, (float)g.nz * g.w);
+    const float x = pi_keep_inside(g.ox + ux, g.ox, g.w, g.nx);
+    const float y = pi_keep_inside(g.oy + uy, g.oy, g.w, g.ny);
+    const float z = pi_keep_inside(g.oz + uz, g.oz, g.w, g.nz);
+    int32_t jx = 0, jy = 0, jz = 0;
+    axis_index(x, g.ox, g.w, g.nx, jx);
+    axis_index(y, g.oy, g.w, g.ny, jy);
+    axis_index(z, g.oz, g.w, g.nz, jz);
+    const int32_t c2 = jx + g.nx * (jy + g.ny * jz);
+    a.xyzw[k] = make_float4(__builtin_fmaf(-(float)jx, g.w, x - g.ox), __builtin_fmaf(-(float)jy, g.w, y - g.oy),
+                            __builtin_fmaf(-(float)jz, g.w, z - g.oz), r.w);
+    a.vel[k] = make_float4(v.x, v.y, v.z, 0.0f);
+    a.newcell[k] = c2;
+    if (c2 != c) {
+        atomicAdd(a.counts + c2, 1);
+        atomicSub(a.counts + c, 1);
+        a.recv[c2] = a.epoch;
+    }
+    if (cut) atomicOr(a.err, PI_DERR_STEP);
+}
+
+// 2. Exclusive scan of the new counts into the new offsets, in three
+// passes: block totals (and maxima), one workgroup scanning the totals, then
+// each block's own scan plus its total's prefix.
+__device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int32_t &total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int32_t before = 0;
+    total = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wid) before += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_totals(const int32_t *__restrict__ cnt, int64_t nc,
+                                                        int32_t *__restrict__ tot, int32_t *__restrict__ mx)
+{
+    __shared__ int32_t wsum[kBlock / 64];
+    __shared__ int32_t wmax[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    int32_t s = 0, m = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int32_t v = base + q < nc ? cnt[base + q] : 0;
+        s += v;
+        m = max(m, v);
+    }
+    s = wave_sum(s);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6] = s;
+        wmax[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0, u = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            t += wsum[w];
+            u = max(u, wmax[w]);
+        }
+        tot[blockIdx.x] = t;
+        mx[blockIdx.x] = u;
+    }
+}
+
+// One workgroup: exclusive prefix of the nb block totals (in place) and the
+// largest count into *max_per_cell.
+__global__ __launch_bounds__(kBlock) void k_scan_top(int32_t *__restrict__ tot, const int32_t *__restrict__ mx,
+                                                     int32_t nb, int32_t *__restrict__ max_per_cell)
+{
+    __shared__ int32_t wsum[kBlock / 64];
+    __shared__ int32_t wmax[kBlock / 64];
+    int32_t carry = 0, m = 0;
+    for (int32_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const int32_t b = b0 + (int32_t)threadIdx.x;
+        const int32_t v = b < nb ? tot[b] : 0;
+        m = max(m, b < nb ? mx[b] : 0);
+        int32_t total;
+        const int32_t ex = block_excl_scan(v, wsum, total);
+        if (b < nb) tot[b] = carry + ex;
+        carry += total;
+    }
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t u = 0;
+        for (int w = 0; w < kBlock / 64; ++w) u = max(u, wmax[w]);
+        *max_per_cell = u;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict__ cnt, int64_t nc,
+                                                       const int32_t *__restrict__ tot, int32_t *__restrict__ off,
+                                                       int32_t n)
+{
+    __shared__ int32_t wsum[kBlock / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
+    int32_t v[4], s = 0;
+    for (int q = 0; q < 4; ++q) {
+        v[q] = base + q < nc ? cnt[base + q] : 0;
+        s += v[q];
+    }
+    int32_t total;
+    int32_t ex = tot[blockIdx.x] + block_excl_scan(s, wsum, total);
+    for (int q = 0; q < 4; ++q) {
+        if (base + q < nc) off[base + q] = ex;
+        ex += v[q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[nc] = n;
+}
+
+// Newcomers to cell c with an original index below o: particles of the 26
+// neighbouring cells (before the step) whose new cell is c.
+__device__ __forceinline__ int32_t newcomers_before(const StepArgs &a, int32_t c, int32_t o)
+{
+    int32_t cx, cy, cz;
+    decode(a.g, c, cx, cy, cz);
+    int32_t r = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int32_t z = cz + dz;
+        if (z < 0 || z >= a.g.nz) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int32_t y = cy + dy;
+            if (y < 0 || y >= a.g.ny) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int32_t x = cx + dx;
+                if (x < 0 || x >= a.g.nx || (dx == 0 && dy == 0 && dz == 0)) continue;
+                const int64_t nb = x + (int64_t)a.g.nx * (y + (int64_t)a.g.ny * z);
+                const int32_t j1 = a.off[nb + 1];
+                for (int32_t j = a.off[nb]; j < j1; ++j) r += (a.newcell[j] == c && a.perm[j] < o) ? 1 : 0;
+            }
+        }
+    }
+    return r;
+}
+
+// 3. Place every particle at its slot of the new stable order.
+__global__ __launch_bounds__(kBlock) void k_step_place(StepArgs a)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= a.n) return;
+    const int32_t c = a.cell[k], c2 = a.newcell[k], o = a.perm[k];
+    int32_t r = 0;
+    if (c2 == c) {
+        // stayers keep their order: those of the cell before this one
+        for (int32_t j = a.off[c]; j < k; ++j) r += a.newcell[j] == c ? 1 : 0;
+        if (a.recv[c] == a.epoch) r += newcomers_before(a, c, o);
+    } else {
+        const int32_t j1 = a.off[c2 + 1];
+        for (int32_t j = a.off[c2]; j < j1; ++j) r += (a.newcell[j] == c2 && a.perm[j] < o) ? 1 : 0;
+        r += newcomers_before(a, c2, o);
+    }
+    const int32_t s = a.off2[c2] + r;
+    if (s >= a.off2[c2 + 1]) { // cannot happen when every mover stays within one cell
+        atomicOr(a.err, PI_DERR_INTERNAL);
+        return;
+    }
+    a.perm2[s] = o;
+    a.cell2[s] = c2;
+    a.xyzw2[s] = a.xyzw[k];
+    a.vel2[s] = a.vel[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_velocity(int32_t n, const int32_t *__restrict__ perm,
+                                                            const float *__restrict__ vx,
+                                                            const float *__restrict__ vy,
+                                                            const float *__restrict__ vz, float4 *__restrict__ vel)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= n) return;
+    const int32_t i = perm[k];
+    vel[k] = make_float4(vx[i], vy[i], vz[i], 0.0f);
+}
+
+// The state back in the caller's (original) order: positions from the
+// records (origin + cell corner + cell-relative part), velocities, and the
+// sweep outputs of the last step.
+__global__ __launch_bounds__(kBlock) void k_scatter_state(int32_t n, GridDev g, const int32_t *__restrict__ perm,
+                                                          const int32_t *__restrict__ cell,
+                                                          const float4 *__restrict__ xyzw,
+                                                          const float4 *__restrict__ vel, float *x, float *y,
+                                                          float *z, float *vx, float *vy, float *vz)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= n) return;
+    const int32_t i = perm[k];
+    int32_t ix, iy, iz;
+    decode(g, cell[k], ix, iy, iz);
+    const float4 r = xyzw[k];
+    if (x) {
+        x[i] = g.ox + __builtin_fmaf((float)ix, g.w, r.x);
+        y[i] = g.oy + __builtin_fmaf((float)iy, g.w, r.y);
+        z[i] = g.oz + __builtin_fmaf((float)iz, g.w, r.z);
+    }
+    if (vx) {
+        const float4 v = vel[k];
+        vx[i] = v.x;
+        vy[i] = v.y;
+        vz[i] = v.z;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_forces(int32_t n, const int32_t *__restrict__ perm,
+                                                           const float *__restrict__ grho,
+                                                           const float *__restrict__ ggx,
+                                                           const float *__restrict__ ggy,
+                                                           const float *__restrict__ ggz, float *rho, float *gx,
+                                                           float *gy, float *gz)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= n) return;
+    const int32_t i = perm[k];
+    rho[i] = grho[k];
+    gx[i] = ggx[k];
+    gy[i] = ggy[k];
+    gz[i] = ggz[k];
+}
+
+inline unsigned nblocks(int64_t n, int b) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+} // namespace
+
+extern "C" pi_status pi_state_set_velocity(pi_ctx *ctx, pi_cells *cells, const float *vx, const float *vy,
+                                           const float *vz, pi_stream stream_)
+{
+    if (!ctx || !cells || cells->ctx != ctx) return PI_EINVAL;
+    if (!pi_cells_ready(cells)) return PI_ESTATE;
+    const int64_t n = cells->n;
+    if (n > 0 && (!vx || !vy || !vz)) return PI_EINVAL;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    const pi_status st = pi_stepping_enable(cells);
+    if (st != PI_OK) return st;
+    hipStream_t s = (hipStream_t)stream_;
+    if (n > 0)
+        PI_LAUNCH(ctx, "k_gather_velocity", k_gather_velocity, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s,
+                  (int32_t)n, cells->perm, vx, vy, vz, cells->vel);
+    PI_CHECK_HIP(hipGetLastError());
+    cells->vel_valid = true;
+    cells->stepped = false;
+    cells->last_stream = s;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_step(pi_ctx *ctx, pi_cells *cells, const pi_step_opts *opts, pi_invariants *inv,
+                             pi_stream stream_)
+{
+    if (!ctx || !cells || !opts || cells->ctx != ctx) return PI_EINVAL;
+    if (!pi_cells_ready(cells) || !cells->stepping || !cells->vel_valid) return PI_ESTATE;
+    const pi_step_opts &o = *opts;
+    if (!isfinite(o.dt) || !(o.dt >= 0.0f) || !isfinite(o.kappa) || !(o.lattice >= 0.0f) || !isfinite(o.lattice))
+        return PI_EINVAL;
+    const int64_t n = cells->n, nc = cells->n_cells;
+    hipStream_t s = (hipStream_t)stream_;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+
+    // 1. the sweep, outputs in sorted order
+    pi_interact_opts io;
+    memset(&io, 0, sizeof(io));
+    io.precision = o.precision;
+    io.sweep = o.sweep;
+    io.order = PI_ORDER_SORTED;
+    for (int q = 0; q < 3; ++q) io.tile[q] = o.tile[q];
+    pi_status st = pi_check_interact_opts(io, n, cells->grho, cells->ggx, cells->ggy, cells->ggz, nullptr, inv);
+    if (st != PI_OK) return st;
+    st = pi_interact_run(ctx, cells, io, cells->grho, cells->ggx, cells->ggy, cells->ggz, nullptr, inv, s,
+                         cells->partials, cells->cap_partials, false);
+    if (st != PI_OK) return st;
+    if (n == 0) return PI_OK;
+
+    // 2. update and new cells
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n = (int32_t)n;
+    a.nc = nc;
+    a.g = grid_dev(cells->grid);
+    a.off = cells->offsets;
+    a.cell = cells->cell;
+    a.perm = cells->perm;
+    a.xyzw = cells->xyzw;
+    a.vel = cells->vel;
+    a.gx = cells->ggx;
+    a.gy = cells->ggy;
+    a.gz = cells->ggz;
+    a.counts = cells->counts;
+    a.recv = cells->recv;
+    a.epoch = ++cells->step_epoch;
+    if (a.epoch == 0) a.epoch = ++cells->step_epoch; // 0: the buffer's initial contents
+    a.newcell = cells->newcell;
+    a.err = cells->d_err;
+    a.dt = o.dt;
+    a.dk = o.dt * o.kappa;
+    a.half_w = 0.5f * cells->grid.cell_w;
+    a.lattice = o.lattice;
+    a.off2 = cells->offsets2;
+    a.perm2 = cells->perm2;
+    a.cell2 = cells->cell2;
+    a.xyzw2 = cells->xyzw2;
+    a.vel2 = cells->vel2;
+    PI_LAUNCH(ctx, "k_step_move", k_step_move, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
+    // 3. new offsets and M_C
+    const int32_t nb = (int32_t)((nc + kScanBlock - 1) / kScanBlock);
+    int32_t *tot = cells->scan, *mx = cells->scan + (nc / kScanBlock + 2);
+    PI_LAUNCH(ctx, "k_scan_totals", k_scan_totals, dim3((unsigned)nb), dim3(kBlock), 0, s, cells->counts, nc, tot,
+              mx);
+    PI_LAUNCH(ctx, "k_scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, tot, mx, nb, cells->max_per_cell);
+    PI_LAUNCH(ctx, "k_scan_apply", k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, cells->counts, nc, tot,
+              cells->offsets2, (int32_t)n);
+    // 4. the new stable order
+    PI_LAUNCH(ctx, "k_step_place", k_step_place, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
+    PI_CHECK_HIP(hipGetLastError());
+    std::swap(cells->perm, cells->perm2);
+    std::swap(cells->cell, cells->cell2);
+    std::swap(cells->xyzw, cells->xyzw2);
+    std::swap(cells->vel, cells->vel2);
+    std::swap(cells->offsets, cells->offsets2);
+    cells->soa_stale = true;
+    cells->stepped = true;
+    cells->last_stream = s;
+    return PI_OK;
+}
+
+extern "C" pi_status pi_state_get(pi_ctx *ctx, pi_cells *cells, float *x, float *y, float *z, float *vx, float *vy,
+                                  float *vz, float *rho, float *gx, float *gy, float *gz, pi_stream stream_)
+{
+    if (!ctx || !cells || cells->ctx != ctx) return PI_EINVAL;
+    if (!pi_cells_ready(cells) || !cells->stepping || !cells->vel_valid) return PI_ESTATE;
+    const bool px = x || y || z, pv = vx || vy || vz, pg = rho || gx || gy || gz;
+    if ((px && !(x && y && z)) || (pv && !(vx && vy && vz)) || (pg && !(rho && gx && gy && gz))) return PI_EINVAL;
+    if (pg && !cells->stepped) return PI_ESTATE;
+    const int64_t n = cells->n;
+    if (n == 0) return PI_OK;
+    PI_CHECK_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream_;
+    if (px || pv)
+        PI_LAUNCH(ctx, "k_scatter_state", k_scatter_state, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, (int32_t)n,
+                  grid_dev(cells->grid), cells->perm, cells->cell, cells->xyzw, cells->vel, px ? x : nullptr, y, z,
+                  pv ? vx : nullptr, vy, vz);
+    // the sweep outputs of the last step are in the order before it, whose
+    // permutation is the other half of the double buffer
+    if (pg)
+        PI_LAUNCH(ctx, "k_scatter_forces", k_scatter_forces, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s,
+                  (int32_t)n, cells->perm2, cells->grho, cells->ggx, cells->ggy, cells->ggz, rho, gx, gy, gz);
+    PI_CHECK_HIP(hipGetLastError());
+    return PI_OK;
+}

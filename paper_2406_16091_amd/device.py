@@ -79,6 +79,30 @@ class DeviceSystem:
         pi.pi_interact_pairfn(self.ctx.handle, self.cells, opts, self.rho, self.count,
                               self.inv if invariants else None, stream)
 
+    def set_velocity(self, vx, vy, vz, stream=None):
+        """Velocities (numpy, input order) for time stepping."""
+        self.vx, self.vy, self.vz = (torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(self.dev)
+                                     for v in (vx, vy, vz))
+        pi.pi_state_set_velocity(self.ctx.handle, self.cells, self.vx, self.vy, self.vz, stream)
+
+    def step(self, dt, kappa, lattice=0.0, precision="compensated", sweep="auto", tile=(0, 0, 0),
+             invariants=True, stream=None):
+        pi.pi_step(self.ctx.handle, self.cells, pi.make_step_opts(dt, kappa, lattice, precision, sweep, tile),
+                   self.inv if invariants else None, stream)
+
+    def state(self, forces=False):
+        """Positions and velocities after the last step (numpy, input order);
+        with forces, the sweep outputs of that step too."""
+        n = self.sys.n
+        f = dict(dtype=torch.float32, device=self.dev)
+        out = {k: torch.empty(max(n, 1), **f) for k in ("x", "y", "z", "vx", "vy", "vz")}
+        extra = {k: torch.empty(max(n, 1), **f) for k in ("rho", "gx", "gy", "gz")} if forces else {}
+        pi.pi_state_get(self.ctx.handle, self.cells, out["x"], out["y"], out["z"], out["vx"], out["vy"],
+                        out["vz"], *(extra[k] for k in ("rho", "gx", "gy", "gz")) if forces else (None,) * 4)
+        pi.pi_sync(self.ctx.handle, self.cells)
+        out.update(extra)
+        return {k: v[:n].cpu().numpy() for k, v in out.items()}
+
     def sync(self, stream=None):
         pi.pi_sync(self.ctx.handle, self.cells, stream)
 

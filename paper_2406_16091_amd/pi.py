@@ -17,8 +17,8 @@ import torch  # loaded first so that libpi.so binds to torch's HIP runtime
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpi.so")
 
-PI_OK, PI_EINVAL, PI_ENOMEM, PI_ERANGE, PI_EDEVICE, PI_EAGAIN, PI_ENOTFOUND, PI_ESTATE = \
-    0, -1, -2, -3, -4, -5, -6, -7
+PI_OK, PI_EINVAL, PI_ENOMEM, PI_ERANGE, PI_EDEVICE, PI_EAGAIN, PI_ENOTFOUND, PI_ESTATE, PI_ESTEP = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 PI_PREC_COMPENSATED, PI_PREC_PLAIN, PI_PREC_FP64ACC = 0, 1, 2
 PI_SWEEP_AUTO, PI_SWEEP_NOLDS, PI_SWEEP_PENCIL, PI_SWEEP_SUBBOX, PI_SWEEP_STREAM = 0, 1, 2, 3, 4
 PI_ORDER_SORTED, PI_ORDER_ORIGINAL = 0, 1
@@ -60,6 +60,11 @@ class pi_pairfn_opts(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("precision", ctypes.c_int32), ("sweep", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("sigma", ctypes.c_float),
                 ("eps", ctypes.c_float), ("e0", ctypes.c_float)]
+
+
+class pi_step_opts(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("kappa", ctypes.c_float), ("lattice", ctypes.c_float),
+                ("precision", ctypes.c_int32), ("sweep", ctypes.c_int32), ("tile", ctypes.c_int32 * 3)]
 
 
 class pi_invariants(ctypes.Structure):
@@ -119,6 +124,9 @@ _SIGS = [
     ("pi_interact_noalloc", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_interact_opts), _P, _P, _P, _P, _P, _P,
                                              _P]),
     ("pi_interact_pairfn", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_pairfn_opts), _P, _P, _P, _P]),
+    ("pi_state_set_velocity", ctypes.c_int32, [_P, _P, _P, _P, _P, _P]),
+    ("pi_step", ctypes.c_int32, [_P, _P, ctypes.POINTER(pi_step_opts), _P, _P]),
+    ("pi_state_get", ctypes.c_int32, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("pi_sync", ctypes.c_int32, [_P, _P, _P]),
     ("pi_batch_create", ctypes.c_int32, [_P, ctypes.POINTER(_P)]),
     ("pi_batch_destroy", ctypes.c_int32, [_P]),
@@ -279,6 +287,31 @@ def make_pairfn_opts(kernel="lj", precision="compensated", sweep="auto", order="
 def pi_interact_pairfn(ctx, cells, opts, v, count=None, inv=None, stream=None):
     _check(_lib().pi_interact_pairfn(ctx, cells, ctypes.byref(opts), _ptr(v), _ptr(count), _ptr(inv),
                                      _stream(stream)), "pi_interact_pairfn")
+
+
+def make_step_opts(dt, kappa, lattice=0.0, precision="compensated", sweep="auto", tile=(0, 0, 0)):
+    o = pi_step_opts()
+    o.dt, o.kappa, o.lattice = float(dt), float(kappa), float(lattice)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.sweep = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
+    for a in range(3):
+        o.tile[a] = int(tile[a])
+    return o
+
+
+def pi_state_set_velocity(ctx, cells, vx, vy, vz, stream=None):
+    _check(_lib().pi_state_set_velocity(ctx, cells, _ptr(vx), _ptr(vy), _ptr(vz), _stream(stream)),
+           "pi_state_set_velocity")
+
+
+def pi_step(ctx, cells, opts, inv=None, stream=None):
+    _check(_lib().pi_step(ctx, cells, ctypes.byref(opts), _ptr(inv), _stream(stream)), "pi_step")
+
+
+def pi_state_get(ctx, cells, x=None, y=None, z=None, vx=None, vy=None, vz=None, rho=None, gx=None, gy=None,
+                 gz=None, stream=None):
+    _check(_lib().pi_state_get(ctx, cells, _ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz), _ptr(rho),
+                               _ptr(gx), _ptr(gy), _ptr(gz), _stream(stream)), "pi_state_get")
 
 
 def pi_sync(ctx, cells=None, stream=None):

@@ -1,0 +1,229 @@
+"""Time stepping through the C ABI (pi_state_set_velocity, pi_step,
+pi_state_get): the position update that ends the pipeline of Sec. 2, with
+the incremental re-binning.
+
+After every step:
+  * the binned arrays (counts, offsets, M_C, the stable order, the cell of
+    every slot, the cell-relative records) equal, bit for bit, the FP64
+    oracle's binning of the positions the GPU produced -- the incremental
+    re-binning gives exactly what a full binning gives;
+  * the sweep outputs the step used equal the oracle's at the positions
+    before the step, within the sweep's tolerance (1e-5 of rho, 1e-5 of A per
+    component of G); the counts bit for bit;
+  * the new velocities and positions equal the oracle's update (oracle.
+    euler_step, FP64, from the GPU's previous state and the oracle's G)
+    within what the FP32 arithmetic and the G tolerance allow:
+      |v - v*| <= dt kappa (1e-5 + 2^-22) A + 2^-22 |v*|,
+      |x - x*| <= dt |v - v*| + 2^-22 (|x*| + dt |v*|) + lattice
+    (the last term: rounding down to the lattice can land one step apart).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_16091_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_16091_amd import device, pi
+    pi.load()
+    return device
+
+
+def _check_binning(ds, x, y, z, s):
+    b = oracle.bin_particles(x, y, z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    g = ds.binned()
+    assert (g["counts"] == b.counts).all()
+    assert (g["offsets"] == b.offsets).all()
+    assert (g["perm"] == b.perm).all()
+    assert (g["cell"] == b.cell[b.perm]).all()
+    for k in ("xs", "ys", "zs", "ws"):
+        assert (g[k].view(np.uint32) == getattr(b, k).view(np.uint32)).all(), k
+    assert g["max_per_cell"] == b.max_per_cell
+    return b
+
+
+def _run(dev, s, vel, steps, dt, kappa, lattice, sweep="auto", tag=""):
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.set_velocity(*vel)
+    x, y, z = s.x.copy(), s.y.copy(), s.z.copy()
+    v = np.stack([np.asarray(a, np.float32) for a in vel])
+    b = oracle.bin_particles(x, y, z, s.w, s.origin, s.dims, s.cell_w, s.rc)
+    movers = 0
+    for t in range(steps):
+        ds.step(dt, kappa, lattice, sweep=sweep)
+        ds.sync()
+        st = ds.state(forces=True)
+        # the sweep the step used, at the positions before it
+        ref = oracle.sweep(x, y, z, s.w, s.dims, s.rc, b)
+        assert np.all(np.abs(st["rho"] - ref.rho) <= 1e-5 * ref.rho + 1e-30), (tag, t)
+        for k in ("gx", "gy", "gz"):
+            assert np.all(np.abs(st[k] - getattr(ref, k)) <= 1e-5 * ref.ascale + 1e-30), (tag, t, k)
+        assert ds.invariants()["pairs"] == int(ref.count.sum())
+        # the update
+        pos, vel_ref, cut = oracle.euler_step(x, y, z, *v, ref.gx, ref.gy, ref.gz, dt, kappa, s.origin, s.dims,
+                                              s.cell_w, lattice)
+        assert not cut.any()
+        got_v = np.stack([st["vx"], st["vy"], st["vz"]]).astype(np.float64)
+        got_x = np.stack([st["x"], st["y"], st["z"]]).astype(np.float64)
+        tol_v = dt * abs(kappa) * (1e-5 + 2.0 ** -22) * ref.ascale + 2.0 ** -22 * np.abs(vel_ref)
+        assert np.all(np.abs(got_v - vel_ref) <= tol_v + 1e-30), (tag, t)
+        tol_x = dt * tol_v + 2.0 ** -22 * (np.abs(pos) + dt * np.abs(vel_ref)) + lattice
+        assert np.all(np.abs(got_x - pos) <= tol_x), (tag, t, float(np.max(np.abs(got_x - pos) - tol_x)))
+        # the incremental re-binning of the GPU's new positions
+        old_cell = b.cell
+        x, y, z = st["x"], st["y"], st["z"]
+        v = np.stack([st["vx"], st["vy"], st["vz"]])
+        b = _check_binning(ds, x, y, z, s)
+        movers += int((b.cell != old_cell).sum())
+    ds.close()
+    _say(f"[step] {tag}: {steps} steps, {movers} cell changes ({movers / (steps * s.n):.3f} per particle-step)")
+    return x, y, z, v
+
+
+# (system, speed in cell widths, force scale kappa / r_c^5, lattice): kappa
+# keeps the velocity change per step at a few percent of a cell width (less
+# where the clusters' dense cores push harder)
+CASES = {
+    # 1 per cell, unit cube on the 2^-24 lattice
+    "uniform_1ppc": (lambda: synth.uniform_unit_cube(20_000, -5, seed=901, name="u1"), 0.05, 0.02, 2.0 ** -24),
+    # 8 per cell
+    "uniform_8ppc": (lambda: synth.uniform_unit_cube(8 * 16 ** 3, -4, seed=902, name="u8"), 0.05, 0.02,
+                     2.0 ** -24),
+    # clustered, unit cells, 2^-18 lattice: dense cells receive and lose many
+    "clustered": (lambda: synth.box_system(30_000, 14, seed=903, lattice_log2=18, clustered_blobs=3), 0.3,
+                  0.001, 2.0 ** -18),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_steps_match_the_oracle_and_a_full_binning(dev, case):
+    make, speed, kscale, lattice = CASES[case]
+    s = make()
+    rng = np.random.default_rng(910)
+    vel = [rng.normal(0, speed * s.cell_w, s.n).astype(np.float32) for _ in range(3)]
+    _run(dev, s, vel, 12, 0.25, kscale * s.rc ** 5, lattice, tag=case)
+
+
+@pytest.mark.parametrize("sweep,tile", [("nolds", (0, 0, 0)), ("subbox", (4, 4, 4)), ("pencil", (30, 1, 1))])
+def test_steps_do_not_depend_on_the_sweep_organisation(dev, sweep, tile):
+    """Same system, same velocities: every organisation gives bit-identical
+    trajectories (their sweep outputs agree bit for bit on lattice inputs)."""
+    from paper_2406_16091_amd import pi
+    s = synth.uniform_unit_cube(12_000, -4, seed=920, name="org")
+    rng = np.random.default_rng(921)
+    vel = [rng.normal(0, 0.05 * s.cell_w, s.n).astype(np.float32) for _ in range(3)]
+    out = {}
+    for sw, tl in (("auto", (0, 0, 0)), (sweep, tile)):
+        ds = dev.DeviceSystem(s)
+        ds.bin()
+        ds.set_velocity(*vel)
+        opts = pi.make_step_opts(0.25, 0.02 * s.rc ** 5, 2.0 ** -24, "compensated", sw, tl)
+        for _ in range(6):
+            pi.pi_step(ds.ctx.handle, ds.cells, opts, None)
+        ds.sync()
+        st = ds.state()
+        out[sw] = st
+        ds.close()
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert (out["auto"][k].view(np.uint32) == out[sweep][k].view(np.uint32)).all(), k
+
+
+def test_stepped_binning_equals_pi_bin(dev):
+    """After 20 steps, binning the stepped positions from scratch with pi_bin
+    gives bit-identical arrays to the incrementally re-binned object."""
+    s = synth.uniform_unit_cube(50_000, -5, seed=930, name="rebin")
+    rng = np.random.default_rng(931)
+    vel = [rng.normal(0, 0.1 * s.cell_w, s.n).astype(np.float32) for _ in range(3)]
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.set_velocity(*vel)
+    for _ in range(20):
+        ds.step(0.25, 0.02 * s.rc ** 5, 2.0 ** -24)
+    ds.sync()
+    st = ds.state()
+    inc = ds.binned()
+    fresh = dev.DeviceSystem(synth.System("fresh", st["x"], st["y"], st["z"], s.w, s.origin, s.dims, s.cell_w,
+                                          s.rc))
+    fresh.bin()
+    fresh.sync()
+    full = fresh.binned()
+    for k in ("counts", "offsets", "perm", "cell", "xs", "ys", "zs", "ws"):
+        assert (inc[k].view(np.uint32) == full[k].view(np.uint32)).all(), k
+    assert inc["max_per_cell"] == full["max_per_cell"]
+    ds.close()
+    fresh.close()
+
+
+def test_long_step_is_cut_and_reported(dev):
+    """A displacement beyond half a cell width is cut to it and latched:
+    pi_sync returns PI_ESTEP; the binning still matches the oracle's."""
+    from paper_2406_16091_amd import pi
+    s = synth.uniform_unit_cube(4_000, -3, seed=940, name="fast")
+    vel = [np.full(s.n, 4.0 * s.cell_w, np.float32), np.zeros(s.n, np.float32), np.zeros(s.n, np.float32)]
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.set_velocity(*vel)
+    ds.step(0.25, 0.0, 2.0 ** -24)
+    with pytest.raises(pi.PiError) as e:
+        ds.sync()
+    assert e.value.status == pi.PI_ESTEP
+    ds.sync()  # the error was cleared
+    st = ds.state()
+    _check_binning(ds, st["x"], st["y"], st["z"], s)
+    ds.close()
+
+
+def test_step_state_errors(dev):
+    from paper_2406_16091_amd import pi
+    s = synth.uniform_unit_cube(1_000, -3, seed=950, name="err")
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ctx = ds.ctx.handle
+    opts = pi.make_step_opts(0.1, 1.0)
+    with pytest.raises(pi.PiError) as e:          # no velocities yet
+        pi.pi_step(ctx, ds.cells, opts)
+    assert e.value.status == pi.PI_ESTATE
+    z = np.zeros(s.n, np.float32)
+    ds.set_velocity(z, z, z)
+    with pytest.raises(pi.PiError) as e:          # forces before any step
+        pi.pi_state_get(ctx, ds.cells, rho=ds.rho, gx=ds.gx, gy=ds.gy, gz=ds.gz)
+    assert e.value.status == pi.PI_ESTATE
+    with pytest.raises(pi.PiError) as e:
+        pi.pi_step(ctx, ds.cells, pi.make_step_opts(float("nan"), 1.0))
+    assert e.value.status == pi.PI_EINVAL
+    ds.bin()                                       # a new binning forgets the velocities
+    with pytest.raises(pi.PiError) as e:
+        pi.pi_step(ctx, ds.cells, opts)
+    assert e.value.status == pi.PI_ESTATE
+    ds.close()
+
+
+def test_full_size_step_rebinning(dev):
+    """2^24 particles at one per cell: one step, and the incremental
+    re-binning against the oracle's full binning of the new positions."""
+    s = synth.scale_1ppc()
+    rng = np.random.default_rng(960)
+    vel = [rng.normal(0, 0.05 * s.cell_w, s.n).astype(np.float32) for _ in range(3)]
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.set_velocity(*vel)
+    ds.step(0.25, 0.02 * s.rc ** 5, 2.0 ** -24)
+    ds.sync()
+    st = ds.state()
+    _check_binning(ds, st["x"], st["y"], st["z"], s)
+    ds.close()

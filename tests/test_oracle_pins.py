@@ -554,3 +554,93 @@ def test_pairfn_cell_list_equals_neighbour_cell_definition(oracle_lib, case):
         assert (cl.cand == br.cand).all() and (cl.cand == ref.cand).all()
         assert np.all(np.abs(cl.v - br.v) <= 1e-13 * br.ascale + 1e-300)
         assert np.allclose(cl.ascale, br.ascale, rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------- time stepping
+# The position update that ends the pipeline (Sec. 2), with the B-spline as a
+# soft pair potential E = (kappa/2) sum_i sum_{j != i} w_i w_j W(r_ij).
+
+def _step_system(pts, vel, w, dims=(8, 8, 8), cw=1.0):
+    p = np.asarray(pts, np.float64)
+    x, y, z = p.T.astype(np.float32)
+    v = np.asarray(vel, np.float64).T
+    w = np.asarray(w, np.float32)
+    b = oracle.bin_particles(x, y, z, w, (0, 0, 0), dims, cw, cw)
+    g = oracle.sweep(x, y, z, w, dims, cw, b)
+    return x, y, z, w, v, g
+
+
+def test_step_free_particle_moves_by_dt_v(oracle_lib):
+    """No neighbour: G = 0, so v' = v and x' = x + dt v (exact in binary)."""
+    x, y, z, w, v, g = _step_system([[2.5, 3.25, 4.0]], [[0.5, -0.25, 0.125]], [1.0])
+    pos, vel, cut = oracle.euler_step(x, y, z, *v, g.gx, g.gy, g.gz, 0.25, 3.0, (0, 0, 0), (8, 8, 8), 1.0)
+    assert pos[:, 0].tolist() == [2.625, 3.1875, 4.03125] and vel[:, 0].tolist() == [0.5, -0.25, 0.125]
+    assert not cut.any()
+
+
+def test_step_reflects_at_both_faces_and_cuts_long_moves(oracle_lib):
+    pts = [[0.0625, 4.5, 4.5], [7.9375, 1.5, 1.5], [4.5, 4.5, 1.5]]
+    vel = [[-0.5, 0, 0], [0.5, 0, 0], [0, 0, 8.0]]
+    x, y, z, w, v, g = _step_system(pts, vel, [1, 1, 1])
+    pos, v2, cut = oracle.euler_step(x, y, z, *v, g.gx, g.gy, g.gz, 0.25, 1.0, (0, 0, 0), (8, 8, 8), 1.0)
+    assert pos[0, 0] == 0.0625 and v2[0, 0] == 0.5          # 0.0625 - 0.125 -> -0.0625 -> 0.0625
+    assert pos[0, 1] == 7.9375 and v2[0, 1] == -0.5         # 7.9375 + 0.125 -> 8.0625 -> 7.9375
+    assert cut.tolist() == [False, False, True] and pos[2, 2] == 2.0  # dt v = 2 cut to half a cell
+
+
+def test_step_repulsion_and_momentum_of_a_pair(oracle_lib):
+    """Two particles at rest 0.625 h apart on x: the B-spline decreases with r,
+    so the pair force pushes them apart, with equal and opposite momenta
+    (w1 v1 = -w2 v2) along the line joining them."""
+    x, y, z, w, v, g = _step_system([[3.25, 4.5, 4.5], [3.875, 4.5, 4.5]], [[0, 0, 0], [0, 0, 0]], [0.75, 1.25])
+    pos, vel, _ = oracle.euler_step(x, y, z, *v, g.gx, g.gy, g.gz, 0.01, 2.0, (0, 0, 0), (8, 8, 8), 1.0)
+    assert vel[0, 0] < 0 < vel[0, 1] and np.all(vel[1:] == 0)
+    assert 0.75 * vel[0, 0] + 1.25 * vel[0, 1] == pytest.approx(0.0, abs=1e-15)
+    # magnitude: dt kappa w_j |W'(0.625)|
+    _, dW = oracle.kernel(0.625, 1.0)
+    assert vel[0, 1] == pytest.approx(0.01 * 2.0 * 0.75 * abs(dW), rel=1e-12)
+
+
+def test_step_momentum_conserved_away_from_walls(oracle_lib):
+    s = synth.box_system(400, 10, seed=51, lattice_log2=18, clustered_blobs=2)
+    inner = np.all([(a > 2) & (a < 8) for a in (s.x, s.y, s.z)], axis=0)
+    x, y, z, w = s.x[inner], s.y[inner], s.z[inner], s.w[inner]
+    rng = np.random.default_rng(5)
+    v = rng.normal(0, 0.05, (3, x.size))
+    b = oracle.bin_particles(x, y, z, w, (0, 0, 0), s.dims, 1.0, 1.0)
+    g = oracle.sweep(x, y, z, w, s.dims, 1.0, b)
+    _, vel, _ = oracle.euler_step(x, y, z, *v, g.gx, g.gy, g.gz, 0.02, 1.5, (0, 0, 0), s.dims, 1.0)
+    p0 = (np.asarray(w, np.float64) * v).sum(axis=1)
+    p1 = (np.asarray(w, np.float64) * vel).sum(axis=1)
+    assert np.all(np.abs(p1 - p0) <= 1e-12 * (np.asarray(w, np.float64) * np.abs(vel)).sum(axis=1))
+
+
+def test_step_energy_error_is_first_order(oracle_lib):
+    """Symplectic Euler on the soft potential: the total energy after a fixed
+    time stays close to the start, and halving dt halves the error (first
+    order), which a wrong force factor or sign would break."""
+    s = synth.box_system(300, 6, seed=52, lattice_log2=18)
+    rng = np.random.default_rng(6)
+    v0 = rng.normal(0, 0.02, (3, s.n))
+    kappa, T = 0.02, 2.0
+
+    def run(dt):
+        x, y, z = (np.asarray(a, np.float64) for a in (s.x, s.y, s.z))
+        v = v0.copy()
+        w64 = np.asarray(s.w, np.float64)
+
+        def energy(x, y, z, v):
+            b = oracle.bin_particles(x, y, z, s.w, (0, 0, 0), s.dims, 1.0, 1.0)
+            o = oracle.sweep(x, y, z, s.w, s.dims, 1.0, b)
+            return 0.5 * float((w64 * (v * v).sum(axis=0)).sum()) + oracle.pair_energy(s.w, o.rho, kappa), o
+
+        e0, o = energy(x, y, z, v)
+        for _ in range(int(round(T / dt))):
+            pos, v, cut = oracle.euler_step(x, y, z, *v, o.gx, o.gy, o.gz, dt, kappa, (0, 0, 0), s.dims, 1.0)
+            assert not cut.any()
+            x, y, z = pos
+            e, o = energy(x, y, z, v)
+        return abs(e - e0) / abs(e0)
+
+    e1, e2 = run(0.1), run(0.05)
+    assert e1 < 2e-2 and 1.4 < e1 / e2 < 2.8, (e1, e2)
