@@ -471,8 +471,7 @@ def bench_step(system, steps: int = 20, warmup: int = 3):
     kt = pi.pi_timing_read(ctx)
     ds.close()
     per = {k: round(v[1] * 1e3 / steps, 2) for k, v in kt.items()}
-    rebin = sum(per.get(k, 0.0) for k in ("k_step_move", "k_scan_totals", "k_scan_top", "k_scan_apply",
-                                          "k_step_place"))
+    rebin = sum(v for k, v in per.items() if k.startswith(("k_step_", "k_scan_")))
     full = sum(v for k, v in per.items() if k.startswith(("k_radix", "k_digit", "k_cell_ranges", "k_max")))
     return {"workload": "the headline system, stepped", "ms_per_step": round(ms, 4),
             "update_and_incremental_rebin_us": round(rebin, 2), "full_pi_bin_us": round(full, 2),

@@ -294,7 +294,11 @@ static int list_buffers(pi_cells *c, BufRef *out)
         add((void **)&c->ggy, BUF_N, 4);
         add((void **)&c->ggz, BUF_N, 4);
         add((void **)&c->offsets2, BUF_CELLS1, 4);
-        add((void **)&c->recv, BUF_CELLS, 4);
+        add((void **)&c->ncnt, BUF_CELLS, 4);
+        add((void **)&c->nstart, BUF_CELLS, 4);
+        add((void **)&c->midx, BUF_N, 4);
+        add((void **)&c->nlist, BUF_N, 8);
+        add((void **)&c->rlist, BUF_N, 4);
         add((void **)&c->scan, BUF_SCAN, 4);
     }
     return k;
@@ -363,7 +367,7 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
         case BUF_CELLS64: count = cap_c + 64; redo = grow_c; break;
         case BUF_PARTIALS: count = cap_parts; redo = grow_n || grow_c; break;
         case BUF_RADIX: count = 256; redo = false; break;
-        case BUF_SCAN: count = 2 * (cap_c / 1024 + 2); redo = grow_c; break;
+        case BUF_SCAN: count = 4 * (cap_c / 1024 + 2); redo = grow_c; break;
         }
         if (!redo && *b[i].ptr) continue;
         if (*b[i].ptr) (void)hipFree(*b[i].ptr);
@@ -376,6 +380,7 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
     }
     c->cap_n = cap_n;
     c->cap_cells = cap_c;
+    c->ncnt_zeroed = false;
     c->cap_hist = cap_hist;
     c->cap_partials = cap_parts;
     return PI_OK;
@@ -385,6 +390,7 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
 pi_status pi_stepping_enable(pi_cells *c)
 {
     if (c->stepping) return PI_OK;
+    c->ncnt_zeroed = false;
     BufRef b0[40];
     const int first = list_buffers(c, b0);
     c->stepping = true;
@@ -396,7 +402,7 @@ pi_status pi_stepping_enable(pi_cells *c)
         case BUF_N: count = c->cap_n; break;
         case BUF_CELLS: count = c->cap_cells; break;
         case BUF_CELLS1: count = c->cap_cells + 1; break;
-        default: count = 2 * (c->cap_cells / 1024 + 2); break;
+        default: count = 4 * (c->cap_cells / 1024 + 2); break;
         }
         if (hipMalloc(b[i].ptr, (size_t)std::max<int64_t>(count, 1) * b[i].elem) != hipSuccess) {
             for (int q = first; q < nb; ++q) {

@@ -91,7 +91,8 @@ struct pi_cells {
     // cell-scan scratch
     int32_t *max_per_cell; // [1]
     uint32_t *d_err;       // 256 bytes: error word [0], max_per_cell [16], the
-                           // epoch of the last tile sweep that overflowed [32]
+                           // epoch of the last tile sweep that overflowed [32],
+                           // a step's receiving-cell count [40]
     // invariant partials
     int64_t cap_partials;
     void *partials;
@@ -105,14 +106,18 @@ struct pi_cells {
     bool stepping;       // the buffers below exist
     bool vel_valid;      // vel holds the velocities of the binned system
     bool stepped;        // a step ran since: grho .. ggz hold its sweep outputs
-    uint32_t step_epoch; // number of the last step
+    bool ncnt_zeroed;    // ncnt was zeroed since it was (re)allocated
     float4 *vel, *vel2;  // [cap_n] sorted (vx, vy, vz, 0)
     int32_t *perm2, *cell2, *newcell; // [cap_n]
     float4 *xyzw2;       // [cap_n]
     float *grho, *ggx, *ggy, *ggz; // [cap_n] sorted sweep outputs of the last step
     int32_t *offsets2;   // [cap_cells + 1]
-    uint32_t *recv;      // [cap_cells] step number of the last step a mover entered the cell
-    int32_t *scan;       // block partials of the offsets scan (2 x (cap_cells / 1024 + 2))
+    int32_t *ncnt;       // [cap_cells] newcomers per cell during a step, zero between steps
+    int32_t *nstart;     // [cap_cells] start of each cell's newcomer list
+    int32_t *midx;       // [cap_n] a mover's place in its new cell's newcomer list
+    uint2 *nlist;        // [cap_n] newcomer lists (original index, slot)
+    int32_t *rlist;      // [cap_n] cells that received a particle in the last step
+    int32_t *scan;       // block partials of the offsets scan (4 x (cap_cells / 1024 + 2))
 };
 
 // Allocate the time-stepping buffers of a cell object at its capacities.

@@ -10,13 +10,15 @@
 //      at the box faces and the box-relative coordinate rounded down to a
 //      lattice (optional), so that lattice inputs stay lattice inputs;
 //   3. the re-binning, incremental: a particle that stays in its cell keeps
-//      its rank among the cell's stayers, and only the cells that receive a
-//      particle re-rank against the newcomers, which come from the 26
-//      neighbouring cells (a step moves a particle by at most half a cell
-//      width per axis).  The result is the stable counting sort of the new
-//      positions -- ascending original index inside each cell -- exactly as
-//      pi_bin would produce it, written into the other half of a double
-//      buffer whose halves then swap.
+//      its rank among the cell's stayers; a particle that changes cell takes
+//      a place in its new cell's newcomer list (a per-cell counter); the
+//      offsets come from one scan over the cells, which also places every
+//      newcomer list and lists the cells that receive anybody; then each
+//      such cell merges its stayers (already in order) with its newcomers
+//      sorted by original index.  The result is the stable counting sort of
+//      the new positions -- ascending original index inside each cell --
+//      exactly as pi_bin would produce it, written into the other half of a
+//      double buffer whose halves then swap.
 #include <math.h>
 #include <string.h>
 
@@ -27,7 +29,9 @@
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kScanBlock = 1024; // cells per block of the offsets scan
+constexpr int kScanThreads = 1024;                  // threads per block of the offsets scan
+constexpr int kScanPer = 4;                          // consecutive cells per thread
+constexpr int kScanBlock = kScanThreads * kScanPer;  // cells per block
 
 struct StepArgs {
     int32_t n;
@@ -39,10 +43,14 @@ struct StepArgs {
     float4 *xyzw;        // records, rewritten in place with the new ones
     float4 *vel;         // velocities, rewritten in place
     const float *gx, *gy, *gz;
-    int32_t *counts;     // updated in place to the new counts
-    uint32_t *recv;
-    uint32_t epoch;
+    int32_t *counts;     // stayers after the update; the new counts after the scan
+    int32_t *ncnt;       // newcomers per cell (zero outside a step)
+    int32_t *nstart;     // start of each cell's newcomer list
+    int32_t *midx;       // a mover's place in its new cell's newcomer list
+    uint2 *nlist;        // newcomer lists: (original index, slot before the step)
     int32_t *newcell;
+    int32_t *rlist;      // cells that receive a particle, in cell order
+    uint32_t *rcount;    // their number
     uint32_t *err;
     float dk;            // dt * kappa
     float dt;
@@ -123,16 +131,18 @@ __global__ __launch_bounds__(kBlock) void k_step_move(StepArgs a)
     a.vel[k] = make_float4(v.x, v.y, v.z, 0.0f);
     a.newcell[k] = c2;
     if (c2 != c) {
-        atomicAdd(a.counts + c2, 1);
         atomicSub(a.counts + c, 1);
-        a.recv[c2] = a.epoch;
+        a.midx[k] = atomicAdd(a.ncnt + c2, 1);
     }
     if (cut) atomicOr(a.err, PI_DERR_STEP);
 }
 
-// 2. Exclusive scan of the new counts into the new offsets, in three
-// passes: block totals (and maxima), one workgroup scanning the totals, then
-// each block's own scan plus its total's prefix.
+// 2. One scan over the cells, in three passes (block totals, one
+// workgroup scanning them, each block's own scan plus its prefix), of the
+// new counts (stayers + newcomers) into the new offsets and of the
+// newcomers into the start of each cell's newcomer list; it also lists the
+// cells that receive anybody, in cell order, and finds M_C.
+template <int NT>
 __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int32_t &total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -141,7 +151,7 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int
     __syncthreads();
     int32_t before = 0;
     total = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         if (w < wid) before += wsum[w];
         total += wsum[w];
     }
@@ -149,52 +159,74 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int
     return before + inc - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_totals(const int32_t *__restrict__ cnt, int64_t nc,
-                                                        int32_t *__restrict__ tot, int32_t *__restrict__ mx)
+// Block b's totals: sums of new counts, newcomers and receiving cells at
+// tot[0 * ns + b], tot[1 * ns + b], tot[2 * ns + b]; the largest new count
+// at tot[3 * ns + b].
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(const int32_t *__restrict__ cnt,
+                                                              const int32_t *__restrict__ ncnt, int64_t nc,
+                                                              int32_t *__restrict__ tot, int32_t ns)
 {
-    __shared__ int32_t wsum[kBlock / 64];
-    __shared__ int32_t wmax[kBlock / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
-    int32_t s = 0, m = 0;
-    for (int q = 0; q < 4; ++q) {
-        const int32_t v = base + q < nc ? cnt[base + q] : 0;
-        s += v;
+    __shared__ int32_t part[4][kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    int32_t sc = 0, sn = 0, sr = 0, m = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+        if (base + q >= nc) break;
+        const int32_t nw = ncnt[base + q];
+        const int32_t v = cnt[base + q] + nw;
+        sc += v;
+        sn += nw;
+        sr += nw > 0 ? 1 : 0;
         m = max(m, v);
     }
-    s = wave_sum(s);
+    sc = wave_sum(sc);
+    sn = wave_sum(sn);
+    sr = wave_sum(sr);
     m = wave_max(m);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        wsum[threadIdx.x >> 6] = s;
-        wmax[threadIdx.x >> 6] = m;
+        part[0][w] = sc;
+        part[1][w] = sn;
+        part[2][w] = sr;
+        part[3][w] = m;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t t = 0, u = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            t += wsum[w];
-            u = max(u, wmax[w]);
+        int32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        for (int q = 0; q < kScanThreads / 64; ++q) {
+            t0 += part[0][q];
+            t1 += part[1][q];
+            t2 += part[2][q];
+            t3 = max(t3, part[3][q]);
         }
-        tot[blockIdx.x] = t;
-        mx[blockIdx.x] = u;
+        tot[blockIdx.x] = t0;
+        tot[ns + blockIdx.x] = t1;
+        tot[2 * ns + blockIdx.x] = t2;
+        tot[3 * ns + blockIdx.x] = t3;
     }
 }
 
-// One workgroup: exclusive prefix of the nb block totals (in place) and the
-// largest count into *max_per_cell.
-__global__ __launch_bounds__(kBlock) void k_scan_top(int32_t *__restrict__ tot, const int32_t *__restrict__ mx,
-                                                     int32_t nb, int32_t *__restrict__ max_per_cell)
+// One workgroup: the exclusive prefixes of the three block sums (in place),
+// the largest count into *max_per_cell, the receiving-cell total into
+// *rcount.
+__global__ __launch_bounds__(kBlock) void k_scan_top(int32_t *__restrict__ tot, int32_t nb, int32_t ns,
+                                                     int32_t *__restrict__ max_per_cell, uint32_t *__restrict__ rcount)
 {
     __shared__ int32_t wsum[kBlock / 64];
     __shared__ int32_t wmax[kBlock / 64];
-    int32_t carry = 0, m = 0;
-    for (int32_t b0 = 0; b0 < nb; b0 += kBlock) {
-        const int32_t b = b0 + (int32_t)threadIdx.x;
-        const int32_t v = b < nb ? tot[b] : 0;
-        m = max(m, b < nb ? mx[b] : 0);
-        int32_t total;
-        const int32_t ex = block_excl_scan(v, wsum, total);
-        if (b < nb) tot[b] = carry + ex;
-        carry += total;
+    int32_t m = 0;
+    for (int q = 0; q < 3; ++q) {
+        int32_t *t = tot + q * ns;
+        int32_t carry = 0;
+        for (int32_t b0 = 0; b0 < nb; b0 += kBlock) {
+            const int32_t b = b0 + (int32_t)threadIdx.x;
+            const int32_t v = b < nb ? t[b] : 0;
+            if (q == 0) m = max(m, b < nb ? tot[3 * ns + b] : 0);
+            int32_t total;
+            const int32_t ex = block_excl_scan<kBlock>(v, wsum, total);
+            if (b < nb) t[b] = carry + ex;
+            carry += total;
+        }
+        if (q == 2 && threadIdx.x == 0) *rcount = (uint32_t)carry;
     }
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
@@ -206,76 +238,137 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(int32_t *__restrict__ tot, 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_apply(const int32_t *__restrict__ cnt, int64_t nc,
-                                                       const int32_t *__restrict__ tot, int32_t *__restrict__ off,
-                                                       int32_t n)
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t *__restrict__ cnt,
+                                                             const int32_t *__restrict__ ncnt, int64_t nc,
+                                                             const int32_t *__restrict__ tot, int32_t ns,
+                                                             int32_t *__restrict__ off, int32_t *__restrict__ nstart,
+                                                             int32_t *__restrict__ rlist, int32_t n)
 {
-    __shared__ int32_t wsum[kBlock / 64];
-    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * 4;
-    int32_t v[4], s = 0;
-    for (int q = 0; q < 4; ++q) {
-        v[q] = base + q < nc ? cnt[base + q] : 0;
-        s += v[q];
+    __shared__ int32_t wsum[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+    int32_t v[kScanPer], nw[kScanPer], sc = 0, sn = 0, sr = 0;
+    for (int q = 0; q < kScanPer; ++q) {
+        const bool in = base + q < nc;
+        nw[q] = in ? ncnt[base + q] : 0;
+        v[q] = in ? cnt[base + q] + nw[q] : 0;
+        sc += v[q];
+        sn += nw[q];
+        sr += nw[q] > 0 ? 1 : 0;
     }
     int32_t total;
-    int32_t ex = tot[blockIdx.x] + block_excl_scan(s, wsum, total);
-    for (int q = 0; q < 4; ++q) {
-        if (base + q < nc) off[base + q] = ex;
-        ex += v[q];
+    int32_t ec = tot[blockIdx.x] + block_excl_scan<kScanThreads>(sc, wsum, total);
+    int32_t en = tot[ns + blockIdx.x] + block_excl_scan<kScanThreads>(sn, wsum, total);
+    int32_t er = tot[2 * ns + blockIdx.x] + block_excl_scan<kScanThreads>(sr, wsum, total);
+    for (int q = 0; q < kScanPer; ++q) {
+        const int64_t c = base + q;
+        if (c < nc) {
+            off[c] = ec;
+            nstart[c] = en;
+            cnt[c] = v[q];
+            if (nw[q] > 0) rlist[er++] = (int32_t)c;
+        }
+        ec += v[q];
+        en += nw[q];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) off[nc] = n;
 }
 
-// Newcomers to cell c with an original index below o: particles of the 26
-// neighbouring cells (before the step) whose new cell is c.
-__device__ __forceinline__ int32_t newcomers_before(const StepArgs &a, int32_t c, int32_t o)
+__device__ __forceinline__ void place(const StepArgs &a, int32_t c, int32_t s, int32_t from)
 {
-    int32_t cx, cy, cz;
-    decode(a.g, c, cx, cy, cz);
-    int32_t r = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int32_t z = cz + dz;
-        if (z < 0 || z >= a.g.nz) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int32_t y = cy + dy;
-            if (y < 0 || y >= a.g.ny) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int32_t x = cx + dx;
-                if (x < 0 || x >= a.g.nx || (dx == 0 && dy == 0 && dz == 0)) continue;
-                const int64_t nb = x + (int64_t)a.g.nx * (y + (int64_t)a.g.ny * z);
-                const int32_t j1 = a.off[nb + 1];
-                for (int32_t j = a.off[nb]; j < j1; ++j) r += (a.newcell[j] == c && a.perm[j] < o) ? 1 : 0;
-            }
-        }
-    }
-    return r;
-}
-
-// 3. Place every particle at its slot of the new stable order.
-__global__ __launch_bounds__(kBlock) void k_step_place(StepArgs a)
-{
-    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (k >= a.n) return;
-    const int32_t c = a.cell[k], c2 = a.newcell[k], o = a.perm[k];
-    int32_t r = 0;
-    if (c2 == c) {
-        // stayers keep their order: those of the cell before this one
-        for (int32_t j = a.off[c]; j < k; ++j) r += a.newcell[j] == c ? 1 : 0;
-        if (a.recv[c] == a.epoch) r += newcomers_before(a, c, o);
-    } else {
-        const int32_t j1 = a.off[c2 + 1];
-        for (int32_t j = a.off[c2]; j < j1; ++j) r += (a.newcell[j] == c2 && a.perm[j] < o) ? 1 : 0;
-        r += newcomers_before(a, c2, o);
-    }
-    const int32_t s = a.off2[c2] + r;
-    if (s >= a.off2[c2 + 1]) { // cannot happen when every mover stays within one cell
+    if (s >= a.off2[c + 1]) { // cannot happen: the counts add up
         atomicOr(a.err, PI_DERR_INTERNAL);
         return;
     }
-    a.perm2[s] = o;
-    a.cell2[s] = c2;
-    a.xyzw2[s] = a.xyzw[k];
-    a.vel2[s] = a.vel[k];
+    a.perm2[s] = a.perm[from];
+    a.cell2[s] = c;
+    a.xyzw2[s] = a.xyzw[from];
+    a.vel2[s] = a.vel[from];
+}
+
+// 3a. One thread per slot: a particle that changed cell enters its new
+// cell's newcomer list; a particle that stays in a cell nobody enters keeps
+// its rank among the cell's stayers (a short loop over the cell's earlier
+// slots) and is placed at once.
+__global__ __launch_bounds__(kBlock) void k_step_place_stayers(StepArgs a)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= a.n) return;
+    const int32_t c = a.cell[k], c2 = a.newcell[k];
+    if (c2 != c) {
+        a.nlist[a.nstart[c2] + a.midx[k]] = make_uint2((uint32_t)a.perm[k], (uint32_t)k);
+        return;
+    }
+    if (a.ncnt[c] > 0) return;
+    int32_t r = 0;
+    for (int32_t j = a.off[c]; j < k; ++j) r += a.newcell[j] == c ? 1 : 0;
+    place(a, c, a.off2[c] + r, k);
+}
+
+// 3b. One thread per receiving cell: its newcomers sorted by original index
+// (up to kNew in LDS by insertion; more are ranked by counting within the
+// list), merged with the cell's stayers, which are in that order already;
+// then the cell's newcomer counter goes back to zero.
+constexpr int kPlaceBlock = 128;
+constexpr int kNew = 32;
+
+__global__ __launch_bounds__(kPlaceBlock) void k_step_place_cells(StepArgs a)
+{
+    __shared__ int32_t norig[kNew][kPlaceBlock];
+    __shared__ int32_t nslot[kNew][kPlaceBlock];
+    const int t = threadIdx.x;
+    const uint32_t m = *a.rcount;
+    for (uint32_t e = blockIdx.x * kPlaceBlock + t; e < m; e += gridDim.x * kPlaceBlock) {
+        const int32_t c = a.rlist[e];
+        const int32_t nn = a.ncnt[c], nb0 = a.nstart[c];
+        const int32_t i0 = a.off[c], i1 = a.off[c + 1];
+        const int32_t s = a.off2[c];
+        if (nn <= kNew) {
+            for (int32_t q0 = 0; q0 < nn; ++q0) {
+                const uint2 e2 = a.nlist[nb0 + q0];
+                const int32_t o = (int32_t)e2.x;
+                int q = q0;
+                while (q > 0 && norig[q - 1][t] > o) {
+                    norig[q][t] = norig[q - 1][t];
+                    nslot[q][t] = nslot[q - 1][t];
+                    --q;
+                }
+                norig[q][t] = o;
+                nslot[q][t] = (int32_t)e2.y;
+            }
+            // merge the stayers (old slots of c still in c) with the newcomers
+            int32_t i = i0, q = 0, d = s;
+            while (i < i1 && a.newcell[i] != c) ++i;
+            while (i < i1 || q < nn) {
+                if (q == nn || (i < i1 && a.perm[i] < norig[q][t])) {
+                    place(a, c, d++, i);
+                    ++i;
+                    while (i < i1 && a.newcell[i] != c) ++i;
+                } else {
+                    place(a, c, d++, nslot[q][t]);
+                    ++q;
+                }
+            }
+        } else {
+            // many newcomers: rank each particle by counting
+            int32_t rank = 0;
+            for (int32_t i = i0; i < i1; ++i) {
+                if (a.newcell[i] != c) continue;
+                const int32_t o = a.perm[i];
+                int32_t r = rank++;
+                for (int32_t q = 0; q < nn; ++q) r += (int32_t)a.nlist[nb0 + q].x < o ? 1 : 0;
+                place(a, c, s + r, i);
+            }
+            for (int32_t q0 = 0; q0 < nn; ++q0) {
+                const uint2 e2 = a.nlist[nb0 + q0];
+                const int32_t o = (int32_t)e2.x;
+                int32_t r = 0;
+                for (int32_t q = 0; q < nn; ++q) r += (int32_t)a.nlist[nb0 + q].x < o ? 1 : 0;
+                for (int32_t i = i0; i < i1; ++i) r += (a.newcell[i] == c && a.perm[i] < o) ? 1 : 0;
+                place(a, c, s + r, (int32_t)e2.y);
+            }
+        }
+        a.ncnt[c] = 0;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_velocity(int32_t n, const int32_t *__restrict__ perm,
@@ -399,10 +492,19 @@ extern "C" pi_status pi_step(pi_ctx *ctx, pi_cells *cells, const pi_step_opts *o
     a.gy = cells->ggy;
     a.gz = cells->ggz;
     a.counts = cells->counts;
-    a.recv = cells->recv;
-    a.epoch = ++cells->step_epoch;
-    if (a.epoch == 0) a.epoch = ++cells->step_epoch; // 0: the buffer's initial contents
+    // the newcomer counters are zero between steps: zeroed once after an
+    // allocation, and back to zero at the end of every step
+    if (!cells->ncnt_zeroed) {
+        PI_CHECK_HIP(hipMemsetAsync(cells->ncnt, 0, (size_t)std::max<int64_t>(nc, 1) * sizeof(int32_t), s));
+        cells->ncnt_zeroed = true;
+    }
+    a.ncnt = cells->ncnt;
+    a.nstart = cells->nstart;
+    a.midx = cells->midx;
+    a.nlist = cells->nlist;
     a.newcell = cells->newcell;
+    a.rlist = cells->rlist;
+    a.rcount = cells->d_err + 40;
     a.err = cells->d_err;
     a.dt = o.dt;
     a.dk = o.dt * o.kappa;
@@ -414,16 +516,20 @@ extern "C" pi_status pi_step(pi_ctx *ctx, pi_cells *cells, const pi_step_opts *o
     a.xyzw2 = cells->xyzw2;
     a.vel2 = cells->vel2;
     PI_LAUNCH(ctx, "k_step_move", k_step_move, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
-    // 3. new offsets and M_C
+    // 3. new offsets, newcomer lists, receiving cells and M_C
     const int32_t nb = (int32_t)((nc + kScanBlock - 1) / kScanBlock);
-    int32_t *tot = cells->scan, *mx = cells->scan + (nc / kScanBlock + 2);
-    PI_LAUNCH(ctx, "k_scan_totals", k_scan_totals, dim3((unsigned)nb), dim3(kBlock), 0, s, cells->counts, nc, tot,
-              mx);
-    PI_LAUNCH(ctx, "k_scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, tot, mx, nb, cells->max_per_cell);
-    PI_LAUNCH(ctx, "k_scan_apply", k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, cells->counts, nc, tot,
-              cells->offsets2, (int32_t)n);
-    // 4. the new stable order
-    PI_LAUNCH(ctx, "k_step_place", k_step_place, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
+    const int32_t ns = (int32_t)(nc / kScanBlock + 2);
+    int32_t *tot = cells->scan;
+    PI_LAUNCH(ctx, "k_scan_totals", k_scan_totals, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cells->counts,
+              cells->ncnt, nc, tot, ns);
+    PI_LAUNCH(ctx, "k_scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, tot, nb, ns, cells->max_per_cell, a.rcount);
+    PI_LAUNCH(ctx, "k_scan_apply", k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cells->counts,
+              cells->ncnt, nc, tot, ns, cells->offsets2, cells->nstart, cells->rlist, (int32_t)n);
+    // 4. the new stable order: stayers of cells nobody enters, then every
+    //    cell that receives a particle (a persistent grid over their list)
+    PI_LAUNCH(ctx, "k_step_place_stayers", k_step_place_stayers, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
+    const unsigned pcb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (n + kPlaceBlock - 1) / kPlaceBlock));
+    PI_LAUNCH(ctx, "k_step_place_cells", k_step_place_cells, dim3(pcb), dim3(kPlaceBlock), 0, s, a);
     PI_CHECK_HIP(hipGetLastError());
     std::swap(cells->perm, cells->perm2);
     std::swap(cells->cell, cells->cell2);
