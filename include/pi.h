@@ -153,6 +153,11 @@ pi_status pi_cells_get_view(pi_cells *cells, pi_cells_view *out);
 #define PI_SWEEP_STREAM 4 /* as NOLDS (nothing staged), with accepted pairs
                              queued per thread in LDS and evaluated by the
                              whole wavefront at once (works at any occupancy) */
+#define PI_SWEEP_PENCILREG 5 /* a workgroup owns a sub-box of target cells held
+                             in registers, one target per thread; the halo's
+                             X-pencils stream through LDS one Z-sheet at a time,
+                             the targets' own particles copied from registers
+                             (Sec. 5.3, X-pencil-reg); shapes 8x8x4 and 4x4x2 */
 
 /* Order of the per-particle outputs. */
 #define PI_ORDER_SORTED   0 /* output[k] belongs to sorted slot k */

@@ -702,6 +702,234 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     if (INV) reduce_invariants_lds(a, lb, icnt, inx, iny, inz, isc, irs, reinterpret_cast<double *>(sp));
 }
 
+// ------------------------------------------------------------------ pencil-reg
+// The X-pencil-reg organisation (Sec. 5.3): a workgroup owns a sub-box of
+// TX x TY x TZ target cells, and each thread keeps one target in registers
+// (targets beyond 256 are taken in further rounds).  The halo's source
+// X-pencils are then streamed through LDS one Z-sheet at a time (the HY
+// pencils of one z, clipped to the grid): a particle of a target cell of
+// the current round is copied into the sheet by the thread that holds it,
+// every other particle is read from global memory.  After each sheet is
+// staged, every target within one cell of it in z walks the three cells
+// around it in each of its three rows of the sheet.  Sheets go in z order,
+// rows in y order, cells in x order and particles in sorted order, so each
+// target sees its 27 cells in the canonical order and the outputs are
+// those of every other organisation.  A sub-box whose largest sheet holds
+// more than SCAP particles is left to the dense pass (single system) or
+// walked from global memory (batch), like an overflowing tile.
+template <int TX, int TY, int TZ, int SCAP, int PREC, bool INV, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_sweep_pencilreg(SweepArgs a, int32_t ntx, int32_t nty)
+{
+    constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+    constexpr int TR = TY * TZ; // target rows
+    static_assert(HY * HZ <= 64 && TR <= 64, "row tables are scanned by one wavefront");
+    __shared__ float4 sp[SCAP];
+    __shared__ int32_t cs[HY][HX + 1]; // staged index of each cell's first particle in the sheet
+    __shared__ int32_t rstart[HY + 1], gstart[HY], rbase[HY];
+    __shared__ int32_t tstart[TR + 1], tfirst[TR];
+    __shared__ int32_t sheetmax;
+
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    uint32_t tl = lb;
+    if (BATCH) {
+        const SysDev &sd = a.sys[enter_system(a, lb)];
+        tl = lb - (uint32_t)sd.block_base;
+        ntx = sd.ntx;
+        nty = sd.nty;
+    }
+    const int32_t bx = (int32_t)(tl % (uint32_t)ntx);
+    const int32_t by = (int32_t)((tl / (uint32_t)ntx) % (uint32_t)nty);
+    const int32_t bz = (int32_t)(tl / ((uint32_t)ntx * (uint32_t)nty));
+    const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    const int32_t cxlo = max(x0 - 1, 0), cxhi = min(x0 + TX, a.nx - 1);
+    const int32_t txhi = min(x0 + TX, a.nx);
+    const int32_t ylo = max(y0 - 1, 0), zlo = max(z0 - 1, 0); // the staging frame's corner
+    const int tid = threadIdx.x;
+    const float W = a.k.w;
+
+    // 1. target rows, and the largest sheet of the halo
+    if (tid < 64) {
+        int32_t tc = 0, tf = 0;
+        if (tid < TR) {
+            const int32_t y = y0 + tid % TY, z = z0 + tid / TY;
+            if (y < a.ny && z < a.nz && x0 < a.nx) {
+                const int64_t rb = (int64_t)a.nx * (y + (int64_t)a.ny * z);
+                tf = a.off[rb + x0];
+                tc = a.off[rb + txhi] - tf;
+            }
+        }
+        const int32_t tinc = wave_incl_scan(tc);
+        if (tid < TR) {
+            tstart[tid] = tinc - tc;
+            tfirst[tid] = tf;
+        }
+        if (tid == TR - 1) tstart[TR] = tinc;
+        // halo row (y, z) counts, summed per sheet
+        int32_t sheet = 0;
+        if (tid < HZ) {
+            const int32_t z = z0 - 1 + tid;
+            if (z >= 0 && z < a.nz)
+                for (int r = 0; r < HY; ++r) {
+                    const int32_t y = y0 - 1 + r;
+                    if (y < 0 || y >= a.ny) continue;
+                    const int64_t rb = (int64_t)a.nx * (y + (int64_t)a.ny * z);
+                    sheet += a.off[rb + cxhi + 1] - a.off[rb + cxlo];
+                }
+        }
+        sheet = wave_max(sheet);
+        if (tid == 0) sheetmax = sheet;
+    }
+    __syncthreads();
+    const int32_t ntarget = tstart[TR];
+    const bool overflow = sheetmax > SCAP;
+    long long icnt = 0;
+    double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
+    if (!BATCH) {
+        if (tid == 0) a.tflag[lb] = overflow ? 1 : 0;
+        if (overflow) {
+            if (tid == 0) *a.ovf = a.epoch;
+            if (INV) reduce_invariants(a, lb, 0, 0.0, 0.0, 0.0, 0.0, 0.0);
+            return;
+        }
+    }
+    auto target_row = [&](int32_t f) {
+        int tr = 0;
+        for (int r = 1; r < TR; ++r) tr = tstart[r] <= f ? r : tr;
+        return tr;
+    };
+    if (overflow) { // batch: walk the targets from global memory
+        for (int32_t f = tid; f < ntarget; f += kBlock) {
+            const int tr = target_row(f);
+            const int32_t k = tfirst[tr] + (f - tstart[tr]);
+            const int32_t y = y0 + tr % TY, z = z0 + tr / TY;
+            const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
+            Target<PREC, INV> T;
+            const float4 pk = a.p4[k];
+            walk_cells_global(a, k, ix, y, z, pk.x, pk.y, pk.z, T);
+            write_target(a, k, T);
+            if (INV) {
+                long long c1;
+                double a1, a2, a3, a4, a5;
+                target_invariants(T, pk.w, c1, a1, a2, a3, a4, a5);
+                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
+            }
+        }
+        if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
+        return;
+    }
+
+    for (int32_t f0 = 0; f0 < ntarget; f0 += kBlock) {
+        // this round's target, in registers
+        const int32_t f = f0 + tid;
+        const bool tgt = f < ntarget;
+        int32_t k = -1, ix = 0, ty_ = 0, tz_ = 0;
+        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (tgt) {
+            const int tr = target_row(f);
+            ty_ = tr % TY;
+            tz_ = tr / TY;
+            k = tfirst[tr] + (f - tstart[tr]);
+            ix = a.cell[k] - a.nx * ((y0 + ty_) + a.ny * (z0 + tz_));
+            const float4 q = a.p4[k];
+            t = make_float4(__builtin_fmaf((float)(ix - cxlo), W, q.x), __builtin_fmaf((float)(y0 + ty_ - ylo), W, q.y),
+                            __builtin_fmaf((float)(z0 + tz_ - zlo), W, q.z), q.w);
+        }
+        const int32_t fend = min(f0 + kBlock, ntarget); // targets of this round: [f0, fend)
+        Target<PREC, INV> T;
+        const int jl = ix > 0 ? (ix - cxlo) - 1 : (ix - cxlo);
+        const int jr = ix + 1 < a.nx ? (ix - cxlo) + 2 : (ix - cxlo) + 1;
+        for (int32_t zs = z0 - 1; zs <= z0 + TZ; ++zs) {
+            if (zs < 0 || zs >= a.nz) continue;
+            // 2. stage the sheet: row ranges, their LDS starts, cell starts
+            if (tid < 64) {
+                int32_t cnt = 0, gs = 0, rb32 = 0;
+                if (tid < HY) {
+                    const int32_t y = y0 - 1 + tid;
+                    if (y >= 0 && y < a.ny) {
+                        const int64_t rb = (int64_t)a.nx * (y + (int64_t)a.ny * zs);
+                        rb32 = (int32_t)rb;
+                        gs = a.off[rb + cxlo];
+                        cnt = a.off[rb + cxhi + 1] - gs;
+                    }
+                }
+                const int32_t inc = wave_incl_scan(cnt);
+                if (tid < HY) {
+                    rstart[tid] = inc - cnt;
+                    gstart[tid] = gs;
+                    rbase[tid] = rb32;
+                }
+                if (tid == HY - 1) rstart[HY] = inc;
+            }
+            __syncthreads();
+            for (int e = tid; e < HY * (HX + 1); e += kBlock) {
+                const int r = e / (HX + 1), jj = e % (HX + 1);
+                const int32_t y = y0 - 1 + r;
+                int32_t v = rstart[r];
+                if (jj <= cxhi - cxlo + 1 && y >= 0 && y < a.ny)
+                    v = a.off[(int64_t)rbase[r] + cxlo + jj] - gstart[r] + rstart[r];
+                cs[r][jj] = v;
+            }
+            // the round's targets in this sheet come from registers ...
+            const bool in_sheet_z = zs >= z0 && zs < z0 + TZ;
+            if (tgt && in_sheet_z && z0 + tz_ == zs) {
+                const int r = ty_ + 1;
+                sp[rstart[r] + (k - gstart[r])] = t;
+            }
+            // ... every other particle from global memory
+            const int32_t total = rstart[HY];
+            for (int32_t g2 = tid; g2 < total; g2 += kBlock) {
+                int r = 0;
+                for (int q = 1; q < HY; ++q) r = rstart[q] <= g2 ? q : r;
+                const int32_t g = gstart[r] + (g2 - rstart[r]);
+                const int32_t cx = a.cell[g] - rbase[r];
+                // a target of this round? (its row is a target row and it
+                // lies in the round's range of targets)
+                if (in_sheet_z && r >= 1 && r <= TY && cx >= x0 && cx < txhi) {
+                    const int trow = (r - 1) + TY * (zs - z0);
+                    const int32_t ft = tstart[trow] + (g - tfirst[trow]);
+                    if (ft >= f0 && ft < fend) continue;
+                }
+                const float4 q = a.p4[g];
+                sp[g2] = make_float4(__builtin_fmaf((float)(cx - cxlo), W, q.x),
+                                     __builtin_fmaf((float)(y0 - 1 + r - ylo), W, q.y),
+                                     __builtin_fmaf((float)(zs - zlo), W, q.z), q.w);
+            }
+            __syncthreads();
+            // 3. targets within one cell of the sheet walk their three rows
+            if (tgt) {
+                const int dz = zs - (z0 + tz_);
+                if (dz >= -1 && dz <= 1) {
+                    const int own = (dz == 0) ? rstart[ty_ + 1] + (k - gstart[ty_ + 1]) : -1;
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const int r = ty_ + 1 + dy;
+                        const int32_t y = y0 + ty_ + dy;
+                        if (y < 0 || y >= a.ny) continue;
+                        const int32_t j1 = cs[r][jr];
+                        for (int32_t j = cs[r][jl]; j < j1; ++j) {
+                            const float4 src = sp[j];
+                            const float ddx = t.x - src.x, ddy = t.y - src.y, ddz = t.z - src.z;
+                            const float d2 = sq_dist(ddx, ddy, ddz);
+                            if (d2 < a.k.hi && j != own && inside_cutoff(ddx, ddy, ddz, d2, a.k))
+                                T.accept(ddx, ddy, ddz, d2, src.w, a.k);
+                        }
+                    }
+                }
+            }
+            __syncthreads(); // the sheet area is restaged next
+        }
+        if (tgt) {
+            write_target(a, k, T);
+            if (INV) {
+                long long c1;
+                double a1, a2, a3, a4, a5;
+                target_invariants(T, t.w, c1, a1, a2, a3, a4, a5);
+                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
+            }
+        }
+    }
+    if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
+}
+
 // The dense pass of a single-system tile sweep: the targets of every tile
 // whose halo overflowed the LDS area, each walked from global memory by one
 // thread (the same walk and order as the tiles, so the same results).  A
@@ -921,6 +1149,9 @@ const TileCfg kTiles[] = {
     {7, 4, 4, 2, 1536, PI_SWEEP_SUBBOX},
     {8, 16, 4, 3, 768, PI_SWEEP_SUBBOX},
     {10, 7, 7, 5, 768, PI_SWEEP_SUBBOX},
+    // X-pencil-reg sub-boxes; cap = the largest Z-sheet staged at once
+    {11, 8, 8, 4, 1024, PI_SWEEP_PENCILREG},
+    {12, 4, 4, 2, 1024, PI_SWEEP_PENCILREG},
 };
 
 #ifndef PI_FIFO_DEPTH
@@ -928,7 +1159,7 @@ const TileCfg kTiles[] = {
 #endif
 constexpr int kFifo = PI_FIFO_DEPTH; // pair queue entries per lane
 constexpr int kStreamId = 9; // organisation id of the FIFO stream sweep
-constexpr int kMaxOrgId = 10; // organisation ids are 0 .. kMaxOrgId
+constexpr int kMaxOrgId = 12; // organisation ids are 0 .. kMaxOrgId
 
 // Workgroups of the dense pass that follows a single-system tile launch: a
 // persistent grid of up to four per compute unit, one per 256 particles at
@@ -943,7 +1174,7 @@ unsigned dense_blocks(int64_t n)
 // count of invariant partial records the launch writes (the tiles', then
 // the dense pass's); in batch mode given (the sum of the systems' tile
 // counts).
-template <int TX, int TY, int TZ, int CAP, int PREC, bool INV, bool BATCH>
+template <int TX, int TY, int TZ, int CAP, int PREC, bool INV, bool BATCH, bool REG = false>
 void launch_tile(pi_ctx *ctx, const char *name, const SweepArgs &a, hipStream_t s, unsigned &nblk)
 {
     int32_t ntx = 0, nty = 0;
@@ -954,15 +1185,23 @@ void launch_tile(pi_ctx *ctx, const char *name, const SweepArgs &a, hipStream_t 
         nblk = (unsigned)((int64_t)ntx * nty * ntz);
     }
     if (BATCH) {
-        PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0,
-                  s, a, ntx, nty);
+        if (REG)
+            PI_LAUNCH(ctx, name, (k_sweep_pencilreg<TX, TY, TZ, CAP, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0,
+                      s, a, ntx, nty);
+        else
+            PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock),
+                      0, s, a, ntx, nty);
         return;
     }
     SweepArgs b = a;
     b.epoch = ++*a.host_epoch;
     if (b.epoch == 0) b.epoch = ++*a.host_epoch; // 0 is the word's initial value
-    PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0, s,
-              b, ntx, nty);
+    if (REG)
+        PI_LAUNCH(ctx, name, (k_sweep_pencilreg<TX, TY, TZ, CAP, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0, s,
+                  b, ntx, nty);
+    else
+        PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0,
+                  s, b, ntx, nty);
     const unsigned nd = dense_blocks(a.n);
     PI_LAUNCH(ctx, "k_sweep_dense", (k_sweep_dense<PREC, INV>), dim3(nd), dim3(kBlock), 0, s, b, TX, TY, TZ, ntx,
               nty, nblk);
@@ -982,6 +1221,8 @@ void launch_sweep(pi_ctx *ctx, int tile_id, const SweepArgs &a, hipStream_t s, u
     case 7: launch_tile<4, 4, 2, 1536, PREC, INV, BATCH>(ctx, "k_sweep_tile<4,4,2>", a, s, nblk); break;
     case 8: launch_tile<16, 4, 3, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<16,4,3>", a, s, nblk); break;
     case 10: launch_tile<7, 7, 5, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<7,7,5>", a, s, nblk); break;
+    case 11: launch_tile<8, 8, 4, 1024, PREC, INV, BATCH, true>(ctx, "k_sweep_pencilreg<8,8,4>", a, s, nblk); break;
+    case 12: launch_tile<4, 4, 2, 1024, PREC, INV, BATCH, true>(ctx, "k_sweep_pencilreg<4,4,2>", a, s, nblk); break;
     case kStreamId:
         if (!BATCH) {
             nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
@@ -1066,7 +1307,7 @@ void pi_tile_opts(int tile, pi_interact_opts *out)
     int tx = 0, ty = 0, tz = 0;
     out->tile[0] = out->tile[1] = out->tile[2] = 0;
     if (tile > 0 && pi_tile_shape(tile, &tx, &ty, &tz)) {
-        out->sweep = (ty == 1 && tz == 1) ? PI_SWEEP_PENCIL : PI_SWEEP_SUBBOX;
+        out->sweep = tile_cfg(tile).sweep;
         out->tile[0] = tx;
         out->tile[1] = ty;
         out->tile[2] = tz;
@@ -1081,6 +1322,14 @@ int pi_pick_tile(const pi_interact_opts &o, double ppc)
 {
     if (o.sweep == PI_SWEEP_NOLDS) return 0;
     if (o.sweep == PI_SWEEP_STREAM) return kStreamId;
+    if (o.sweep == PI_SWEEP_PENCILREG) {
+        if (o.tile[0] > 0) {
+            for (const TileCfg &t : kTiles)
+                if (t.sweep == o.sweep && t.tx == o.tile[0] && t.ty == o.tile[1] && t.tz == o.tile[2]) return t.id;
+            return -1;
+        }
+        return ppc <= 2.0 ? 11 : 12;
+    }
     if (o.sweep == PI_SWEEP_PENCIL || o.sweep == PI_SWEEP_SUBBOX) {
         if (o.tile[0] > 0) {
             for (const TileCfg &t : kTiles)
@@ -1405,7 +1654,7 @@ pi_status pi_check_interact_opts(const pi_interact_opts &o, int64_t n, const flo
                                  const float *gy, const float *gz, const int32_t *count, const pi_invariants *inv)
 {
     if (o.precision < PI_PREC_COMPENSATED || o.precision > PI_PREC_FP64ACC) return PI_EINVAL;
-    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_STREAM) return PI_EINVAL;
+    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_PENCILREG) return PI_EINVAL;
     if (o.order != PI_ORDER_SORTED && o.order != PI_ORDER_ORIGINAL) return PI_EINVAL;
     const bool anyf = rho || gx || gy || gz;
     const bool allf = rho && gx && gy && gz;

@@ -119,7 +119,8 @@ def test_steps_match_the_oracle_and_a_full_binning(dev, case):
     _run(dev, s, vel, 12, 0.25, kscale * s.rc ** 5, lattice, tag=case)
 
 
-@pytest.mark.parametrize("sweep,tile", [("nolds", (0, 0, 0)), ("subbox", (4, 4, 4)), ("pencil", (30, 1, 1))])
+@pytest.mark.parametrize("sweep,tile", [("nolds", (0, 0, 0)), ("subbox", (4, 4, 4)), ("pencil", (30, 1, 1)),
+                                        ("pencilreg", (4, 4, 2))])
 def test_steps_do_not_depend_on_the_sweep_organisation(dev, sweep, tile):
     """Same system, same velocities: every organisation gives bit-identical
     trajectories (their sweep outputs agree bit for bit on lattice inputs)."""
