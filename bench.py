@@ -58,6 +58,7 @@ WORKLOADS = {
     "scale_8ppc": ("uniform 2^24 particles, unit cube, r_c=1/128, 128^3 cells (8 ppc)", "scale_8ppc"),
     "clustered": ("2^23 particles, 64 Gaussian blobs + 10% uniform, r_c=1/128, 128^3 cells", "clustered"),
     "tiny": ("uniform 32768 particles, unit cube, r_c=1/32, 32^3 cells", "tiny"),
+    "dense_64ppc": ("uniform 2^21 particles, unit cube, r_c=1/32, 32^3 cells (64 ppc)", "dense_64ppc"),
 }
 
 

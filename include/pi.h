@@ -158,6 +158,17 @@ pi_status pi_cells_get_view(pi_cells *cells, pi_cells_view *out);
                              X-pencils stream through LDS one Z-sheet at a time,
                              the targets' own particles copied from registers
                              (Sec. 5.3, X-pencil-reg); shapes 8x8x4 and 4x4x2 */
+#define PI_SWEEP_CELL   6 /* cell-based with LDS staging (Sec. 4.4, Par-Cell-SM,
+                             Algorithm 3), as a path for dense cells: a
+                             one-wavefront workgroup owns a run of tile[0]
+                             cells of an X-row and takes each cell holding at
+                             least tile[1] particles, 64 targets at a time; the
+                             cell's 9 neighbour rows stream through LDS and
+                             every lane walks them in step.  tile[1] = 1: every
+                             cell (the paper's organisation); larger: the
+                             no-LDS walk takes the targets of the other cells.
+                             Shapes (s, d, 1): (1, 1), (4, 1), (2, 16),
+                             (2, 32), (2, 64) */
 
 /* Order of the per-particle outputs. */
 #define PI_ORDER_SORTED   0 /* output[k] belongs to sorted slot k */
@@ -167,7 +178,8 @@ typedef struct pi_interact_opts {
     int32_t precision; /* PI_PREC_* */
     int32_t sweep;     /* PI_SWEEP_* */
     int32_t order;     /* PI_ORDER_* */
-    int32_t tile[3];   /* target cells per tile for PENCIL/SUBBOX; 0 = tuned */
+    int32_t tile[3];   /* target cells per tile for PENCIL/SUBBOX/PENCILREG/
+                          CELL; 0 = tuned */
 } pi_interact_opts;
 
 /* Global invariants, reduced in FP64 on the device. */
@@ -352,8 +364,10 @@ pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream);
 /*
  * Tuner.  The paper concludes that which organisation is fastest is hard to
  * predict and needs a profiling step per configuration (Sec. 8).  With
- * PI_SWEEP_AUTO the library times every compiled organisation (no-LDS and
- * each pencil / sub-box tile) once per size and occupancy class -- buckets
+ * PI_SWEEP_AUTO the library times every compiled organisation (no-LDS, the
+ * stream, each pencil / sub-box / pencil-reg tile, the cell-SM dense-cell
+ * passes from two particles per cell on and the cell-SM over every cell from
+ * 16 on) once per size and occupancy class -- buckets
  * of log2(n) and of the mean particles per cell -- on the caller's stream,
  * and reuses the fastest for that class afterwards (per context).  Tuning
  * runs the sweep once per candidate and waits for the stream.  In
@@ -362,7 +376,9 @@ pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream);
  * staged halo is expected to fit in LDS (mean + 6 standard deviations of a
  * Poisson count, up to about 1.2 particles per cell), then 4x4x4 (up to
  * about 6), then no LDS.  The same fit test picks the tile of PI_SWEEP_PENCIL
- * and PI_SWEEP_SUBBOX when tile[] is zero.
+ * and PI_SWEEP_SUBBOX when tile[] is zero; PI_SWEEP_CELL with tile[] zero
+ * takes every cell (one per workgroup) from 32 particles per cell on, else
+ * the cells holding 32 or more with the no-LDS walk for the rest.
  */
 #define PI_TUNE_STATIC 0
 #define PI_TUNE_TIMED  1

@@ -167,7 +167,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
     if (o.precision < PI_PREC_COMPENSATED || o.precision > PI_PREC_FP64ACC) return PI_EINVAL;
-    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_PENCILREG) return PI_EINVAL;
+    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_CELL) return PI_EINVAL;
     if (o.order != PI_ORDER_SORTED && o.order != PI_ORDER_ORIGINAL) return PI_EINVAL;
     const bool anyf = rho || gx || gy || gz;
     if (anyf && !(rho && gx && gy && gz)) return PI_EINVAL;
@@ -226,7 +226,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         int t = pi_pick_tile(o, ppc);
         if (t < 0) return PI_EINVAL;
         if (o.sweep == PI_SWEEP_AUTO) t = pi_auto_tile(ctx, o.precision, sys[s].n, ppc);
-        b->tile_of[s] = t;
+        b->tile_of[s] = pi_batch_org(t);
     }
     // sweep table: systems grouped by organisation (caller's order within a
     // group), one work-list layout per group

@@ -268,6 +268,7 @@ int pi_pick_tile(const pi_interact_opts &o, double ppc);
 void pi_tile_opts(int tile_id, pi_interact_opts *out);
 int pi_auto_tile(pi_ctx *ctx, int precision, int64_t n, double ppc);
 int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys);
+int pi_batch_org(int tile_id);
 pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
                          int64_t total_blocks, int64_t part_base, int tile_id, const pi_interact_opts &o, float *rho,
                          float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);

@@ -410,7 +410,7 @@ extern "C" pi_status pi_submit(pi_server *s, const pi_request *r, uint64_t *tick
     if (r->n > 0 && (!r->x || !r->y || !r->z || !r->w)) return PI_EINVAL;
     if (!pi_grid_valid(&r->grid) || !(r->jitter_sigma >= 0.0f) || !(r->lattice >= 0.0f)) return PI_EINVAL;
     if (r->precision < PI_PREC_COMPENSATED || r->precision > PI_PREC_FP64ACC) return PI_EINVAL;
-    if (r->sweep < PI_SWEEP_AUTO || r->sweep > PI_SWEEP_PENCILREG) return PI_EINVAL;
+    if (r->sweep < PI_SWEEP_AUTO || r->sweep > PI_SWEEP_CELL) return PI_EINVAL;
     const int64_t nc = (int64_t)r->grid.dims[0] * r->grid.dims[1] * r->grid.dims[2];
     const int64_t fp = footprint_bytes(r->n, nc, r->n_sweeps);
     if (fp > s->opts.hbm_budget) return PI_ENOMEM;

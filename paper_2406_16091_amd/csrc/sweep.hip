@@ -38,6 +38,9 @@ struct SweepArgs {
     uint32_t *ovf;
     uint32_t epoch;
     uint32_t *host_epoch; // host memory, not read by the kernels
+    // no-LDS walk: > 0 skips the targets of cells holding at least this many
+    // particles (the cell-SM pass takes them)
+    int32_t dense_min;
     KernelConst k;
     // batch mode: system table, per-system kernel constants
     const SysDev *sys;
@@ -159,7 +162,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
         k = (int32_t)(lb * kBlock + threadIdx.x);
         kend = min(a.off[a.nc], a.n);
     }
-    const bool active = k < kend;
+    bool active = k < kend;
+    if (!BATCH && active && a.dense_min > 0) {
+        const int32_t c = a.cell[k];
+        active = a.off[c + 1] - a.off[c] < a.dense_min;
+    }
     Target<PREC, INV> T;
     float wi = 0.f;
     if (active) {
@@ -930,6 +937,213 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pencilreg(SweepArgs a, int32_t
     if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
 }
 
+// ------------------------------------------------------------------ cell-SM
+// The cell-based organisation with LDS staging (Par-Cell-SM, Sec. 4.4,
+// Algorithm 3) on one-wavefront workgroups, also as a path for dense cells.
+// A workgroup owns a run of SEG consecutive cells of one X-row and takes each
+// of them that holds at least DENSE particles in turn (DENSE = 1: every
+// cell, the paper's organisation; larger: the no-LDS walk takes the other
+// cells' targets in the same launch sequence).  One lane keeps one target,
+// 64 at a time (the paper's loop over a cell's targets in steps of the block
+// size).  The 27 neighbour cells are 9 X-rows of three cells, each row one
+// contiguous range of the sorted arrays; the rows are copied into LDS in
+// fills of up to CAP particles, and the wavefront walks each staged cell
+// with one trip count, every lane reading the same LDS word, G sources per
+// LDS round trip.  A lane skips a neighbour cell whose nearest face is surely
+// beyond the cutoff from its target (the reach test of the no-LDS walk, which
+// changes no result) and evaluates an accepted pair at once.  Differences
+// are taken in the target's own cell frame with the roundings of the no-LDS
+// walk, and each target sees its 27 cells in the canonical order, so the
+// outputs are bitwise those of the no-LDS walk, also off the lattice.
+__device__ __forceinline__ void wave_reduce_partial(InvPartial *dst, long long cnt, double nx, double ny, double nz,
+                                                    double sc, double rs)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        cnt += __shfl_xor(cnt, o, 64);
+        nx += __shfl_xor(nx, o, 64);
+        ny += __shfl_xor(ny, o, 64);
+        nz += __shfl_xor(nz, o, 64);
+        sc += __shfl_xor(sc, o, 64);
+        rs += __shfl_xor(rs, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        InvPartial p;
+        p.pairs = cnt;
+        p.net[0] = nx;
+        p.net[1] = ny;
+        p.net[2] = nz;
+        p.scale = sc;
+        p.rho_sum = rs;
+        p.pad[0] = p.pad[1] = 0.0;
+        *dst = p;
+    }
+}
+
+constexpr int kCellBlock = 64;
+constexpr int kCellGroup = 4; // staged sources read per LDS round trip
+
+template <int CAP, int PREC, bool INV, bool BATCH>
+__global__ __launch_bounds__(kCellBlock) void k_sweep_cell(SweepArgs a, int32_t seg, int32_t dense, int32_t ntx,
+                                                           int32_t nty)
+{
+    constexpr int G = kCellGroup;
+    __shared__ float4 stage[CAP];
+    __shared__ int4 rows[9];          // per neighbour row: first sorted index of its left, centre and
+                                      // right cell (x, y, z) and of the cell after them (w)
+    __shared__ int32_t rstart[10];    // each row's start in the concatenated source list
+
+    const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    uint32_t tl = lb;
+    if (BATCH) {
+        const SysDev &sd = a.sys[enter_system(a, lb)];
+        tl = lb - (uint32_t)sd.block_base;
+        ntx = sd.ntx;
+        nty = sd.nty;
+    }
+    const int32_t bx = (int32_t)(tl % (uint32_t)ntx);
+    const int32_t iy = (int32_t)((tl / (uint32_t)ntx) % (uint32_t)nty);
+    const int32_t iz = (int32_t)(tl / ((uint32_t)ntx * (uint32_t)nty));
+    const int32_t x0 = bx * seg, nrun = min(seg, a.nx - x0);
+    const int64_t rc0 = (int64_t)a.nx * (iy + (int64_t)a.ny * iz);
+    const int lane = threadIdx.x;
+    const float W = a.k.w;
+    const float reach2 = a.k.reach2;
+    auto sel = [](int q, float m, float o, float p) { return q == 0 ? m : (q == 1 ? o : p); };
+
+    // the run's cells that this workgroup takes (lane q: cell x0 + q)
+    int32_t cb = 0, ce = 0;
+    if (lane < nrun) {
+        cb = a.off[rc0 + x0 + lane];
+        ce = a.off[rc0 + x0 + lane + 1];
+    }
+    uint64_t todo = __ballot(lane < nrun && ce - cb >= dense);
+
+    long long icnt = 0;
+    double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
+    while (todo) {
+        const int q = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const int32_t ix = x0 + q;
+        const int32_t c0 = __shfl(cb, q, 64), c1 = __shfl(ce, q, 64);
+        // the 9 neighbour rows (lane r: dy = r % 3 - 1, dz = r / 3 - 1)
+        int32_t total;
+        {
+            int4 rg = make_int4(0, 0, 0, 0);
+            if (lane < 9) {
+                const int32_t cy = iy + lane % 3 - 1, cz = iz + lane / 3 - 1;
+                if (cy >= 0 && cy < a.ny && cz >= 0 && cz < a.nz) {
+                    const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz) + ix;
+                    rg.y = a.off[rb];
+                    rg.z = a.off[rb + 1];
+                    rg.x = ix > 0 ? a.off[rb - 1] : rg.y;
+                    rg.w = ix + 1 < a.nx ? a.off[rb + 2] : rg.z;
+                }
+            }
+            const int32_t len = rg.w - rg.x;
+            const int32_t inc = wave_incl_scan(len);
+            if (lane < 9) {
+                rows[lane] = rg;
+                rstart[lane] = inc - len;
+            }
+            if (lane == 8) rstart[9] = inc;
+            total = __shfl(inc, 8, 64);
+        }
+        __syncthreads();
+        for (int32_t t0 = c0; t0 < c1; t0 += 64) {
+            const int32_t k = t0 + lane;
+            const bool tgt = k < c1;
+            const float4 pk = tgt ? a.p4[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float xi = pk.x, yi = pk.y, zi = pk.z;
+            const float xm = xi - (float)(-1) * W, xp = xi - (float)(1) * W;
+            const float ym = yi - (float)(-1) * W, yp = yi - (float)(1) * W;
+            const float zm = zi - (float)(-1) * W, zp = zi - (float)(1) * W;
+            // the reach test per row: bit r of `rowok` if row r is within
+            // reach, of `useL` / `useR` if its left / right cell is too
+            uint32_t rowok = 0, useL = 0, useR = 0;
+            if (tgt) {
+                const float gyl = yi * yi, gyr = (W - yi) * (W - yi);
+                const float gzl = zi * zi, gzr = (W - zi) * (W - zi);
+                const float tlx = ix > 0 ? reach2 - xi * xi : -1.0f;
+                const float trx = ix + 1 < a.nx ? reach2 - (W - xi) * (W - xi) : -1.0f;
+#pragma unroll
+                for (int r = 0; r < 9; ++r) {
+                    const int dy = r % 3 - 1, dz = r / 3 - 1;
+                    const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + (dz < 0 ? gzl : (dz > 0 ? gzr : 0.f));
+                    rowok |= (gyz < reach2 ? 1u : 0u) << r;
+                    useL |= (gyz < tlx ? 1u : 0u) << r;
+                    useR |= (gyz < trx ? 1u : 0u) << r;
+                }
+            }
+            Target<PREC, INV> T;
+            for (int32_t p0 = 0; p0 < total; p0 += CAP) {
+                const int32_t nfill = min(CAP, total - p0);
+                // stage the fill: list position p is in the last row whose start is <= p
+#pragma unroll 4
+                for (int32_t e = lane; e < nfill; e += 64) {
+                    const int32_t p = p0 + e;
+                    int r = 0;
+#pragma unroll
+                    for (int u = 1; u < 9; ++u) r += rstart[u] <= p ? 1 : 0;
+                    stage[e] = a.p4[rows[r].x + (p - rstart[r])];
+                }
+                __syncthreads();
+                for (int r = 0; r < 9; ++r) {
+                    const int4 rgl = rows[r];
+                    const int4 rg = make_int4(__builtin_amdgcn_readfirstlane(rgl.x), __builtin_amdgcn_readfirstlane(rgl.y),
+                                              __builtin_amdgcn_readfirstlane(rgl.z), __builtin_amdgcn_readfirstlane(rgl.w));
+                    // sorted index of slot s: base + s
+                    const int32_t base = rg.x - __builtin_amdgcn_readfirstlane(rstart[r]) + p0;
+                    if (rg.w == rg.x || rg.x - base >= nfill || rg.w - base <= 0) continue;
+                    const int dyc = r % 3, dzc = r / 3;
+                    const float ty = sel(dyc, ym, yi, yp), tz = sel(dzc, zm, zi, zp);
+                    const bool rin = (rowok >> r) & 1u;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const int32_t ja = d == 0 ? rg.x : (d == 1 ? rg.y : rg.z);
+                        const int32_t jz = d == 0 ? rg.y : (d == 1 ? rg.z : rg.w);
+                        const int32_t sa = max(ja - base, 0), sz = min(jz - base, nfill);
+                        if (sa >= sz) continue;
+                        const bool en = tgt && rin && (d == 0 ? ((useL >> r) & 1u) : (d == 2 ? ((useR >> r) & 1u) : true));
+                        if (!__any(en)) continue;
+                        const float tx = sel(d, xm, xi, xp);
+                        // the target itself is a source only in its own cell
+                        const int32_t self = (r == 4 && d == 1) ? k - base : -1;
+                        // one staged source, tested by every lane and taken by
+                        // those whose neighbour cell this is
+                        auto test = [&](int32_t sl, const float4 &src) {
+                            const float ddx = tx - src.x, ddy = ty - src.y, ddz = tz - src.z;
+                            const float t = sq_dist(ddx, ddy, ddz);
+                            if (en && t < a.k.hi && sl != self && inside_cutoff(ddx, ddy, ddz, t, a.k))
+                                T.accept(ddx, ddy, ddz, t, src.w, a.k);
+                        };
+                        int32_t s = sa;
+                        for (; s + G <= sz; s += G) {
+                            float4 src[G];
+#pragma unroll
+                            for (int u = 0; u < G; ++u) src[u] = stage[s + u];
+#pragma unroll
+                            for (int u = 0; u < G; ++u) test(s + u, src[u]);
+                        }
+                        for (; s < sz; ++s) test(s, stage[s]);
+                    }
+                }
+                __syncthreads(); // the area is refilled next
+            }
+            if (tgt) {
+                write_target(a, k, T);
+                if (INV) {
+                    long long c1n;
+                    double a1, a2, a3, a4, a5;
+                    target_invariants(T, pk.w, c1n, a1, a2, a3, a4, a5);
+                    icnt += c1n; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
+                }
+            }
+        }
+        __syncthreads(); // the row tables are rewritten for the next cell
+    }
+    if (INV) wave_reduce_partial(a.partials + lb, icnt, inx, iny, inz, isc, irs);
+}
+
 // The dense pass of a single-system tile sweep: the targets of every tile
 // whose halo overflowed the LDS area, each walked from global memory by one
 // thread (the same walk and order as the tiles, so the same results).  A
@@ -1152,14 +1366,23 @@ const TileCfg kTiles[] = {
     // X-pencil-reg sub-boxes; cap = the largest Z-sheet staged at once
     {11, 8, 8, 4, 1024, PI_SWEEP_PENCILREG},
     {12, 4, 4, 2, 1024, PI_SWEEP_PENCILREG},
+    // cell-SM: tx = cells of an X-row per workgroup, ty = the fewest particles
+    // a cell must hold to be taken (1: all; larger: the no-LDS walk takes the
+    // rest); cap = particles per LDS fill
+    {13, 1, 1, 1, 256, PI_SWEEP_CELL},
+    {14, 4, 1, 1, 256, PI_SWEEP_CELL},
+    {15, 2, 16, 1, 256, PI_SWEEP_CELL},
+    {16, 2, 32, 1, 256, PI_SWEEP_CELL},
+    {17, 2, 64, 1, 256, PI_SWEEP_CELL},
 };
 
 #ifndef PI_FIFO_DEPTH
 #define PI_FIFO_DEPTH 4
 #endif
 constexpr int kFifo = PI_FIFO_DEPTH; // pair queue entries per lane
+constexpr int kCellCap = 256;       // cell-SM: particles per LDS fill
 constexpr int kStreamId = 9; // organisation id of the FIFO stream sweep
-constexpr int kMaxOrgId = 12; // organisation ids are 0 .. kMaxOrgId
+constexpr int kMaxOrgId = 17; // organisation ids are 0 .. kMaxOrgId
 
 // Workgroups of the dense pass that follows a single-system tile launch: a
 // persistent grid of up to four per compute unit, one per 256 particles at
@@ -1208,6 +1431,37 @@ void launch_tile(pi_ctx *ctx, const char *name, const SweepArgs &a, hipStream_t 
     nblk += nd;
 }
 
+// The cell-SM sweep: one workgroup per run of `seg` cells of an X-row (the
+// LDS fills take any occupancy, so there is no dense pass).  With dense > 1
+// (single system only) the no-LDS walk first takes the targets of the cells
+// holding fewer than `dense` particles; nblk counts both launches'
+// workgroups, the no-LDS walk's partial records first.
+
+template <int CAP, int PREC, bool INV, bool BATCH>
+void launch_cell(pi_ctx *ctx, const char *name, int32_t seg, int32_t dense, const SweepArgs &a, hipStream_t s,
+                 unsigned &nblk)
+{
+    if (BATCH) {
+        PI_LAUNCH(ctx, name, (k_sweep_cell<CAP, PREC, INV, BATCH>), dim3(nblk), dim3(kCellBlock), 0, s, a,
+                  seg, 1, 0, 0);
+        return;
+    }
+    SweepArgs b = a;
+    unsigned n0 = 0;
+    if (dense > 1) {
+        n0 = (unsigned)((a.n + kBlock - 1) / kBlock);
+        SweepArgs c = a;
+        c.dense_min = dense;
+        PI_LAUNCH(ctx, "k_sweep_nolds", (k_sweep_nolds<PREC, INV, false>), dim3(n0), dim3(kBlock), 0, s, c);
+        if (b.partials) b.partials += n0;
+    }
+    const int32_t ntx = (a.nx + seg - 1) / seg;
+    const unsigned n1 = (unsigned)((int64_t)ntx * a.ny * a.nz);
+    PI_LAUNCH(ctx, name, (k_sweep_cell<CAP, PREC, INV, false>), dim3(n1), dim3(kCellBlock), 0, s, b, seg,
+              dense, ntx, a.ny);
+    nblk = n0 + n1;
+}
+
 template <int PREC, bool INV, bool BATCH>
 void launch_sweep(pi_ctx *ctx, int tile_id, const SweepArgs &a, hipStream_t s, unsigned &nblk)
 {
@@ -1223,6 +1477,11 @@ void launch_sweep(pi_ctx *ctx, int tile_id, const SweepArgs &a, hipStream_t s, u
     case 10: launch_tile<7, 7, 5, 768, PREC, INV, BATCH>(ctx, "k_sweep_tile<7,7,5>", a, s, nblk); break;
     case 11: launch_tile<8, 8, 4, 1024, PREC, INV, BATCH, true>(ctx, "k_sweep_pencilreg<8,8,4>", a, s, nblk); break;
     case 12: launch_tile<4, 4, 2, 1024, PREC, INV, BATCH, true>(ctx, "k_sweep_pencilreg<4,4,2>", a, s, nblk); break;
+    case 13: launch_cell<kCellCap, PREC, INV, BATCH>(ctx, "k_sweep_cell<1,1>", 1, 1, a, s, nblk); break;
+    case 14: launch_cell<kCellCap, PREC, INV, BATCH>(ctx, "k_sweep_cell<4,1>", 4, 1, a, s, nblk); break;
+    case 15: launch_cell<kCellCap, PREC, INV, BATCH>(ctx, "k_sweep_cell<2,16>", 2, 16, a, s, nblk); break;
+    case 16: launch_cell<kCellCap, PREC, INV, BATCH>(ctx, "k_sweep_cell<2,32>", 2, 32, a, s, nblk); break;
+    case 17: launch_cell<kCellCap, PREC, INV, BATCH>(ctx, "k_sweep_cell<2,64>", 2, 64, a, s, nblk); break;
     case kStreamId:
         if (!BATCH) {
             nblk = (unsigned)((a.n + kBlock - 1) / kBlock);
@@ -1322,6 +1581,14 @@ int pi_pick_tile(const pi_interact_opts &o, double ppc)
 {
     if (o.sweep == PI_SWEEP_NOLDS) return 0;
     if (o.sweep == PI_SWEEP_STREAM) return kStreamId;
+    if (o.sweep == PI_SWEEP_CELL) {
+        if (o.tile[0] > 0) {
+            for (const TileCfg &t : kTiles)
+                if (t.sweep == o.sweep && t.tx == o.tile[0] && t.ty == o.tile[1] && t.tz == o.tile[2]) return t.id;
+            return -1;
+        }
+        return ppc >= 32.0 ? 13 : 16;
+    }
     if (o.sweep == PI_SWEEP_PENCILREG) {
         if (o.tile[0] > 0) {
             for (const TileCfg &t : kTiles)
@@ -1342,6 +1609,16 @@ int pi_pick_tile(const pi_interact_opts &o, double ppc)
     return pick_tile_default(ppc);
 }
 
+// The organisation a batch runs for a system whose own choice is `tile`: the
+// cell-SM's dense-cell pass, which pairs it with a no-LDS launch, is run as
+// the no-LDS walk alone (the same outputs).
+int pi_batch_org(int tile)
+{
+    if (tile > 0 && tile_cfg(tile).id == tile && tile_cfg(tile).sweep == PI_SWEEP_CELL && tile_cfg(tile).ty > 1)
+        return 0;
+    return tile;
+}
+
 // Batch sweep: h_sys gets each system's block_base / ntx / nty for tile_id
 // (the caller uploads the table to d_sys before launching).  Returns the
 // total workgroup count.
@@ -1349,6 +1626,7 @@ int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys)
 {
     int tx = 0, ty = 0, tz = 0;
     const bool tiled = tile_id > 0 && pi_tile_shape(tile_id, &tx, &ty, &tz);
+    if (tiled && tile_cfg(tile_id).sweep == PI_SWEEP_CELL) ty = tz = 1; // runs of tx cells
     int64_t base = 0;
     for (int32_t s = 0; s < nsys; ++s) {
         SysDev &d = h_sys[s];
@@ -1415,7 +1693,16 @@ uint64_t tune_key(int prec, int64_t n, double ppc, bool batch)
 // partial records in `a` are overwritten.  The static default is timed first and a later organisation
 // displaces the current best only when it is faster by more than 5%, so that
 // near-ties (within run-to-run noise) resolve the same way every time.
-int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, bool inv, hipStream_t s)
+// Organisations that cannot win at mean occupancy ppc and are not timed: the
+// cell-SM over every cell below 16 particles per cell (a wavefront of mostly
+// idle lanes per cell), and its dense-cell pass below 2.
+bool worth_timing(int id, double ppc)
+{
+    if (id < 13 || id > 17) return true;
+    return id <= 14 ? ppc >= 16.0 : ppc >= 2.0;
+}
+
+int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, bool inv, double ppc, hipStream_t s)
 {
     SweepArgs a = a0;
     if (!inv) a.partials = nullptr;
@@ -1431,7 +1718,7 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, bool 
     float best_ms = 0.f;
     for (int i = -1; i <= kMaxOrgId; ++i) {
         const int cand = i < 0 ? first : i;
-        if (i >= 0 && cand == first) continue;
+        if (i >= 0 && (cand == first || !worth_timing(cand, ppc))) continue;
         unsigned nblk = 0;
         float ms = 0.f;
         bool ok = true;
@@ -1469,7 +1756,7 @@ pi_status tuned_tile(pi_ctx *ctx, const SweepArgs &a, int prec, int64_t n, doubl
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PI_OK;
-    const int best = time_candidates(ctx, a, prec, *tile, inv, s);
+    const int best = time_candidates(ctx, a, prec, *tile, inv, ppc, s);
     if (best < 0) return PI_EDEVICE;
     std::lock_guard<std::mutex> g(t->mu);
     t->choice[key] = best;
@@ -1547,8 +1834,11 @@ namespace {
 int64_t sweep_blocks(int tile, int64_t n, int32_t nx, int32_t ny, int32_t nz)
 {
     int tx = 0, ty = 0, tz = 0;
-    if (tile > 0 && tile != kStreamId && pi_tile_shape(tile, &tx, &ty, &tz))
+    if (tile > 0 && tile != kStreamId && pi_tile_shape(tile, &tx, &ty, &tz)) {
+        if (tile_cfg(tile).sweep == PI_SWEEP_CELL) // runs of tx cells, after the no-LDS walk's records
+            return (int64_t)((nx + tx - 1) / tx) * ny * nz + (ty > 1 ? (n + kBlock - 1) / kBlock : 0);
         return (int64_t)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty) * ((nz + tz - 1) / tz) + dense_blocks(n);
+    }
     const int64_t b = (n + kBlock - 1) / kBlock;
     return b > 0 ? b : 1;
 }
@@ -1654,7 +1944,7 @@ pi_status pi_check_interact_opts(const pi_interact_opts &o, int64_t n, const flo
                                  const float *gy, const float *gz, const int32_t *count, const pi_invariants *inv)
 {
     if (o.precision < PI_PREC_COMPENSATED || o.precision > PI_PREC_FP64ACC) return PI_EINVAL;
-    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_PENCILREG) return PI_EINVAL;
+    if (o.sweep < PI_SWEEP_AUTO || o.sweep > PI_SWEEP_CELL) return PI_EINVAL;
     if (o.order != PI_ORDER_SORTED && o.order != PI_ORDER_ORIGINAL) return PI_EINVAL;
     const bool anyf = rho || gx || gy || gz;
     const bool allf = rho && gx && gy && gz;

@@ -20,8 +20,8 @@ LIB_PATH = os.path.join(HERE, "libpi.so")
 PI_OK, PI_EINVAL, PI_ENOMEM, PI_ERANGE, PI_EDEVICE, PI_EAGAIN, PI_ENOTFOUND, PI_ESTATE, PI_ESTEP = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 PI_PREC_COMPENSATED, PI_PREC_PLAIN, PI_PREC_FP64ACC = 0, 1, 2
-PI_SWEEP_AUTO, PI_SWEEP_NOLDS, PI_SWEEP_PENCIL, PI_SWEEP_SUBBOX, PI_SWEEP_STREAM, PI_SWEEP_PENCILREG = \
-    0, 1, 2, 3, 4, 5
+PI_SWEEP_AUTO, PI_SWEEP_NOLDS, PI_SWEEP_PENCIL, PI_SWEEP_SUBBOX, PI_SWEEP_STREAM, PI_SWEEP_PENCILREG, PI_SWEEP_CELL = \
+    0, 1, 2, 3, 4, 5, 6
 PI_ORDER_SORTED, PI_ORDER_ORIGINAL = 0, 1
 PI_NOALLOC_SCRATCH_RECORDS = 1 << 19
 PI_PAIRFN_LJ, PI_PAIRFN_LOWFLOP, PI_PAIRFN_HIGHFLOP = 1, 2, 3
@@ -29,7 +29,8 @@ PAIRFNS = {"lj": PI_PAIRFN_LJ, "lowflop": PI_PAIRFN_LOWFLOP, "highflop": PI_PAIR
 
 PRECISIONS = {"compensated": PI_PREC_COMPENSATED, "plain": PI_PREC_PLAIN, "fp64acc": PI_PREC_FP64ACC}
 SWEEPS = {"auto": PI_SWEEP_AUTO, "nolds": PI_SWEEP_NOLDS, "pencil": PI_SWEEP_PENCIL,
-          "subbox": PI_SWEEP_SUBBOX, "stream": PI_SWEEP_STREAM, "pencilreg": PI_SWEEP_PENCILREG}
+          "subbox": PI_SWEEP_SUBBOX, "stream": PI_SWEEP_STREAM, "pencilreg": PI_SWEEP_PENCILREG,
+          "cell": PI_SWEEP_CELL}
 
 
 class PiError(RuntimeError):

@@ -96,6 +96,12 @@ def scale_8ppc(seed=2):
     return uniform_unit_cube(1 << 24, -7, seed, "uniform-16.8M-128^3-8ppc")
 
 
+def dense_64ppc(seed=4):
+    """2^21 uniform particles, r_c = 1/32, 32^3 cells (64 per cell): the
+    occupancy of the dense cores of the clustered inputs, everywhere."""
+    return uniform_unit_cube(1 << 21, -5, seed, "uniform-2.1M-32^3-64ppc")
+
+
 def _blob_sigmas(rng, n_blobs, n_blob_pts, g, lo, hi, peak_ppc):
     """Blob widths in cells: drawn from U(lo, hi) * g, raised where needed so
     that no blob's centre holds more than about peak_ppc particles per cell

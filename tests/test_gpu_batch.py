@@ -59,7 +59,8 @@ def _check(res, ref):
 
 
 @pytest.mark.parametrize("sweep,tile", [("auto", (0, 0, 0)), ("nolds", (0, 0, 0)), ("stream", (0, 0, 0)),
-                                        ("subbox", (4, 4, 4)), ("pencil", (30, 1, 1)), ("subbox", (6, 6, 6))])
+                                        ("subbox", (4, 4, 4)), ("pencil", (30, 1, 1)), ("subbox", (6, 6, 6)),
+                                        ("pencilreg", (4, 4, 2)), ("cell", (4, 1, 1)), ("cell", (2, 32, 1))])
 def test_batch_matches_oracle_per_system(dev, sweep, tile):
     systems = _mixed_systems()
     db = dev.DeviceBatch(systems)

@@ -27,7 +27,9 @@ pytestmark = pytest.mark.gpu
 SWEEPS = [("nolds", (0, 0, 0)), ("stream", (0, 0, 0)), ("pencil", (254, 1, 1)), ("pencil", (62, 1, 1)),
           ("pencil", (30, 1, 1)), ("subbox", (8, 8, 3)), ("subbox", (6, 6, 6)), ("subbox", (4, 4, 4)),
           ("subbox", (4, 4, 2)), ("subbox", (16, 4, 3)), ("subbox", (7, 7, 5)),
-          ("pencilreg", (8, 8, 4)), ("pencilreg", (4, 4, 2))]
+          ("pencilreg", (8, 8, 4)), ("pencilreg", (4, 4, 2)),
+          ("cell", (1, 1, 1)), ("cell", (4, 1, 1)), ("cell", (2, 16, 1)), ("cell", (2, 32, 1)),
+          ("cell", (2, 64, 1))]
 SAMPLE = 1_000_000
 
 

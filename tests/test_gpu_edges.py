@@ -49,7 +49,9 @@ TOL = 1e-5
 SWEEPS = [("nolds", (0, 0, 0)), ("stream", (0, 0, 0)), ("pencil", (254, 1, 1)), ("pencil", (62, 1, 1)),
           ("pencil", (30, 1, 1)), ("subbox", (8, 8, 3)), ("subbox", (6, 6, 6)), ("subbox", (4, 4, 4)),
           ("subbox", (4, 4, 2)), ("subbox", (16, 4, 3)), ("subbox", (7, 7, 5)),
-          ("pencilreg", (8, 8, 4)), ("pencilreg", (4, 4, 2))]
+          ("pencilreg", (8, 8, 4)), ("pencilreg", (4, 4, 2)),
+          ("cell", (1, 1, 1)), ("cell", (4, 1, 1)), ("cell", (2, 16, 1)), ("cell", (2, 32, 1)),
+          ("cell", (2, 64, 1))]
 PRECISIONS = ["compensated", "fp64acc", "plain"]
 
 
@@ -267,12 +269,12 @@ def _frame_band(sweep, tile, cw):
     """Bound on |computed - exact| of a pair's difference vector for one
     organisation, with the origin at zero.  Each stored cell-relative
     coordinate fl(x - i w) is off by at most ulp(w) (its value lies within
-    about [0, w]).  The no-LDS and stream walks shift the target by -+w and
-    subtract, two roundings of values below 2w: at most 2 ulp(w) more per
-    axis.  A tile stages both particles at fl(c w + x_rel) with c up to the
+    about [0, w]).  The no-LDS, stream and cell-SM walks shift the target by
+    -+w and subtract, two roundings of values below 2w: at most 2 ulp(w) more
+    per axis.  A tile stages both particles at fl(c w + x_rel) with c up to the
     halo's extent E_a = (T_a + 2) w, a rounding of ulp(E_a)/2 each, and then
     subtracts exactly (both on the ulp(E_a) grid, difference below 2w)."""
-    if sweep in ("nolds", "stream"):
+    if sweep in ("nolds", "stream", "cell"):
         e = [4 * _ulp(cw)] * 3
     else:
         e = [2 * _ulp(cw) + _ulp((t + 2) * cw) for t in tile]
@@ -285,7 +287,9 @@ def test_off_lattice_counts_within_the_rounding_band(dev, case):
     """Off-lattice positions and a cell width that is not a power of two:
     each organisation's counts lie between the oracle's at r_c -+ delta, and
     its floats within the tolerance widened by what a displacement of delta
-    changes (module docstring)."""
+    changes (module docstring).  The walks that compute in the target's cell
+    frame (no-LDS, stream, cell-SM) take the same roundings in the same
+    order, so their outputs are bitwise equal even here."""
     s = OFF[case]()
     b, ref = _oracle(s)
     h = float(s.rc)
@@ -310,6 +314,11 @@ def test_off_lattice_counts_within_the_rounding_band(dev, case):
         res = ds.results()
         cnt = res["count"].astype(np.int64)
         assert np.all(cnt >= lo) and np.all(cnt <= hi), (sweep, tile, delta)
+        if sweep == "nolds":
+            cell_frame = res
+        elif sweep in ("stream", "cell"):
+            for k in ("rho", "gx", "gy", "gz", "count"):
+                assert (res[k].view(np.uint32) == cell_frame[k].view(np.uint32)).all(), (sweep, tile, k)
         differ[f"{sweep}{tile}"] = int((cnt != ref.count).sum())
         nband = (hi - lo).astype(np.float64)
         sw = wmax * ref.count

@@ -120,7 +120,8 @@ def test_steps_match_the_oracle_and_a_full_binning(dev, case):
 
 
 @pytest.mark.parametrize("sweep,tile", [("nolds", (0, 0, 0)), ("subbox", (4, 4, 4)), ("pencil", (30, 1, 1)),
-                                        ("pencilreg", (4, 4, 2))])
+                                        ("pencilreg", (4, 4, 2)), ("cell", (4, 1, 1)),
+                                        ("cell", (2, 16, 1))])
 def test_steps_do_not_depend_on_the_sweep_organisation(dev, sweep, tile):
     """Same system, same velocities: every organisation gives bit-identical
     trajectories (their sweep outputs agree bit for bit on lattice inputs)."""
