@@ -247,8 +247,8 @@ def _fresh_requests(pool, count, rng, sweeps, first_seed):
 
 
 def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(0.5, 0.8), seed: int = 5,
-                n_closed: int = 24):
-    """Serving: requests of N log-uniform in [1e4, 4e6] particles (uniform or
+                n_closed: int = 24, n_lo: float = 1e4, n_hi: float = 4e6, max_slots: int = 64, n_streams: int = 4):
+    """Serving: requests of N log-uniform in [n_lo, n_hi] particles (uniform or
     8-blob clustered, 1/2/4/8 per cell), each swept `sweeps` times with
     Gaussian displacements of 0.1 r_c between sweeps.  Every submission is a
     fresh particle set (_fresh_requests); no request is submitted twice.
@@ -260,7 +260,7 @@ def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(
     import torch
     from paper_2406_16091_amd import device, pi, synth
 
-    pool = synth.serve_requests(n_pool, seed=seed)
+    pool = synth.serve_requests(n_pool, seed=seed, n_lo=n_lo, n_hi=n_hi)
     rng = np.random.default_rng(seed)
     ctx = device.Context.get(0).handle
     torch.cuda.synchronize()
@@ -295,13 +295,14 @@ def bench_serve(n_pool: int = 48, sweeps: int = 8, seconds: float = 3.0, loads=(
     t_seq, pairs_seq = run_all(one, closed)
     pi.pi_server_destroy(one)
 
-    server = pi.pi_server_create(ctx, max_slots=8, n_streams=4)
-    run_all(server, fresh(8, largest))
-    run_all(server, fresh(24))
+    server = pi.pi_server_create(ctx, max_slots=max_slots, n_streams=n_streams)
+    run_all(server, fresh(n_streams, largest))
+    run_all(server, fresh(n_closed))
     t_sat, pairs_sat = run_all(server, closed)
     assert pairs_sat == pairs_seq, "a request's results depend on what runs beside it"
     rate_sat = len(closed) / t_sat
-    out = {"distinct_systems": n_pool, "fresh_request_sets": True, "closed_loop_requests": n_closed,
+    out = {"request_particles": [n_lo, n_hi], "max_slots": max_slots, "lanes": n_streams,
+           "distinct_systems": n_pool, "fresh_request_sets": True, "closed_loop_requests": n_closed,
            "sweeps_per_request": sweeps, "mean_particles": float(np.mean([s.n for s in pool])),
            "saturation_requests_per_s": round(rate_sat, 2),
            "saturation_pairs_per_s": round(pairs_sat / t_sat, 1),
@@ -649,6 +650,8 @@ def main():
     if not args.no_serve:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serve"] = bench_serve()
+        print("[bench] serving small requests", file=sys.stderr, flush=True)
+        out["serve_small"] = bench_serve(n_pool=64, n_closed=256, n_lo=2e3, n_hi=1e5, max_slots=256)
     if not args.no_table1:
         print("[bench] table 1 grid", file=sys.stderr, flush=True)
         out["table1"] = bench_table1()

@@ -439,19 +439,26 @@ pi_status pi_batch_sync(pi_ctx *ctx, pi_batch *batch, pi_stream stream);
  * a Gaussian step (counter-based RNG, reflected at the box faces, rounded to
  * a lattice) and the system is re-binned in place: its cell list stays
  * resident on the GPU for the whole request.  A scheduler thread admits
- * queued requests first-in first-out as soon as a slot is free and the
- * request's device-memory footprint fits the budget, and queues the whole
- * request on one of the server's streams, so requests run concurrently and
- * new ones are admitted while older ones are in flight.  Results stay in
- * pinned host memory owned by the server until pi_release.  All calls are
- * thread-safe.
+ * queued requests first-in first-out while fewer than max_slots are in
+ * flight and their device-memory footprints fit the budget, and runs the
+ * requests it admits at one time as one batch on a free lane (one of
+ * n_streams streams): one upload per request, then per sweep one batched
+ * displacement and one batched re-binning and sweep of all of them
+ * (pi_batch_run), then one download per request.  Lanes run side by side,
+ * so requests that arrive while batches are on the GPU are admitted onto
+ * another lane as soon as one is free.  A batch holds requests of the same
+ * n_sweeps, precision and sweep, each under 2^18 particles; a larger
+ * request, or one admitted alone, runs the plain single-system path (pi_bin,
+ * pi_interact).  A request's results are the same whatever it shares its
+ * batch with.  Results stay in pinned host memory owned by
+ * the server until pi_release.  All calls are thread-safe.
  */
 typedef struct pi_server pi_server;
 
 typedef struct pi_server_opts {
     int64_t hbm_budget;      /* device bytes the admitted requests may hold together */
-    int32_t max_slots;       /* requests in flight at once (1..256) */
-    int32_t n_streams;       /* HIP streams the slots are spread over (1..16) */
+    int32_t max_slots;       /* requests in flight at once, over all lanes (1..4096) */
+    int32_t n_streams;       /* lanes: streams that each run one batch at a time (1..16) */
     int32_t queue_capacity;  /* requests waiting for admission; beyond -> PI_EAGAIN */
     int32_t pad;
 } pi_server_opts;
@@ -494,7 +501,9 @@ pi_status pi_server_create(pi_ctx *ctx, const pi_server_opts *opts, pi_server **
 /* Admitted requests finish first; queued ones end with PI_EAGAIN. */
 pi_status pi_server_destroy(pi_server *server);
 /* PI_EAGAIN if the queue is full, PI_ENOMEM if the request alone exceeds the
- * budget, PI_EINVAL for a bad request.  *ticket identifies the request. */
+ * budget, PI_ERANGE if a particle lies outside its box (by the binning's own
+ * float32 decision), PI_EINVAL for a bad request.  *ticket identifies the
+ * request. */
 pi_status pi_submit(pi_server *server, const pi_request *req, uint64_t *ticket);
 /* Non-blocking: out->done tells whether the request has finished. */
 pi_status pi_poll(pi_server *server, uint64_t ticket, pi_result *out);

@@ -375,8 +375,10 @@ pi_status pi_ensure_capacity(pi_cells *c, int64_t n, int64_t n_cells, hipStream_
         if (hipMalloc(b[i].ptr, (size_t)count * b[i].elem) != hipSuccess) {
             free_buffers(c);
             c->cap_n = c->cap_cells = 0;
+            c->cap_tflag = 0;
             return PI_ENOMEM;
         }
+        if (b[i].ptr == (void **)&c->tflag) c->cap_tflag = count;
     }
     c->cap_n = cap_n;
     c->cap_cells = cap_c;

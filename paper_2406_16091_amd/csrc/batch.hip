@@ -39,10 +39,12 @@ struct pi_batch {
     std::vector<int> tile_of;       // organisation of each system (caller's order)
     std::vector<BatchGroup> groups;
     int64_t total_blocks;
-    // graph cache
+    // graph cache (or, with `direct`, the layout the tables hold)
     std::vector<unsigned char> sig;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    bool direct;       // launch the sequence directly instead of capturing it
+    bool layout_valid; // direct: the tables hold the layout of `sig`
     hipStream_t graph_stream;
     // side streams and events that fork the sweep groups off the binning
     // and join them back (default priority, created on first use)
@@ -73,7 +75,14 @@ static void drop_graph(pi_batch *b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->layout_valid = false;
     b->sig.clear();
+}
+
+void pi_batch_set_direct(pi_batch *b, bool direct)
+{
+    drop_graph(b);
+    b->direct = direct;
 }
 
 extern "C" pi_status pi_batch_destroy(pi_batch *b)
@@ -195,6 +204,11 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         PI_CHECK_HIP(hipGraphLaunch(b->exec, stream));
         return PI_OK;
     }
+    if (b->direct && b->layout_valid && sig == b->sig && stream) {
+        pi_status sst = ensure_side(b);
+        if (sst != PI_OK) return sst;
+        return launch_all(b, x, y, z, w, b->cells->n, b->cells->n_cells, o, rho, gx, gy, gz, count, inv, stream);
+    }
     drop_graph(b);
 
     // binning table (caller's order)
@@ -295,6 +309,18 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         pi_cells_forget(c);
         return st;
     }
+    if (b->total_blocks > c->cap_tflag) {
+        // one overflow flag per workgroup of the sweep launches
+        PI_CHECK_HIP(hipStreamSynchronize(stream));
+        if (c->tflag) (void)hipFree(c->tflag);
+        c->tflag = nullptr;
+        c->cap_tflag = 0;
+        if (hipMalloc((void **)&c->tflag, (size_t)b->total_blocks) != hipSuccess) {
+            pi_cells_forget(c);
+            return PI_ENOMEM;
+        }
+        c->cap_tflag = b->total_blocks;
+    }
     if (b->total_blocks + 64 > c->cap_partials) {
         PI_CHECK_HIP(hipStreamSynchronize(stream));
         if (c->partials) (void)hipFree(c->partials);
@@ -322,6 +348,13 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
 
     if (!stream) // the null stream cannot be captured: launch directly
         return launch_all(b, x, y, z, w, n_total, cells_total, o, rho, gx, gy, gz, count, inv, stream);
+    if (b->direct) {
+        pi_status sst = ensure_side(b);
+        if (sst != PI_OK) return sst;
+        b->sig = sig;
+        b->layout_valid = true;
+        return launch_all(b, x, y, z, w, n_total, cells_total, o, rho, gx, gy, gz, count, inv, stream);
+    }
 
     pi_status sst = ensure_side(b);
     if (sst != PI_OK) return sst;

@@ -96,9 +96,11 @@ struct pi_cells {
     // invariant partials
     int64_t cap_partials;
     void *partials;
-    // per tile of a sweep launch: whether its halo overflowed the LDS area
-    // (cap_cells + 64 bytes; a launch has at most one tile per cell)
+    // per workgroup of a sweep launch: whether its tile's halo overflowed
+    // the LDS area (cap_tflag bytes: cap_cells + 64, as a single system has
+    // at most one tile per cell; a batch may enlarge it to its workgroups)
     uint8_t *tflag;
+    int64_t cap_tflag;
     uint32_t sweep_epoch; // number of the last tile sweep launched on the object
     // time stepping (allocated once pi_state_set_velocity is first called on
     // the object; the "2" arrays are the other half of a double buffer whose
@@ -215,8 +217,10 @@ __device__ __forceinline__ uint32_t div_by(uint32_t n, uint64_t m)
 }
 
 // One axis of the cell decision: t = (x - o) / w in float32 (IEEE), inside
-// iff 0 <= t < n, index floor(t).  NaN fails the test.
-__device__ __forceinline__ bool axis_index(float x, float o, float w, int32_t n, int32_t &out)
+// iff 0 <= t < n, index floor(t).  NaN fails the test.  The host takes the
+// same decision with the same two roundings (the library is built without
+// floating-point contraction).
+__host__ __device__ __forceinline__ bool axis_index(float x, float o, float w, int32_t n, int32_t &out)
 {
     const float u = x - o;
     const float t = u / w;
@@ -269,6 +273,10 @@ void pi_tile_opts(int tile_id, pi_interact_opts *out);
 int pi_auto_tile(pi_ctx *ctx, int precision, int64_t n, double ppc);
 int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys);
 int pi_batch_org(int tile_id);
+// A batch object that launches its sequence directly on every call instead
+// of capturing it into a graph (for layouts used a few times only); the
+// tables are rebuilt only when the layout changes.
+void pi_batch_set_direct(pi_batch *batch, bool direct);
 pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
                          int64_t total_blocks, int64_t part_base, int tile_id, const pi_interact_opts &o, float *rho,
                          float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);

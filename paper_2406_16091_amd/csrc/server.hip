@@ -1,12 +1,17 @@
 // Request server: many particle systems submitted over time, each swept R
 // times with small random displacements between sweeps and its cell list
-// kept resident on the GPU.  A scheduler thread admits queued requests as
-// soon as a slot is free and the request's HBM footprint fits the budget,
-// and queues the request's whole sequence (upload, R x [jitter, re-bin,
-// sweep], download) on one of the server's streams; requests on different
-// streams overlap on the device, and new ones are admitted while older ones
-// are still running.  Results land in pinned host memory owned by the
-// server until the ticket is released.
+// kept resident on the GPU for the whole request.  A scheduler thread admits
+// queued requests first-in first-out while the request cap and the HBM
+// budget allow, and runs the requests it admits together as one batch on a
+// free lane (a stream with its own buffers): one upload per request, then R
+// times [batched displacement, batched re-binning and sweep of every system
+// at once (pi_batch_run)], then one download per request.  A request of
+// 2^18 particles or more, which fills the GPU by itself, or one admitted
+// alone takes the plain single-system path (pi_bin, pi_interact) instead,
+// which gives the same results.  Lanes run side by
+// side, so requests that arrive while a batch is on the GPU start on
+// another lane as soon as one is free.  Results land in pinned host memory
+// owned by the server until the ticket is released.
 #include <math.h>
 #include <string.h>
 #include <time.h>
@@ -38,46 +43,115 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-// Displace every particle by sigma * N(0,1) per axis (Box-Muller on two
-// uniforms drawn from the counter (seed, step, particle, axis)), reflect at
-// the faces of the box [o, o + L), L = n w, and round the offset from o down
-// to the lattice (if > 0).  The stored coordinate o + v is rounded once more
-// when o is large against L; pi_keep_inside then moves it by single ulps
-// until the binning's float32 decision keeps it inside the box.
+// One request of a batch, as the device kernels see it.
+struct BatchReq {
+    int64_t off;      // first particle in the concatenated arrays
+    int64_t in_byte;  // its inputs (x, y, z, w of n each) in the upload area
+    int64_t out_byte; // its results in the download area
+    int32_t n;
+    int32_t pad0;
+    float sigma, lattice;
+    float ox, oy, oz, w;
+    int32_t nx, ny, nz;
+    int32_t pad1;
+    uint64_t seed;
+};
 
-__global__ __launch_bounds__(256) void k_jitter(int32_t n, float *x, float *y, float *z, uint64_t seed,
-                                                int32_t step, float sigma, float lattice, float ox, float oy,
-                                                float oz, float w, int32_t nx, int32_t ny, int32_t nz)
+// The request owning concatenated particle i (requests in offset order).
+__device__ __forceinline__ int req_of(const BatchReq *__restrict__ t, int32_t m, int64_t i)
 {
-    const int32_t i = (int32_t)(blockIdx.x * 256 + threadIdx.x);
-    if (i >= n) return;
-    float *p[3] = {x, y, z};
-    const float o[3] = {ox, oy, oz};
-    const int32_t dims[3] = {nx, ny, nz};
+    int lo = 0, hi = m; // t[lo].off <= i < t[hi].off
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t[mid].off <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Upload area (each request's x, y, z, w back to back) to the concatenated
+// arrays x, y, z, w (cap entries apart).
+__global__ __launch_bounds__(256) void k_unpack_inputs(int64_t ntot, const BatchReq *__restrict__ t, int32_t m,
+                                                       const char *__restrict__ up, float *__restrict__ xyzw,
+                                                       int64_t cap)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ntot) return;
+    const BatchReq &r = t[req_of(t, m, i)];
+    const float *src = reinterpret_cast<const float *>(up + r.in_byte);
+    const int64_t j = i - r.off;
+    xyzw[i] = src[j];
+    xyzw[cap + i] = src[r.n + j];
+    xyzw[2 * cap + i] = src[2 * (int64_t)r.n + j];
+    xyzw[3 * cap + i] = src[3 * (int64_t)r.n + j];
+}
+
+// Displace every particle by sigma * N(0,1) per axis (Box-Muller on two
+// uniforms drawn from the counter (seed, step, particle, axis), the particle
+// counted within its own request), reflect at the faces of the box [o, o +
+// L), L = n w, and round the offset from o down to the lattice (if > 0).  The
+// stored coordinate o + v is rounded once more when o is large against L;
+// pi_keep_inside then moves it by single ulps until the binning's float32
+// decision keeps it inside the box.
+__global__ __launch_bounds__(256) void k_jitter(int64_t ntot, const BatchReq *__restrict__ t, int32_t m,
+                                                float *__restrict__ xyzw, int64_t cap, int32_t step)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ntot) return;
+    const BatchReq &r = t[req_of(t, m, i)];
+    if (!(r.sigma > 0.0f)) return;
+    const uint64_t li = (uint64_t)(i - r.off);
+    const float o[3] = {r.ox, r.oy, r.oz};
+    const int32_t dims[3] = {r.nx, r.ny, r.nz};
     for (int a = 0; a < 3; ++a) {
-        const float L = (float)dims[a] * w;
-        const uint64_t r = mix64(seed ^ mix64(((uint64_t)step << 40) ^ ((uint64_t)i << 2) ^ (uint64_t)a));
-        const float u1 = ((float)(uint32_t)(r >> 40) + 0.5f) * (1.0f / 16777216.0f); // (0, 1)
-        const float u2 = (float)(uint32_t)(r & 0xffffffu) * (1.0f / 16777216.0f);     // [0, 1)
+        float *p = xyzw + (int64_t)a * cap + i;
+        const float L = (float)dims[a] * r.w;
+        const uint64_t h = mix64(r.seed ^ mix64(((uint64_t)step << 40) ^ (li << 2) ^ (uint64_t)a));
+        const float u1 = ((float)(uint32_t)(h >> 40) + 0.5f) * (1.0f / 16777216.0f); // (0, 1)
+        const float u2 = (float)(uint32_t)(h & 0xffffffu) * (1.0f / 16777216.0f);     // [0, 1)
         const float g = sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
-        float v = p[a][i] - o[a] + sigma * g;
+        float v = *p - o[a] + r.sigma * g;
         if (v < 0.0f) v = -v;
         if (v >= L) v = 2.0f * L - v;
-        if (lattice > 0.0f) {
-            v = floorf(v / lattice) * lattice;
-            v = fminf(fmaxf(v, 0.0f), L - lattice);
+        if (r.lattice > 0.0f) {
+            v = floorf(v / r.lattice) * r.lattice;
+            v = fminf(fmaxf(v, 0.0f), L - r.lattice);
         } else {
             v = fminf(fmaxf(v, 0.0f), L * (1.0f - 1e-7f));
         }
-        p[a][i] = pi_keep_inside(o[a] + v, o[a], w, dims[a]);
+        *p = pi_keep_inside(o[a] + v, o[a], r.w, dims[a]);
     }
 }
 
-// The device error word of a binned system back to zero (a fill kernel, not
-// a memset, so that the sequence stays capturable).
-__global__ void k_clear_err(uint32_t *err)
+// Results to the download area: per request rho, gx, gy, gz, count, x, y, z
+// (max(n, 1) entries each), then its R invariants.
+__global__ __launch_bounds__(256) void k_pack_results(int64_t ntot, const BatchReq *__restrict__ t, int32_t m,
+                                                      const float *__restrict__ out5,
+                                                      const float *__restrict__ xyzw, int64_t cap,
+                                                      char *__restrict__ down)
 {
-    if (threadIdx.x == 0) err[0] = 0u;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= ntot) return;
+    const BatchReq &r = t[req_of(t, m, i)];
+    float *dst = reinterpret_cast<float *>(down + r.out_byte);
+    const int64_t j = i - r.off, nn = r.n > 0 ? r.n : 1;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) dst[a * nn + j] = out5[a * cap + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dst[(5 + a) * nn + j] = xyzw[a * cap + i];
+}
+
+// hist[k * m + q] (sweep k of request q) to request q's download block.
+__global__ __launch_bounds__(256) void k_pack_invariants(const BatchReq *__restrict__ t, int32_t m, int32_t sweeps,
+                                                         const pi_invariants *__restrict__ hist,
+                                                         char *__restrict__ down)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)m * sweeps) return;
+    const int q = (int)(e / sweeps), k = (int)(e % sweeps);
+    const BatchReq &r = t[q];
+    const int64_t nn = r.n > 0 ? r.n : 1;
+    pi_invariants *dst = reinterpret_cast<pi_invariants *>(down + r.out_byte + 32 * nn);
+    dst[k] = hist[(int64_t)k * m + q];
 }
 
 } // namespace
@@ -90,26 +164,34 @@ struct Ticket {
     int64_t footprint;
     int32_t status;
     bool done;
-    int slot;
+    int lane;
     double t_submit, t_start, t_done;
     // pinned host buffer: the inputs (x, y, z, w) on the way in; then the
-    // outputs rho, gx, gy, gz, count, x, y, z, the per-sweep invariants and
-    // the device error word (pinned_size)
+    // outputs rho, gx, gy, gz, count, x, y, z (max(n, 1) entries each) and
+    // the per-sweep invariants (pinned_size)
     void *pinned;
     size_t pinned_bytes;
 };
 
-struct Slot {
+// A stream with its own buffers, running one batch of requests at a time.
+struct Lane {
     bool busy = false;
-    uint64_t ticket = 0;
+    std::vector<uint64_t> tickets;   // the batch in flight
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    pi_cells *cells = nullptr;
-    float *d_in = nullptr;           // x, y, z, w (4 x cap)
+    pi_batch *batch = nullptr;       // batches of two or more requests
+    pi_cells *cells = nullptr;       // a request alone
+    bool alone = false;              // the batch in flight is one request
+    char *d_up = nullptr;            // upload area (16 bytes per particle)
+    char *d_down = nullptr;          // download area
+    float *d_xyzw = nullptr;         // x, y, z, w (4 x cap)
     float *d_out = nullptr;          // rho, gx, gy, gz, count (5 x cap)
-    pi_invariants *d_inv = nullptr;  // [cap_sweeps]
-    int64_t cap = 0, cap_sweeps = 0;
-    pi_status launch_status = PI_OK; // error queuing the request (retired with it)
+    pi_invariants *d_inv = nullptr;  // one sweep's invariants [cap_req]
+    pi_invariants *d_hist = nullptr; // every sweep's [cap_hist]
+    BatchReq *d_req = nullptr;
+    BatchReq *h_req = nullptr;       // pinned staging of the request table
+    int64_t cap = 0, cap_up = 0, cap_down = 0, cap_req = 0, cap_hist = 0;
+    pi_status launch_status = PI_OK; // error queuing the batch (retired with it)
 };
 
 } // namespace
@@ -121,10 +203,10 @@ struct pi_server {
     std::condition_variable cv;
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, Ticket *> tickets;
-    std::vector<Slot> slots;
-    std::vector<hipStream_t> streams;
+    std::vector<Lane> lanes;
     uint64_t next_id = 1;
     int64_t in_use = 0;
+    int32_t in_flight = 0;
     bool stop = false;
     std::thread worker;
     std::vector<std::pair<size_t, void *>> pool;
@@ -134,28 +216,29 @@ namespace {
 
 int64_t footprint_bytes(int64_t n, int64_t nc, int32_t sweeps)
 {
-    // device bytes a request holds: inputs 16, outputs 20, binned arrays 24,
-    // radix ping-pong 48 and histograms ~1 per particle; counts, offsets and
-    // invariant partials per cell; a fixed allowance
-    return 109 * n + 8 * nc + 2 * 64 * (nc + n / 64) + 64 * (int64_t)sweeps + (1 << 20);
+    // device bytes a request holds: upload 16, inputs 16, outputs 20,
+    // download 32, binned arrays 24, radix ping-pong 48 and histograms ~1
+    // per particle; counts, offsets and invariant partials per cell; per
+    // sweep invariants; a fixed allowance
+    return 157 * n + 8 * nc + 2 * 64 * (nc + n / 64) + 2 * 64 * (int64_t)sweeps + (1 << 20);
 }
 
 // Pinned host buffer of a request: inputs x, y, z, w on the way in; then
-// rho, gx, gy, gz, count, x, y, z (8 arrays of max(n, 1) words), the
-// per-sweep invariants and the device error word.
+// rho, gx, gy, gz, count, x, y, z (8 arrays of max(n, 1) words) and the
+// per-sweep invariants.
 size_t pinned_size(int64_t n, int32_t sweeps)
 {
     return (size_t)std::max<int64_t>(1, n) * 32 + sizeof(pi_invariants) * (size_t)sweeps + 256;
 }
 
+size_t result_bytes(int64_t n, int32_t sweeps)
+{
+    return (size_t)std::max<int64_t>(1, n) * 32 + sizeof(pi_invariants) * (size_t)sweeps;
+}
+
 pi_invariants *pinned_invariants(void *pin, int64_t n)
 {
     return (pi_invariants *)((float *)pin + 8 * std::max<int64_t>(n, 1));
-}
-
-uint32_t *pinned_err(void *pin, int64_t n, int32_t sweeps)
-{
-    return (uint32_t *)(pinned_invariants(pin, n) + sweeps);
 }
 
 // Pinned buffers come in size classes (powers of two from 1 MiB), so that a
@@ -182,185 +265,314 @@ void *pool_take(pi_server *s, size_t bytes, size_t *got)
     return p;
 }
 
-// Device buffers of a slot grow to the next power of two of the particles
-// they must hold, so that a stream of varied request sizes stops growing
-// them (each growth frees the old buffers, which waits for the device).
-pi_status slot_reserve(pi_server *s, Slot &sl, int64_t n, int32_t sweeps)
+int64_t grow_pow2(int64_t need, int64_t floor_)
 {
-    if (n > sl.cap || !sl.d_in) {
-        int64_t cap = 1024;
-        while (cap < n) cap <<= 1;
-        if (sl.d_in) (void)hipFree(sl.d_in);
-        if (sl.d_out) (void)hipFree(sl.d_out);
-        sl.d_in = sl.d_out = nullptr;
-        if (hipMalloc((void **)&sl.d_in, (size_t)cap * 16) != hipSuccess) return PI_ENOMEM;
-        if (hipMalloc((void **)&sl.d_out, (size_t)cap * 20) != hipSuccess) return PI_ENOMEM;
-        sl.cap = cap;
+    int64_t c = floor_;
+    while (c < need) c <<= 1;
+    return c;
+}
+
+// Device buffers of a lane grow to the next power of two of what a batch
+// needs (each growth frees the old buffers, which waits for the device, so
+// a stream of varied batches soon stops growing them).  The lane is idle.
+pi_status lane_reserve(Lane &ln, int64_t n, int64_t down, int32_t m, int64_t hist)
+{
+    auto realloc_ = [](void **p, size_t bytes) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        return hipMalloc(p, bytes) == hipSuccess;
+    };
+    if (n > ln.cap || !ln.d_xyzw) {
+        const int64_t cap = grow_pow2(n, 1024);
+        if (!realloc_((void **)&ln.d_xyzw, (size_t)cap * 16) || !realloc_((void **)&ln.d_out, (size_t)cap * 20) ||
+            !realloc_((void **)&ln.d_up, (size_t)cap * 16)) {
+            ln.cap = 0;
+            return PI_ENOMEM;
+        }
+        ln.cap = ln.cap_up = cap;
     }
-    if (sweeps > sl.cap_sweeps || !sl.d_inv) {
-        if (sl.d_inv) (void)hipFree(sl.d_inv);
-        sl.d_inv = nullptr;
-        if (hipMalloc((void **)&sl.d_inv, sizeof(pi_invariants) * (size_t)sweeps) != hipSuccess) return PI_ENOMEM;
-        sl.cap_sweeps = sweeps;
+    if (down > ln.cap_down || !ln.d_down) {
+        const int64_t cap = grow_pow2(down, 1 << 16);
+        if (!realloc_((void **)&ln.d_down, (size_t)cap)) {
+            ln.cap_down = 0;
+            return PI_ENOMEM;
+        }
+        ln.cap_down = cap;
     }
-    if (!sl.cells) return pi_cells_create(s->ctx, &sl.cells);
+    if (m > ln.cap_req || !ln.d_req) {
+        const int64_t cap = grow_pow2(m, 64);
+        if (!realloc_((void **)&ln.d_req, sizeof(BatchReq) * (size_t)cap) ||
+            !realloc_((void **)&ln.d_inv, sizeof(pi_invariants) * (size_t)cap)) {
+            ln.cap_req = 0;
+            return PI_ENOMEM;
+        }
+        if (ln.h_req) (void)hipHostFree(ln.h_req);
+        ln.h_req = nullptr;
+        if (hipHostMalloc((void **)&ln.h_req, sizeof(BatchReq) * (size_t)cap, hipHostMallocDefault) != hipSuccess) {
+            ln.cap_req = 0;
+            return PI_ENOMEM;
+        }
+        ln.cap_req = cap;
+    }
+    if (hist > ln.cap_hist || !ln.d_hist) {
+        const int64_t cap = grow_pow2(hist, 64);
+        if (!realloc_((void **)&ln.d_hist, sizeof(pi_invariants) * (size_t)cap)) {
+            ln.cap_hist = 0;
+            return PI_ENOMEM;
+        }
+        ln.cap_hist = cap;
+    }
     return PI_OK;
 }
 
-// Queue a request's whole sequence on its slot's stream (the caller records
-// the slot's completion event after it).
-pi_status launch_request(pi_server *s, Slot &sl, Ticket *t)
+// Queue a batch of requests (same sweep count and options) on an idle lane;
+// the caller records the lane's completion event after it.
+pi_status launch_batch(pi_server *s, Lane &ln, const std::vector<Ticket *> &ts)
 {
-    const pi_request &r = t->req;
-    const int64_t n = r.n;
-    pi_status st = slot_reserve(s, sl, n, r.n_sweeps);
-    if (st != PI_OK) return st;
-    hipStream_t q = sl.stream;
-    const int64_t c = sl.cap;
-    float *dx = sl.d_in, *dy = dx + c, *dz = dy + c, *dw = dz + c;
-    float *rho = sl.d_out, *gx = rho + c, *gy = gx + c, *gz = gy + c;
-    int32_t *cnt = (int32_t *)(gz + c);
-    float *h = (float *)t->pinned;
-    const size_t b = (size_t)n * 4;
-    if (n > 0) {
-        PI_CHECK_HIP(hipMemcpyAsync(dx, h, b, hipMemcpyHostToDevice, q));
-        PI_CHECK_HIP(hipMemcpyAsync(dy, h + n, b, hipMemcpyHostToDevice, q));
-        PI_CHECK_HIP(hipMemcpyAsync(dz, h + 2 * n, b, hipMemcpyHostToDevice, q));
-        PI_CHECK_HIP(hipMemcpyAsync(dw, h + 3 * n, b, hipMemcpyHostToDevice, q));
+    const int32_t m = (int32_t)ts.size();
+    const pi_request &r0 = ts[0]->req;
+    const int32_t R = r0.n_sweeps;
+    int64_t ntot = 0, down = 0;
+    for (const Ticket *t : ts) {
+        ntot += t->req.n;
+        down += (int64_t)result_bytes(t->req.n, R);
     }
+    // a request alone runs the plain single-system path (pi_bin, pi_interact)
+    ln.alone = m == 1;
+    if (ln.alone && !ln.cells) {
+        pi_status st = pi_cells_create(s->ctx, &ln.cells);
+        if (st != PI_OK) return st;
+    }
+    if (!ln.alone && !ln.batch) {
+        pi_status st = pi_batch_create(s->ctx, &ln.batch);
+        if (st != PI_OK) return st;
+        // a batch's layout serves its own sweeps only: launched directly,
+        // no graph to capture per batch
+        pi_batch_set_direct(ln.batch, true);
+    }
+    pi_status st = lane_reserve(ln, ntot, down, m, (int64_t)m * R);
+    if (st != PI_OK) return st;
+    hipStream_t q = ln.stream;
+    std::vector<pi_system_desc> sys((size_t)m);
+    int64_t off = 0, ob = 0;
+    for (int32_t i = 0; i < m; ++i) {
+        const pi_request &r = ts[i]->req;
+        BatchReq &b = ln.h_req[i];
+        memset(&b, 0, sizeof(b));
+        b.off = off;
+        b.in_byte = 16 * off;
+        b.out_byte = ob;
+        b.n = (int32_t)r.n;
+        b.sigma = r.jitter_sigma;
+        b.lattice = r.lattice;
+        b.ox = r.grid.origin[0];
+        b.oy = r.grid.origin[1];
+        b.oz = r.grid.origin[2];
+        b.w = r.grid.cell_w;
+        b.nx = r.grid.dims[0];
+        b.ny = r.grid.dims[1];
+        b.nz = r.grid.dims[2];
+        b.seed = r.seed;
+        sys[i].offset = off;
+        sys[i].n = r.n;
+        sys[i].grid = r.grid;
+        off += r.n;
+        ob += (int64_t)result_bytes(r.n, R);
+    }
+    PI_CHECK_HIP(hipMemcpyAsync(ln.d_req, ln.h_req, sizeof(BatchReq) * (size_t)m, hipMemcpyHostToDevice, q));
+    for (int32_t i = 0; i < m; ++i)
+        if (ts[i]->req.n > 0)
+            PI_CHECK_HIP(hipMemcpyAsync(ln.d_up + ln.h_req[i].in_byte, ts[i]->pinned, (size_t)ts[i]->req.n * 16,
+                                        hipMemcpyHostToDevice, q));
+    const int64_t cap = ln.cap;
+    float *x = ln.d_xyzw, *y = x + cap, *z = y + cap, *w = z + cap;
+    float *rho = ln.d_out, *gx = rho + cap, *gy = gx + cap, *gz = gy + cap;
+    int32_t *cnt = (int32_t *)(gz + cap);
+    const unsigned nb = (unsigned)((ntot + 255) / 256);
+    if (ntot > 0)
+        PI_LAUNCH(s->ctx, "k_unpack_inputs", k_unpack_inputs, dim3(nb), dim3(256), 0, q, ntot,
+                  (const BatchReq *)ln.d_req, m, (const char *)ln.d_up, ln.d_xyzw, cap);
     pi_interact_opts o;
     memset(&o, 0, sizeof(o));
-    o.precision = r.precision;
-    o.sweep = r.sweep;
+    o.precision = r0.precision;
+    o.sweep = r0.sweep;
     o.order = PI_ORDER_ORIGINAL;
-    const pi_grid &g = r.grid;
-    if (o.sweep == PI_SWEEP_AUTO) {
+    pi_interact_opts o1 = o;
+    if (ln.alone && o1.sweep == PI_SWEEP_AUTO) {
         // no timed trials on a request's path: the tuner's cached choice for
-        // the request's class if there is one, else the static rule
-        const double nc = (double)g.dims[0] * g.dims[1] * g.dims[2];
-        pi_tile_opts(pi_auto_tile(s->ctx, r.precision, n, (double)n / nc), &o);
+        // the request's class if there is one, else the static rule (what a
+        // batch takes for the same system)
+        const double nc = (double)r0.grid.dims[0] * r0.grid.dims[1] * r0.grid.dims[2];
+        pi_tile_opts(pi_auto_tile(s->ctx, r0.precision, r0.n, (double)r0.n / nc), &o1);
     }
-    for (int32_t k = 0; k < r.n_sweeps; ++k) {
-        if (k > 0 && r.jitter_sigma > 0.0f && n > 0)
-            PI_LAUNCH(s->ctx, "k_jitter", k_jitter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, q, (int32_t)n,
-                      dx, dy, dz, r.seed, k, r.jitter_sigma, r.lattice, g.origin[0], g.origin[1], g.origin[2],
-                      g.cell_w, g.dims[0], g.dims[1], g.dims[2]);
-        st = pi_bin(s->ctx, sl.cells, dx, dy, dz, dw, n, &g, q);
+    bool jitter = false;
+    for (const Ticket *t : ts) jitter = jitter || t->req.jitter_sigma > 0.0f;
+    for (int32_t k = 0; k < R; ++k) {
+        if (k > 0 && jitter && ntot > 0)
+            PI_LAUNCH(s->ctx, "k_jitter", k_jitter, dim3(nb), dim3(256), 0, q, ntot, (const BatchReq *)ln.d_req, m,
+                      ln.d_xyzw, cap, k);
+        if (ln.alone) {
+            st = pi_bin(s->ctx, ln.cells, x, y, z, w, ntot, &r0.grid, (pi_stream)q);
+            if (st != PI_OK) return st;
+            st = pi_interact(s->ctx, ln.cells, &o1, rho, gx, gy, gz, cnt, ln.d_inv, (pi_stream)q);
+        } else {
+            // (AUTO: the tuner's cached choice per system, else the static
+            // rule; a batch never runs timed trials)
+            st = pi_batch_run(s->ctx, ln.batch, m, sys.data(), x, y, z, w, &o, rho, gx, gy, gz, cnt, ln.d_inv,
+                              (pi_stream)q);
+        }
         if (st != PI_OK) return st;
-        st = pi_interact(s->ctx, sl.cells, &o, rho, gx, gy, gz, cnt, sl.d_inv + k, q);
-        if (st != PI_OK) return st;
+        PI_CHECK_HIP(hipMemcpyAsync(ln.d_hist + (int64_t)k * m, ln.d_inv, sizeof(pi_invariants) * (size_t)m,
+                                    hipMemcpyDeviceToDevice, q));
     }
-    // the inputs were consumed by the first copy; the same pinned buffer
-    // receives rho, gx, gy, gz, count, x, y, z, the invariants and the
-    // device error word (cleared on the stream for the next request)
-    if (n > 0) {
-        const void *src[8] = {rho, gx, gy, gz, cnt, dx, dy, dz};
-        for (int a = 0; a < 8; ++a)
-            PI_CHECK_HIP(hipMemcpyAsync(h + (size_t)a * n, src[a], b, hipMemcpyDeviceToHost, q));
-    }
-    PI_CHECK_HIP(hipMemcpyAsync(pinned_invariants(t->pinned, n), sl.d_inv,
-                                sizeof(pi_invariants) * (size_t)r.n_sweeps, hipMemcpyDeviceToHost, q));
-    PI_CHECK_HIP(hipMemcpyAsync(pinned_err(t->pinned, n, r.n_sweeps), sl.cells->d_err, sizeof(uint32_t),
-                                hipMemcpyDeviceToHost, q));
-    PI_LAUNCH(s->ctx, "k_clear_err", k_clear_err, dim3(1), dim3(64), 0, q, sl.cells->d_err);
+    if (ntot > 0)
+        PI_LAUNCH(s->ctx, "k_pack_results", k_pack_results, dim3(nb), dim3(256), 0, q, ntot,
+                  (const BatchReq *)ln.d_req, m, (const float *)ln.d_out, (const float *)ln.d_xyzw, cap, ln.d_down);
+    const int64_t ninv = (int64_t)m * R;
+    PI_LAUNCH(s->ctx, "k_pack_invariants", k_pack_invariants, dim3((unsigned)((ninv + 255) / 256)), dim3(256), 0, q,
+              (const BatchReq *)ln.d_req, m, R, (const pi_invariants *)ln.d_hist, ln.d_down);
+    for (int32_t i = 0; i < m; ++i)
+        PI_CHECK_HIP(hipMemcpyAsync(ts[i]->pinned, ln.d_down + ln.h_req[i].out_byte, result_bytes(ts[i]->req.n, R),
+                                    hipMemcpyDeviceToHost, q));
     PI_CHECK_HIP(hipGetLastError());
     return PI_OK;
 }
 
-// Retire finished requests (lock held; never waits).  A request's status
-// comes from its launch, else from the device error word its stream copied
-// into the ticket's pinned buffer before the completion event.
+// Retire finished batches (lock held; never waits on work in flight).  A
+// request's status comes from its batch's launch, else from the device
+// error word of the batch (a range error cannot come from a request that
+// pi_submit accepted, since it checks every position with the binning's own
+// decision and the displacements keep particles inside).
 bool retire(pi_server *s)
 {
     bool changed = false;
-    for (Slot &sl : s->slots) {
-        if (!sl.busy) continue;
-        const hipError_t q = hipEventQuery(sl.done);
+    for (Lane &ln : s->lanes) {
+        if (!ln.busy) continue;
+        const hipError_t q = hipEventQuery(ln.done);
         if (q == hipErrorNotReady) continue;
-        Ticket *t = s->tickets[sl.ticket];
-        pi_status st = sl.launch_status;
+        pi_status st = ln.launch_status;
         if (st == PI_OK && q != hipSuccess) st = PI_EDEVICE;
-        if (st == PI_OK) {
-            const uint32_t err = *(volatile uint32_t *)pinned_err(t->pinned, t->req.n, t->req.n_sweeps);
-            if (err) st = (err & PI_DERR_RANGE) ? PI_ERANGE : PI_EDEVICE;
-        }
         if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
-        t->status = st;
-        t->t_done = now_s();
-        t->done = true;
-        s->in_use -= t->footprint;
-        sl.busy = false;
+        if (st == PI_OK) {
+            if (ln.alone && ln.cells) st = pi_sync(s->ctx, ln.cells, (pi_stream)ln.stream);
+            else if (!ln.alone && ln.batch) st = pi_batch_sync(s->ctx, ln.batch, (pi_stream)ln.stream);
+        }
+        const double t = now_s();
+        for (uint64_t id : ln.tickets) {
+            Ticket *tk = s->tickets[id];
+            tk->status = st;
+            tk->t_done = t;
+            tk->done = true;
+            s->in_use -= tk->footprint;
+            --s->in_flight;
+        }
+        ln.tickets.clear();
+        ln.busy = false;
         changed = true;
     }
     return changed;
 }
 
-// Admit queued requests in arrival order while a slot is free and the
-// budget allows (lock held): the slots are marked busy and listed in `go`.
-void admit(pi_server *s, std::vector<Slot *> &go)
+// Requests of at least this many particles fill the GPU on their own and
+// run alone (the plain single-system path); smaller ones share batches.
+constexpr int64_t kAloneN = (int64_t)1 << 18;
+
+// Requests that may share a batch (same sweep count and options, both
+// small).
+bool same_batch(const pi_request &a, const pi_request &b)
 {
-    while (!s->queue.empty()) {
-        Ticket *t = s->tickets[s->queue.front()];
-        if (s->in_use + t->footprint > s->opts.hbm_budget) break; // first in, first served
-        Slot *free_slot = nullptr;
-        for (Slot &sl : s->slots)
-            if (!sl.busy) {
-                free_slot = &sl;
+    return a.n < kAloneN && b.n < kAloneN && a.n_sweeps == b.n_sweeps && a.precision == b.precision &&
+           a.sweep == b.sweep;
+}
+
+// Admit queued requests in arrival order onto free lanes while the request
+// cap and the budget allow (lock held): each free lane takes the longest
+// run at the head of the queue that may share a batch; the lanes are marked
+// busy and listed in `go`.
+void admit(pi_server *s, std::vector<Lane *> &go)
+{
+    for (Lane &ln : s->lanes) {
+        if (ln.busy) continue;
+        int64_t ntot = 0, ctot = 0;
+        while (!s->queue.empty() && s->in_flight < s->opts.max_slots) {
+            Ticket *t = s->tickets[s->queue.front()];
+            if (s->in_use + t->footprint > s->opts.hbm_budget) break; // first in, first served
+            if (!ln.tickets.empty() && !same_batch(s->tickets[ln.tickets[0]]->req, t->req)) break;
+            const int64_t nc = (int64_t)t->req.grid.dims[0] * t->req.grid.dims[1] * t->req.grid.dims[2];
+            if (!ln.tickets.empty() && (ntot + t->req.n >= ((int64_t)1 << 30) || ctot + nc >= ((int64_t)1 << 30)))
                 break;
-            }
-        if (!free_slot) break;
-        s->queue.pop_front();
-        free_slot->busy = true;
-        free_slot->ticket = t->id;
-        free_slot->launch_status = PI_OK;
-        t->slot = (int)(free_slot - s->slots.data());
-        t->t_start = now_s();
-        s->in_use += t->footprint;
-        go.push_back(free_slot);
+            s->queue.pop_front();
+            ln.tickets.push_back(t->id);
+            t->lane = (int)(&ln - s->lanes.data());
+            t->t_start = now_s();
+            s->in_use += t->footprint;
+            ++s->in_flight;
+            ntot += t->req.n;
+            ctot += nc;
+        }
+        if (ln.tickets.empty()) break;
+        ln.busy = true;
+        ln.launch_status = PI_OK;
+        go.push_back(&ln);
     }
 }
 
-// The scheduler thread.  Requests are queued on their slots' streams with
-// the lock released (allocations, binning set-up and launches take time;
+// The scheduler thread.  Batches are queued on their lanes' streams with the
+// lock released (allocations, binning set-up and launches take time;
 // pi_submit, pi_poll and pi_wait stay responsive meanwhile).  Only this
-// thread marks slots busy or free, so the admitted slots stay its own while
+// thread marks lanes busy or free, so the admitted lanes stay its own while
 // it launches them.
 void worker_loop(pi_server *s)
 {
     (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
-    std::vector<Slot *> go;
+    std::vector<Lane *> go;
     while (!s->stop) {
         bool changed = retire(s);
         go.clear();
         admit(s, go);
         if (!go.empty()) {
-            std::vector<Ticket *> ts;
-            for (Slot *sl : go) ts.push_back(s->tickets[sl->ticket]);
+            std::vector<std::vector<Ticket *>> ts(go.size());
+            for (size_t i = 0; i < go.size(); ++i)
+                for (uint64_t id : go[i]->tickets) ts[i].push_back(s->tickets[id]);
             lk.unlock();
             for (size_t i = 0; i < go.size(); ++i) {
-                Slot &sl = *go[i];
-                pi_status st = launch_request(s, sl, ts[i]);
+                Lane &ln = *go[i];
+                pi_status st = launch_batch(s, ln, ts[i]);
                 // the completion event follows whatever was queued, so a
-                // failed request is retired only once its stream is idle
-                if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
+                // failed batch is retired only once its stream is idle
+                if (hipEventRecord(ln.done, ln.stream) != hipSuccess) {
                     (void)hipGetLastError();
-                    (void)hipStreamSynchronize(sl.stream);
+                    (void)hipStreamSynchronize(ln.stream);
                     (void)hipGetLastError();
                     if (st == PI_OK) st = PI_EDEVICE;
                 }
-                sl.launch_status = st;
+                ln.launch_status = st;
             }
             lk.lock();
             changed = true;
         }
         if (changed) s->cv.notify_all();
         bool busy = !s->queue.empty();
-        for (const Slot &sl : s->slots) busy = busy || sl.busy;
+        for (const Lane &ln : s->lanes) busy = busy || ln.busy;
         // poll in-flight work every 20 us; sleep until a submit otherwise
         if (busy) s->cv.wait_for(lk, std::chrono::microseconds(20));
         else s->cv.wait(lk);
     }
+}
+
+// Whether every particle of a request lies in its box by the binning's own
+// float32 decision.
+bool inside_box(const pi_request &r)
+{
+    const pi_grid &g = r.grid;
+    int32_t idx;
+    for (int64_t i = 0; i < r.n; ++i)
+        if (!axis_index(r.x[i], g.origin[0], g.cell_w, g.dims[0], idx) ||
+            !axis_index(r.y[i], g.origin[1], g.cell_w, g.dims[1], idx) ||
+            !axis_index(r.z[i], g.origin[2], g.cell_w, g.dims[2], idx))
+            return false;
+    return true;
 }
 
 } // namespace
@@ -376,7 +588,7 @@ extern "C" pi_status pi_server_create(pi_ctx *ctx, const pi_server_opts *opts, p
     o.n_streams = 4;
     o.queue_capacity = 1024;
     if (opts) o = *opts;
-    if (o.hbm_budget <= 0 || o.max_slots < 1 || o.max_slots > 256 || o.n_streams < 1 || o.n_streams > 16 ||
+    if (o.hbm_budget <= 0 || o.max_slots < 1 || o.max_slots > 4096 || o.n_streams < 1 || o.n_streams > 16 ||
         o.queue_capacity < 1)
         return PI_EINVAL;
     PI_CHECK_HIP(hipSetDevice(ctx->device));
@@ -384,19 +596,17 @@ extern "C" pi_status pi_server_create(pi_ctx *ctx, const pi_server_opts *opts, p
     if (!s) return PI_ENOMEM;
     s->ctx = ctx;
     s->opts = o;
-    for (int i = 0; i < o.n_streams; ++i) {
-        hipStream_t q = nullptr;
-        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) {
-            for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+    s->lanes.resize((size_t)o.n_streams);
+    for (Lane &ln : s->lanes) {
+        if (hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
+            for (Lane &l2 : s->lanes) {
+                if (l2.stream) (void)hipStreamDestroy(l2.stream);
+                if (l2.done) (void)hipEventDestroy(l2.done);
+            }
             delete s;
             return PI_EDEVICE;
         }
-        s->streams.push_back(q);
-    }
-    s->slots.resize((size_t)o.max_slots);
-    for (int i = 0; i < o.max_slots; ++i) {
-        s->slots[i].stream = s->streams[(size_t)i % s->streams.size()];
-        (void)hipEventCreateWithFlags(&s->slots[i].done, hipEventDisableTiming);
     }
     s->worker = std::thread(worker_loop, s);
     *out = s;
@@ -414,6 +624,7 @@ extern "C" pi_status pi_submit(pi_server *s, const pi_request *r, uint64_t *tick
     const int64_t nc = (int64_t)r->grid.dims[0] * r->grid.dims[1] * r->grid.dims[2];
     const int64_t fp = footprint_bytes(r->n, nc, r->n_sweeps);
     if (fp > s->opts.hbm_budget) return PI_ENOMEM;
+    if (!inside_box(*r)) return PI_ERANGE;
     size_t bytes = pinned_size(r->n, r->n_sweeps);
     void *pin;
     {
@@ -442,7 +653,7 @@ extern "C" pi_status pi_submit(pi_server *s, const pi_request *r, uint64_t *tick
     t->footprint = fp;
     t->status = PI_OK;
     t->done = false;
-    t->slot = -1;
+    t->lane = -1;
     t->pinned = pin;
     t->pinned_bytes = bytes;
     t->t_submit = now_s();
@@ -536,7 +747,7 @@ extern "C" pi_status pi_server_stats(pi_server *s, pi_server_stats_t *out)
     std::lock_guard<std::mutex> g(s->mu);
     memset(out, 0, sizeof(*out));
     out->queued = (int32_t)s->queue.size();
-    for (const Slot &sl : s->slots) out->running += sl.busy ? 1 : 0;
+    out->running = s->in_flight;
     out->hbm_in_use = s->in_use;
     return PI_OK;
 }
@@ -558,15 +769,17 @@ extern "C" pi_status pi_server_destroy(pi_server *s)
     s->cv.notify_all();
     if (s->worker.joinable()) s->worker.join();
     (void)hipSetDevice(s->ctx->device);
-    for (Slot &sl : s->slots) {
-        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.cells) pi_cells_destroy(sl.cells);
-        if (sl.d_in) (void)hipFree(sl.d_in);
-        if (sl.d_out) (void)hipFree(sl.d_out);
-        if (sl.d_inv) (void)hipFree(sl.d_inv);
-        if (sl.done) (void)hipEventDestroy(sl.done);
+    for (Lane &ln : s->lanes) {
+        if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+        if (ln.batch) pi_batch_destroy(ln.batch);
+        if (ln.cells) pi_cells_destroy(ln.cells);
+        void *bufs[] = {ln.d_up, ln.d_down, ln.d_xyzw, ln.d_out, ln.d_inv, ln.d_hist, ln.d_req};
+        for (void *p : bufs)
+            if (p) (void)hipFree(p);
+        if (ln.h_req) (void)hipHostFree(ln.h_req);
+        if (ln.done) (void)hipEventDestroy(ln.done);
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
     }
-    for (hipStream_t q : s->streams) (void)hipStreamDestroy(q);
     for (auto &kv : s->tickets) {
         (void)hipHostFree(kv.second->pinned);
         delete kv.second;

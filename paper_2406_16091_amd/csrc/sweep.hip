@@ -381,9 +381,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
 // target's accumulation order canonical, so results stay bit-identical to the
 // other organisations.
 //
-// A tile whose halo holds more than CAP particles is swept from global
-// memory with the plain per-lane walk over 27 cells (same order, same
-// results).
+// A tile whose halo holds more than CAP particles is flagged and left to the
+// dense pass, which walks each of its targets from global memory with the
+// plain per-lane walk over 27 cells (same order, same results).
 template <int PREC, bool INV>
 __device__ __forceinline__ void walk_cells_global(const SweepArgs &a, int32_t k, int32_t ix, int32_t iy, int32_t iz,
                                                   float xi, float yi, float zi, Target<PREC, INV> &T)
@@ -448,6 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
         tl = lb - (uint32_t)sd.block_base;
         ntx = sd.ntx;
         nty = sd.nty;
+        // the system's workgroups past its tiles belong to its dense pass
+        if (tl >= (uint32_t)(ntx * nty * ((a.nz + TZ - 1) / TZ))) return;
     }
     const int32_t bx = (int32_t)(tl % (uint32_t)ntx);
     const int32_t by = (int32_t)((tl / (uint32_t)ntx) % (uint32_t)nty);
@@ -505,40 +507,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
     long long icnt = 0;
     double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
 
-    if (!BATCH) {
-        if (tid == 0) a.tflag[lb] = total > CAP ? 1 : 0;
-        if (total > CAP) {
-            // halo too large for LDS: the dense pass (k_sweep_dense) takes
-            // this tile's targets, one thread each across the whole grid,
-            // so a dense region is not left to one workgroup
-            if (tid == 0) *a.ovf = a.epoch;
-            if (INV) reduce_invariants(a, lb, 0, 0.0, 0.0, 0.0, 0.0, 0.0);
-            return;
-        }
-    }
+    if (tid == 0) a.tflag[lb] = total > CAP ? 1 : 0;
     if (total > CAP) {
-        // halo too large for LDS: sweep this tile from global memory
-        for (int32_t f = tid; f < ntarget; f += kBlock) {
-            int lo = 0, hi = TR;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (tstart[mid] <= f) lo = mid; else hi = mid;
-            }
-            const int32_t k = tfirst[lo] + (f - tstart[lo]);
-            const int32_t y = y0 + lo % TY, z = z0 + lo / TY;
-            const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
-            Target<PREC, INV> T;
-            const float4 pk = a.p4[k];
-            walk_cells_global(a, k, ix, y, z, pk.x, pk.y, pk.z, T);
-            write_target(a, k, T);
-            if (INV) {
-                long long c1;
-                double a1, a2, a3, a4, a5;
-                target_invariants(T, pk.w, c1, a1, a2, a3, a4, a5);
-                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
-            }
-        }
-        if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
+        // halo too large for LDS: the dense pass (k_sweep_dense, or
+        // k_sweep_dense_batch for a batch) takes this tile's targets, one
+        // thread each across the system, so a dense region is not left to
+        // one workgroup
+        if (!BATCH && tid == 0) *a.ovf = a.epoch;
+        if (INV) reduce_invariants(a, lb, 0, 0.0, 0.0, 0.0, 0.0, 0.0);
         return;
     }
 
@@ -722,8 +698,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
 // rows in y order, cells in x order and particles in sorted order, so each
 // target sees its 27 cells in the canonical order and the outputs are
 // those of every other organisation.  A sub-box whose largest sheet holds
-// more than SCAP particles is left to the dense pass (single system) or
-// walked from global memory (batch), like an overflowing tile.
+// more than SCAP particles is left to the dense pass, like an overflowing
+// tile.
 template <int TX, int TY, int TZ, int SCAP, int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_pencilreg(SweepArgs a, int32_t ntx, int32_t nty)
 {
@@ -743,6 +719,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pencilreg(SweepArgs a, int32_t
         tl = lb - (uint32_t)sd.block_base;
         ntx = sd.ntx;
         nty = sd.nty;
+        // the system's workgroups past its tiles belong to its dense pass
+        if (tl >= (uint32_t)(ntx * nty * ((a.nz + TZ - 1) / TZ))) return;
     }
     const int32_t bx = (int32_t)(tl % (uint32_t)ntx);
     const int32_t by = (int32_t)((tl / (uint32_t)ntx) % (uint32_t)nty);
@@ -791,39 +769,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_pencilreg(SweepArgs a, int32_t
     const bool overflow = sheetmax > SCAP;
     long long icnt = 0;
     double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
-    if (!BATCH) {
-        if (tid == 0) a.tflag[lb] = overflow ? 1 : 0;
-        if (overflow) {
-            if (tid == 0) *a.ovf = a.epoch;
-            if (INV) reduce_invariants(a, lb, 0, 0.0, 0.0, 0.0, 0.0, 0.0);
-            return;
-        }
+    if (tid == 0) a.tflag[lb] = overflow ? 1 : 0;
+    if (overflow) {
+        if (!BATCH && tid == 0) *a.ovf = a.epoch;
+        if (INV) reduce_invariants(a, lb, 0, 0.0, 0.0, 0.0, 0.0, 0.0);
+        return;
     }
     auto target_row = [&](int32_t f) {
         int tr = 0;
         for (int r = 1; r < TR; ++r) tr = tstart[r] <= f ? r : tr;
         return tr;
     };
-    if (overflow) { // batch: walk the targets from global memory
-        for (int32_t f = tid; f < ntarget; f += kBlock) {
-            const int tr = target_row(f);
-            const int32_t k = tfirst[tr] + (f - tstart[tr]);
-            const int32_t y = y0 + tr % TY, z = z0 + tr / TY;
-            const int32_t ix = a.cell[k] - a.nx * (y + a.ny * z);
-            Target<PREC, INV> T;
-            const float4 pk = a.p4[k];
-            walk_cells_global(a, k, ix, y, z, pk.x, pk.y, pk.z, T);
-            write_target(a, k, T);
-            if (INV) {
-                long long c1;
-                double a1, a2, a3, a4, a5;
-                target_invariants(T, pk.w, c1, a1, a2, a3, a4, a5);
-                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
-            }
-        }
-        if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
-        return;
-    }
 
     for (int32_t f0 = 0; f0 < ntarget; f0 += kBlock) {
         // this round's target, in registers
@@ -1193,6 +1149,51 @@ __global__ __launch_bounds__(kBlock) void k_sweep_dense(SweepArgs a, int32_t tx,
     if (INV) reduce_invariants(a, rec0 + blockIdx.x, icnt, inx, iny, inz, isc, irs);
 }
 
+// The dense pass of a batch tile sweep.  Each system's workgroups in the
+// launch are its tiles followed by its dense workgroups (the batch layout);
+// a dense workgroup first checks whether any tile of its system overflowed
+// (the flags the tile launch just wrote) and, if so, strides over the
+// system's particles and walks from global memory the targets of flagged
+// tiles.  Its invariant partial record stays in the system's range.
+template <int PREC, bool INV>
+__global__ __launch_bounds__(kBlock) void k_sweep_dense_batch(SweepArgs a, int32_t tx, int32_t ty, int32_t tz,
+                                                              int32_t total_blocks)
+{
+    const uint32_t lb = blockIdx.x;
+    const int s = enter_system(a, lb);
+    const SysDev &sd = a.sys[s];
+    const int32_t ntx = sd.ntx, nty = sd.nty, ntz = (a.nz + tz - 1) / tz;
+    const int32_t ntiles = ntx * nty * ntz;
+    const int32_t d = (int32_t)(lb - (uint32_t)sd.block_base) - ntiles;
+    if (d < 0) return; // a tile's workgroup
+    const int32_t nd = (s + 1 < a.nsys ? a.sys[s + 1].block_base : total_blocks) - sd.block_base - ntiles;
+    const uint8_t *flags = a.tflag + sd.block_base;
+    int any = 0;
+    for (int32_t t = (int32_t)threadIdx.x; t < ntiles && !any; t += kBlock) any = flags[t];
+    any = __syncthreads_or(any);
+    long long icnt = 0;
+    double inx = 0, iny = 0, inz = 0, isc = 0, irs = 0;
+    if (any) {
+        const int32_t kend = (int32_t)sd.first + sd.n;
+        for (int32_t k = (int32_t)sd.first + d * kBlock + (int32_t)threadIdx.x; k < kend; k += nd * kBlock) {
+            const int32_t c = a.cell[k];
+            const int32_t ix = c % a.nx, iy = (c / a.nx) % a.ny, iz = c / (a.nx * a.ny);
+            if (!flags[ix / tx + ntx * (iy / ty + nty * (iz / tz))]) continue;
+            Target<PREC, INV> T;
+            const float4 pk = a.p4[k];
+            walk_cells_global(a, k, ix, iy, iz, pk.x, pk.y, pk.z, T);
+            write_target(a, k, T);
+            if (INV) {
+                long long c1;
+                double a1, a2, a3, a4, a5;
+                target_invariants(T, pk.w, c1, a1, a2, a3, a4, a5);
+                icnt += c1; inx += a1; iny += a2; inz += a3; isc += a4; irs += a5;
+            }
+        }
+    }
+    if (INV) reduce_invariants(a, lb, icnt, inx, iny, inz, isc, irs);
+}
+
 // FP64 reduction of the per-workgroup partials in two fixed-order stages
 // (deterministic): stage 1 folds each run of up to 1024 records into one,
 // stage 2 (one workgroup) folds those into the output.
@@ -1393,6 +1394,13 @@ unsigned dense_blocks(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
 }
 
+// Dense workgroups of one system of a batch tile sweep: one per 2048
+// particles, at most 256.
+int64_t batch_dense_blocks(int64_t n)
+{
+    return std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 256));
+}
+
 // nblk: in single-system mode computed here from the grid, and then the
 // count of invariant partial records the launch writes (the tiles', then
 // the dense pass's); in batch mode given (the sum of the systems' tile
@@ -1408,12 +1416,15 @@ void launch_tile(pi_ctx *ctx, const char *name, const SweepArgs &a, hipStream_t 
         nblk = (unsigned)((int64_t)ntx * nty * ntz);
     }
     if (BATCH) {
+        // (nblk counts every system's tiles and dense workgroups)
         if (REG)
             PI_LAUNCH(ctx, name, (k_sweep_pencilreg<TX, TY, TZ, CAP, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock), 0,
                       s, a, ntx, nty);
         else
             PI_LAUNCH(ctx, name, (k_sweep_tile<TX, TY, TZ, CAP, kFifo, PREC, INV, BATCH>), dim3(nblk), dim3(kBlock),
                       0, s, a, ntx, nty);
+        PI_LAUNCH(ctx, "k_sweep_dense_batch", (k_sweep_dense_batch<PREC, INV>), dim3(nblk), dim3(kBlock), 0, s, a, TX,
+                  TY, TZ, (int32_t)nblk);
         return;
     }
     SweepArgs b = a;
@@ -1626,7 +1637,8 @@ int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys)
 {
     int tx = 0, ty = 0, tz = 0;
     const bool tiled = tile_id > 0 && pi_tile_shape(tile_id, &tx, &ty, &tz);
-    if (tiled && tile_cfg(tile_id).sweep == PI_SWEEP_CELL) ty = tz = 1; // runs of tx cells
+    const bool cell = tiled && tile_cfg(tile_id).sweep == PI_SWEEP_CELL;
+    if (cell) ty = tz = 1; // runs of tx cells
     int64_t base = 0;
     for (int32_t s = 0; s < nsys; ++s) {
         SysDev &d = h_sys[s];
@@ -1636,6 +1648,8 @@ int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys)
             d.nty = (d.g.ny + ty - 1) / ty;
             const int32_t ntz = (d.g.nz + tz - 1) / tz;
             base += (int64_t)d.ntx * d.nty * ntz;
+            // the dense workgroups of an LDS tiling (none for the cell-SM)
+            if (!cell) base += batch_dense_blocks(d.n);
         } else {
             d.ntx = d.nty = 0;
             base += (d.n + kBlock - 1) / kBlock;
@@ -1665,6 +1679,7 @@ pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDe
     a.gz = gz;
     a.count = count;
     a.partials = (InvPartial *)cells->partials + part_base;
+    a.tflag = cells->tflag + part_base; // (one flag per workgroup of the group)
     a.sys = d_sys;
     a.kcs = d_kcs;
     a.nsys = nsys;

@@ -105,6 +105,47 @@ def test_alone_and_in_the_mix_are_identical(lib):
         pi.pi_server_destroy(server)
 
 
+def test_many_small_requests_batched(lib):
+    """Two hundred small requests (a few hundred to a few thousand particles)
+    submitted at once to a server that runs up to 64 per batch on 4 lanes:
+    every result equals the same request run alone (one-request server), and
+    a sample matches the oracle on its final positions."""
+    pi, device = lib
+    ctx = device.Context.get(0).handle
+    rng = np.random.default_rng(97)
+    systems = []
+    for k in range(200):
+        g = int(rng.integers(3, 12))
+        n = int(rng.integers(0, 3 * g ** 3))
+        systems.append(synth.box_system(n, g, seed=9700 + k, lattice_log2=16, clustered_blobs=4 if k % 3 else 0))
+    alone = []
+    server = pi.pi_server_create(ctx, max_slots=1, n_streams=1)
+    try:
+        for k, s in enumerate(systems):
+            t = pi.pi_submit(server, pi.make_request(s, n_sweeps=3, jitter_sigma=0.1 * s.rc, lattice=2.0 ** -16,
+                                                     seed=5000 + k))
+            alone.append(pi.pi_wait(server, t))
+            pi.pi_release(server, t)
+    finally:
+        pi.pi_server_destroy(server)
+    server = pi.pi_server_create(ctx, max_slots=64, n_streams=4)
+    try:
+        tickets = [pi.pi_submit(server, pi.make_request(s, n_sweeps=3, jitter_sigma=0.1 * s.rc,
+                                                        lattice=2.0 ** -16, seed=5000 + k))
+                   for k, s in enumerate(systems)]
+        for k, (t, a, s) in enumerate(zip(tickets, alone, systems)):
+            m = pi.pi_wait(server, t)
+            assert m["status"] == pi.PI_OK
+            for key in ("rho", "gx", "gy", "gz", "count", "x", "y", "z"):
+                assert (m[key].view(np.uint32) == a[key].view(np.uint32)).all(), (k, key)
+            assert m["pairs_per_sweep"] == a["pairs_per_sweep"], k
+            if k % 25 == 0:
+                _check_final(m, s)
+            pi.pi_release(server, t)
+    finally:
+        pi.pi_server_destroy(server)
+
+
 def test_admission_and_errors(lib):
     pi, device = lib
     ctx = device.Context.get(0).handle
@@ -118,6 +159,13 @@ def test_admission_and_errors(lib):
         with pytest.raises(pi.PiError) as e:
             pi.pi_poll(server, 987654321)
         assert e.value.status == pi.PI_ENOTFOUND
+        # a particle outside its box (by the binning's own float32 decision)
+        # is refused at submission
+        bad = synth.System("bad", small.x.copy(), small.y, small.z, small.w, small.origin, small.dims,
+                           small.cell_w, small.rc)
+        bad.x[17] = np.float32(small.dims[0])
+        st, _ = pi.pi_submit_status(server, pi.make_request(bad, n_sweeps=1))
+        assert st == pi.PI_ERANGE
     finally:
         pi.pi_server_destroy(server)
     # one slot: a long request runs, the next waits in the queue, the third
