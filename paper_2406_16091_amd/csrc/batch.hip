@@ -85,6 +85,11 @@ void pi_batch_set_direct(pi_batch *b, bool direct)
     b->direct = direct;
 }
 
+pi_cells *pi_batch_cells(pi_batch *b)
+{
+    return b->cells;
+}
+
 extern "C" pi_status pi_batch_destroy(pi_batch *b)
 {
     if (!b) return PI_EINVAL;

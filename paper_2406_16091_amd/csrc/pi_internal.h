@@ -277,6 +277,8 @@ int pi_batch_org(int tile_id);
 // of capturing it into a graph (for layouts used a few times only); the
 // tables are rebuilt only when the layout changes.
 void pi_batch_set_direct(pi_batch *batch, bool direct);
+// The cell object a batch bins its systems into (its device error word).
+pi_cells *pi_batch_cells(pi_batch *batch);
 pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
                          int64_t total_blocks, int64_t part_base, int tile_id, const pi_interact_opts &o, float *rho,
                          float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);

@@ -140,6 +140,13 @@ __global__ __launch_bounds__(256) void k_pack_results(int64_t ntot, const BatchR
     for (int a = 0; a < 3; ++a) dst[(5 + a) * nn + j] = xyzw[a * cap + i];
 }
 
+// The device error word of a binned system back to zero (a fill kernel, not
+// a memset, so that the sequence stays capturable).
+__global__ void k_clear_err(uint32_t *err)
+{
+    if (threadIdx.x == 0) err[0] = 0u;
+}
+
 // hist[k * m + q] (sweep k of request q) to request q's download block.
 __global__ __launch_bounds__(256) void k_pack_invariants(const BatchReq *__restrict__ t, int32_t m, int32_t sweeps,
                                                          const pi_invariants *__restrict__ hist,
@@ -190,6 +197,7 @@ struct Lane {
     pi_invariants *d_hist = nullptr; // every sweep's [cap_hist]
     BatchReq *d_req = nullptr;
     BatchReq *h_req = nullptr;       // pinned staging of the request table
+    uint32_t *h_err = nullptr;       // pinned copy of the batch's device error word
     int64_t cap = 0, cap_up = 0, cap_down = 0, cap_req = 0, cap_hist = 0;
     pi_status launch_status = PI_OK; // error queuing the batch (retired with it)
 };
@@ -298,6 +306,10 @@ pi_status lane_reserve(Lane &ln, int64_t n, int64_t down, int32_t m, int64_t his
             return PI_ENOMEM;
         }
         ln.cap_down = cap;
+    }
+    if (!ln.h_err) {
+        if (hipHostMalloc((void **)&ln.h_err, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) return PI_ENOMEM;
+        *ln.h_err = 0;
     }
     if (m > ln.cap_req || !ln.d_req) {
         const int64_t cap = grow_pow2(m, 64);
@@ -434,15 +446,21 @@ pi_status launch_batch(pi_server *s, Lane &ln, const std::vector<Ticket *> &ts)
     for (int32_t i = 0; i < m; ++i)
         PI_CHECK_HIP(hipMemcpyAsync(ts[i]->pinned, ln.d_down + ln.h_req[i].out_byte, result_bytes(ts[i]->req.n, R),
                                     hipMemcpyDeviceToHost, q));
+    // the device error word, copied before the completion event and cleared
+    // on the stream, so that retiring the batch never waits on the device
+    uint32_t *d_err = (ln.alone ? ln.cells : pi_batch_cells(ln.batch))->d_err;
+    PI_CHECK_HIP(hipMemcpyAsync(ln.h_err, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, q));
+    PI_LAUNCH(s->ctx, "k_clear_err", k_clear_err, dim3(1), dim3(64), 0, q, d_err);
     PI_CHECK_HIP(hipGetLastError());
     return PI_OK;
 }
 
-// Retire finished batches (lock held; never waits on work in flight).  A
-// request's status comes from its batch's launch, else from the device
-// error word of the batch (a range error cannot come from a request that
-// pi_submit accepted, since it checks every position with the binning's own
-// decision and the displacements keep particles inside).
+// Retire finished batches (lock held; never waits on the device).  A
+// request's status comes from its batch's launch, else from the copy of the
+// batch's device error word that its stream made before the completion
+// event (a range error cannot come from a request that pi_submit accepted,
+// since it checks every position with the binning's own decision and the
+// displacements keep particles inside).
 bool retire(pi_server *s)
 {
     bool changed = false;
@@ -454,8 +472,8 @@ bool retire(pi_server *s)
         if (st == PI_OK && q != hipSuccess) st = PI_EDEVICE;
         if (q != hipSuccess && q != hipErrorNotReady) (void)hipGetLastError();
         if (st == PI_OK) {
-            if (ln.alone && ln.cells) st = pi_sync(s->ctx, ln.cells, (pi_stream)ln.stream);
-            else if (!ln.alone && ln.batch) st = pi_batch_sync(s->ctx, ln.batch, (pi_stream)ln.stream);
+            const uint32_t err = *(volatile uint32_t *)ln.h_err;
+            if (err) st = (err & PI_DERR_RANGE) ? PI_ERANGE : PI_EDEVICE;
         }
         const double t = now_s();
         for (uint64_t id : ln.tickets) {
@@ -777,6 +795,7 @@ extern "C" pi_status pi_server_destroy(pi_server *s)
         for (void *p : bufs)
             if (p) (void)hipFree(p);
         if (ln.h_req) (void)hipHostFree(ln.h_req);
+        if (ln.h_err) (void)hipHostFree(ln.h_err);
         if (ln.done) (void)hipEventDestroy(ln.done);
         if (ln.stream) (void)hipStreamDestroy(ln.stream);
     }
