@@ -230,16 +230,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_nolds(SweepArgs a)
 // evaluation by a per-lane LDS FIFO as in the tiles: the test of one
 // candidate is a few instructions, the evaluation of an accepted pair about a
 // hundred, and at several particles per cell some lane of a wavefront
-// accepts on nearly every step.  A queue entry is the source's sorted index
-// and a byte code of its cell shift (dx, dy, dz), from which the pop rebuilds
-// the same differences the test used.  Nothing is staged, so the
+// accepts on nearly every step.  A queue entry holds the differences the
+// test computed and the source's weight, so a pop reads nothing from global
+// memory and evaluates the same values.  Nothing is staged, so the
 // organisation works at any occupancy.
 template <int Q, int PREC, bool INV, bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
 {
     static_assert((Q & (Q - 1)) == 0, "FIFO depth must be a power of two");
-    __shared__ int32_t fifo[kBlock / 64][Q][64];   // accepted source: sorted index
-    __shared__ uint8_t fcode[kBlock / 64][Q][64];  // its shift: (dx+1) | (dy+1) << 2 | (dz+1) << 4
+    __shared__ float4 fifo[kBlock / 64][Q][64];   // accepted pair: (dx, dy, dz, w_j)
 
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     int32_t k, kend;
@@ -280,19 +279,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
     const float tr = ix + 1 < a.nx ? reach2 - (W - xi) * (W - xi) : -1.0f;
 
     Target<PREC, INV> T;
-    int32_t *myq = &fifo[wid][0][lane];
-    uint8_t *myc = &fcode[wid][0][lane];
+    float4 *myq = &fifo[wid][0][lane];
     int qh = 0, qc = 0;
     auto pop = [&]() {
-        const int32_t jj = myq[qh * 64];
-        const int cd = myc[qh * 64];
+        const float4 e = myq[qh * 64];
         qh = (qh + 1) & (Q - 1);
         --qc;
-        const float4 s = a.p4[jj];
-        const float ddx = sel(cd & 3, xm, xi, xp) - s.x;
-        const float ddy = sel((cd >> 2) & 3, ym, yi, yp) - s.y;
-        const float ddz = sel((cd >> 4) & 3, zm, zi, zp) - s.z;
-        T.accept(ddx, ddy, ddz, sq_dist(ddx, ddy, ddz), s.w, a.k);
+        T.template accept<true>(e.x, e.y, e.z, sq_dist(e.x, e.y, e.z), e.w, a.k);
     };
     for (int dz = -1; dz <= 1; ++dz) {
         const float tz = dz < 0 ? zm : (dz > 0 ? zp : zi);
@@ -311,7 +304,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
                 j = gyz < tl ? a.off[rb - 1] : b1;
                 j3 = gyz < tr ? a.off[rb + 2] : b2;
             }
-            const int rowcode = ((dy + 1) << 2) | ((dz + 1) << 4);
             while (__any(j < j3)) {
                 if (j < j3) {
                     const int dxc = j < b1 ? 0 : (j < b2 ? 1 : 2);
@@ -320,12 +312,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
                     const float t = sq_dist(ddx, ddy, ddz);
                     bool acc = t < a.k.lo;
                     if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
-                    // written always (the slot after the tail is free), kept
-                    // if accepted
-                    const int slot = ((qh + qc) & (Q - 1)) * 64;
-                    myq[slot] = j;
-                    myc[slot] = (uint8_t)(dxc | rowcode);
-                    qc += (acc && j != k) ? 1 : 0;
+                    if (acc && j != k) {
+                        myq[((qh + qc) & (Q - 1)) * 64] = make_float4(ddx, ddy, ddz, s.w);
+                        ++qc;
+                    }
                     ++j;
                 }
                 if (__any(qc == Q)) {
