@@ -118,7 +118,10 @@ def measured_traffic(kernel: str, inv: bool = True):
                 if line.startswith("TRAFFIC "):
                     parts = line.split()
                     name, val, h = " ".join(parts[1:-2]), parts[-2], parts[-1]
-                    if kernel_key(name) == want and h == cur:
+                    key = kernel_key(name)
+                    # (a timing name without template arguments matches
+                    # every instance of its kernel)
+                    if (key == want or ("<" not in want and key.split("<")[0] == want)) and h == cur:
                         found.append((name, float(val)))
     if not found:
         return None
