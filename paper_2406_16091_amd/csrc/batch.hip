@@ -176,6 +176,14 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
                                   float *rho, float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv,
                                   pi_stream stream_)
 {
+    return pi_batch_run_orgs(ctx, b, nsys, sys, nullptr, x, y, z, w, opts, rho, gx, gy, gz, count, inv, stream_);
+}
+
+pi_status pi_batch_run_orgs(pi_ctx *ctx, pi_batch *b, int32_t nsys, const pi_system_desc *sys, const int32_t *org,
+                            const float *x, const float *y, const float *z, const float *w,
+                            const pi_interact_opts *opts, float *rho, float *gx, float *gy, float *gz,
+                            int32_t *count, pi_invariants *inv, pi_stream stream_)
+{
     if (!ctx || !b || b->ctx != ctx || nsys < 1 || !sys) return PI_EINVAL;
     pi_interact_opts o;
     memset(&o, 0, sizeof(o));
@@ -205,6 +213,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
     const void *ptrs[] = {x, y, z, w, rho, gx, gy, gz, count, inv, stream};
     append(sig, ptrs, sizeof(ptrs));
     append(sig, &o, sizeof(o));
+    if (org) append(sig, org, sizeof(int32_t) * (size_t)nsys);
     if (b->exec && sig == b->sig) {
         PI_CHECK_HIP(hipGraphLaunch(b->exec, stream));
         return PI_OK;
@@ -245,6 +254,7 @@ extern "C" pi_status pi_batch_run(pi_ctx *ctx, pi_batch *b, int32_t nsys, const 
         int t = pi_pick_tile(o, ppc);
         if (t < 0) return PI_EINVAL;
         if (o.sweep == PI_SWEEP_AUTO) t = pi_auto_tile(ctx, o.precision, sys[s].n, ppc);
+        if (org && org[s] >= 0) t = org[s];
         b->tile_of[s] = pi_batch_org(t);
     }
     // sweep table: systems grouped by organisation (caller's order within a

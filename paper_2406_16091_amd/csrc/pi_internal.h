@@ -279,6 +279,13 @@ int pi_batch_org(int tile_id);
 void pi_batch_set_direct(pi_batch *batch, bool direct);
 // The cell object a batch bins its systems into (its device error word).
 pi_cells *pi_batch_cells(pi_batch *batch);
+// pi_batch_run with per-system organisations: org[s] >= 0 (an organisation
+// id, 0 = no LDS) replaces system s's AUTO or explicit choice; org may be
+// null.
+pi_status pi_batch_run_orgs(pi_ctx *ctx, pi_batch *b, int32_t nsys, const pi_system_desc *sys, const int32_t *org,
+                            const float *x, const float *y, const float *z, const float *w,
+                            const pi_interact_opts *opts, float *rho, float *gx, float *gy, float *gz,
+                            int32_t *count, pi_invariants *inv, pi_stream stream);
 pi_status pi_sweep_batch(pi_ctx *ctx, pi_cells *cells, int32_t nsys, const SysDev *d_sys, const KernelConst *d_kcs,
                          int64_t total_blocks, int64_t part_base, int tile_id, const pi_interact_opts &o, float *rho,
                          float *gx, float *gy, float *gz, int32_t *count, pi_invariants *inv, hipStream_t stream);

@@ -172,6 +172,7 @@ struct Ticket {
     int32_t status;
     bool done;
     int lane;
+    int32_t max_ppc; // the most particles in one cell (-1: not counted)
     double t_submit, t_start, t_done;
     // pinned host buffer: the inputs (x, y, z, w) on the way in; then the
     // outputs rho, gx, gy, gz, count, x, y, z (max(n, 1) entries each) and
@@ -337,6 +338,8 @@ pi_status lane_reserve(Lane &ln, int64_t n, int64_t down, int32_t m, int64_t his
     return PI_OK;
 }
 
+bool clustered(const Ticket *t);
+
 // Queue a batch of requests (same sweep count and options) on an idle lane;
 // the caller records the lane's completion event after it.
 pi_status launch_batch(pi_server *s, Lane &ln, const std::vector<Ticket *> &ts)
@@ -409,14 +412,18 @@ pi_status launch_batch(pi_server *s, Lane &ln, const std::vector<Ticket *> &ts)
     o.precision = r0.precision;
     o.sweep = r0.sweep;
     o.order = PI_ORDER_ORIGINAL;
+    // AUTO never runs timed trials on a request's path: the tuner's cached
+    // choice for the request's class if there is one, else the static rule;
+    // a request whose densest cell would overflow the LDS tilings takes the
+    // no-LDS walk (the same choice alone and in a batch)
     pi_interact_opts o1 = o;
     if (ln.alone && o1.sweep == PI_SWEEP_AUTO) {
-        // no timed trials on a request's path: the tuner's cached choice for
-        // the request's class if there is one, else the static rule (what a
-        // batch takes for the same system)
         const double nc = (double)r0.grid.dims[0] * r0.grid.dims[1] * r0.grid.dims[2];
-        pi_tile_opts(pi_auto_tile(s->ctx, r0.precision, r0.n, (double)r0.n / nc), &o1);
+        pi_tile_opts(clustered(ts[0]) ? 0 : pi_auto_tile(s->ctx, r0.precision, r0.n, (double)r0.n / nc), &o1);
     }
+    std::vector<int32_t> org((size_t)m, -1);
+    if (o.sweep == PI_SWEEP_AUTO)
+        for (int32_t i = 0; i < m; ++i) org[i] = clustered(ts[i]) ? 0 : -1;
     bool jitter = false;
     for (const Ticket *t : ts) jitter = jitter || t->req.jitter_sigma > 0.0f;
     for (int32_t k = 0; k < R; ++k) {
@@ -430,8 +437,8 @@ pi_status launch_batch(pi_server *s, Lane &ln, const std::vector<Ticket *> &ts)
         } else {
             // (AUTO: the tuner's cached choice per system, else the static
             // rule; a batch never runs timed trials)
-            st = pi_batch_run(s->ctx, ln.batch, m, sys.data(), x, y, z, w, &o, rho, gx, gy, gz, cnt, ln.d_inv,
-                              (pi_stream)q);
+            st = pi_batch_run_orgs(s->ctx, ln.batch, m, sys.data(), org.data(), x, y, z, w, &o, rho, gx, gy, gz,
+                                   cnt, ln.d_inv, (pi_stream)q);
         }
         if (st != PI_OK) return st;
         PI_CHECK_HIP(hipMemcpyAsync(ln.d_hist + (int64_t)k * m, ln.d_inv, sizeof(pi_invariants) * (size_t)m,
@@ -580,17 +587,36 @@ void worker_loop(pi_server *s)
 }
 
 // Whether every particle of a request lies in its box by the binning's own
-// float32 decision.
-bool inside_box(const pi_request &r)
+// float32 decision; with `occupancy`, also the most particles in one cell
+// (counted when the grid has at most 8n + 4096 cells, else -1).
+bool inside_box(const pi_request &r, bool occupancy, int32_t *max_ppc)
 {
     const pi_grid &g = r.grid;
-    int32_t idx;
-    for (int64_t i = 0; i < r.n; ++i)
-        if (!axis_index(r.x[i], g.origin[0], g.cell_w, g.dims[0], idx) ||
-            !axis_index(r.y[i], g.origin[1], g.cell_w, g.dims[1], idx) ||
-            !axis_index(r.z[i], g.origin[2], g.cell_w, g.dims[2], idx))
+    const int64_t nc = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
+    std::vector<int32_t> cnt;
+    if (occupancy && nc <= 8 * r.n + 4096) cnt.assign((size_t)nc, 0);
+    int32_t most = 0;
+    for (int64_t i = 0; i < r.n; ++i) {
+        int32_t ix, iy, iz;
+        if (!axis_index(r.x[i], g.origin[0], g.cell_w, g.dims[0], ix) ||
+            !axis_index(r.y[i], g.origin[1], g.cell_w, g.dims[1], iy) ||
+            !axis_index(r.z[i], g.origin[2], g.cell_w, g.dims[2], iz))
             return false;
+        if (!cnt.empty()) most = std::max(most, ++cnt[(size_t)(ix + (int64_t)g.dims[0] * (iy + (int64_t)g.dims[1] * iz))]);
+    }
+    *max_ppc = cnt.empty() ? -1 : most;
     return true;
+}
+
+// Whether a request's densest cell makes the LDS tilings overflow there, so
+// that AUTO should take the no-LDS walk: its most-occupied cell holds more
+// than four times the mean plus eight (the clustered inputs; the static rule
+// reads only the mean).
+bool clustered(const Ticket *t)
+{
+    const pi_grid &g = t->req.grid;
+    const double nc = (double)g.dims[0] * g.dims[1] * g.dims[2];
+    return t->max_ppc >= 0 && (double)t->max_ppc > 4.0 * (double)t->req.n / nc + 8.0;
 }
 
 } // namespace
@@ -642,7 +668,8 @@ extern "C" pi_status pi_submit(pi_server *s, const pi_request *r, uint64_t *tick
     const int64_t nc = (int64_t)r->grid.dims[0] * r->grid.dims[1] * r->grid.dims[2];
     const int64_t fp = footprint_bytes(r->n, nc, r->n_sweeps);
     if (fp > s->opts.hbm_budget) return PI_ENOMEM;
-    if (!inside_box(*r)) return PI_ERANGE;
+    int32_t max_ppc = -1;
+    if (!inside_box(*r, r->n < kAloneN, &max_ppc)) return PI_ERANGE;
     size_t bytes = pinned_size(r->n, r->n_sweeps);
     void *pin;
     {
@@ -672,6 +699,7 @@ extern "C" pi_status pi_submit(pi_server *s, const pi_request *r, uint64_t *tick
     t->status = PI_OK;
     t->done = false;
     t->lane = -1;
+    t->max_ppc = max_ppc;
     t->pinned = pin;
     t->pinned_bytes = bytes;
     t->t_submit = now_s();

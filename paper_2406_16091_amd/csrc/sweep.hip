@@ -383,33 +383,42 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
 //
 // A tile whose halo holds more than CAP particles is flagged and left to the
 // dense pass, which walks each of its targets from global memory with the
-// plain per-lane walk over 27 cells (same order, same results).
+// row walk of the no-LDS sweep (each neighbour X-row's up to three cells as
+// one range, cells surely beyond the cutoff trimmed; same sources, same
+// order, same roundings, so the same results).
 template <int PREC, bool INV>
-__device__ __forceinline__ void walk_cells_global(const SweepArgs &a, int32_t k, int32_t ix, int32_t iy, int32_t iz,
-                                                  float xi, float yi, float zi, Target<PREC, INV> &T)
+__device__ __forceinline__ void walk_rows_global(const SweepArgs &a, int32_t k, int32_t ix, int32_t iy, int32_t iz,
+                                                 float xi, float yi, float zi, Target<PREC, INV> &T)
 {
     const float W = a.k.w;
+    const float reach2 = a.k.reach2;
+    const float xm = xi - (float)(-1) * W, xp = xi - (float)(1) * W;
+    const float gyl = yi * yi, gyr = (W - yi) * (W - yi);
+    const float gzl = zi * zi, gzr = (W - zi) * (W - zi);
+    const float tl = ix > 0 ? reach2 - xi * xi : -1.0f;
+    const float tr = ix + 1 < a.nx ? reach2 - (W - xi) * (W - xi) : -1.0f;
     for (int dz = -1; dz <= 1; ++dz) {
         const int32_t cz = iz + dz;
         if (cz < 0 || cz >= a.nz) continue;
         const float tz = zi - (float)dz * W;
+        const float gz = dz < 0 ? gzl : (dz > 0 ? gzr : 0.f);
         for (int dy = -1; dy <= 1; ++dy) {
             const int32_t cy = iy + dy;
             if (cy < 0 || cy >= a.ny) continue;
+            const float gyz = (dy < 0 ? gyl : (dy > 0 ? gyr : 0.f)) + gz;
+            if (gyz >= reach2) continue;
             const float ty = yi - (float)dy * W;
-            const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz);
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int32_t cx = ix + dx;
-                if (cx < 0 || cx >= a.nx) continue;
-                const float tx = xi - (float)dx * W;
-                const int32_t j0 = a.off[rb + cx], j1 = a.off[rb + cx + 1];
-                for (int32_t j = j0; j < j1; ++j) {
-                    const float4 s = a.p4[j];
-                    const float ddx = tx - s.x, ddy = ty - s.y, ddz = tz - s.z;
-                    const float t = sq_dist(ddx, ddy, ddz);
-                    if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k))
-                        T.accept(ddx, ddy, ddz, t, s.w, a.k);
-                }
+            const int64_t rb = (int64_t)a.nx * (cy + (int64_t)a.ny * cz) + ix;
+            const int32_t b1 = a.off[rb], b2 = a.off[rb + 1];
+            const int32_t j0 = gyz < tl ? a.off[rb - 1] : b1;
+            const int32_t j3 = gyz < tr ? a.off[rb + 2] : b2;
+            for (int32_t j = j0; j < j3; ++j) {
+                const float tx = j < b1 ? xm : (j < b2 ? xi : xp);
+                const float4 s = a.p4[j];
+                const float ddx = tx - s.x, ddy = ty - s.y, ddz = tz - s.z;
+                const float t = sq_dist(ddx, ddy, ddz);
+                if (t < a.k.hi && j != k && inside_cutoff(ddx, ddy, ddz, t, a.k))
+                    T.accept(ddx, ddy, ddz, t, s.w, a.k);
             }
         }
     }
@@ -1136,7 +1145,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_dense(SweepArgs a, int32_t tx,
             if (!a.tflag[tile]) continue;
             Target<PREC, INV> T;
             const float4 pk = a.p4[k];
-            walk_cells_global(a, k, ix, iy, iz, pk.x, pk.y, pk.z, T);
+            walk_rows_global(a, k, ix, iy, iz, pk.x, pk.y, pk.z, T);
             write_target(a, k, T);
             if (INV) {
                 long long c1;
@@ -1181,7 +1190,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_dense_batch(SweepArgs a, int32
             if (!flags[ix / tx + ntx * (iy / ty + nty * (iz / tz))]) continue;
             Target<PREC, INV> T;
             const float4 pk = a.p4[k];
-            walk_cells_global(a, k, ix, iy, iz, pk.x, pk.y, pk.z, T);
+            walk_rows_global(a, k, ix, iy, iz, pk.x, pk.y, pk.z, T);
             write_target(a, k, T);
             if (INV) {
                 long long c1;
@@ -1394,11 +1403,12 @@ unsigned dense_blocks(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 1024));
 }
 
-// Dense workgroups of one system of a batch tile sweep: one per 2048
-// particles, at most 256.
+// Dense workgroups of one system of a batch tile sweep: one per 512
+// particles, at most 1024 (a workgroup of a system without an overflowing
+// tile only reads the system's tile flags).
 int64_t batch_dense_blocks(int64_t n)
 {
-    return std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 256));
+    return std::max<int64_t>(1, std::min<int64_t>((n + 511) / 512, 1024));
 }
 
 // nblk: in single-system mode computed here from the grid, and then the
