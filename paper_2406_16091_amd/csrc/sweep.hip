@@ -1711,7 +1711,8 @@ uint64_t tune_key(int prec, int64_t n, double ppc, bool batch)
     return (uint64_t)prec + 4ull * (uint64_t)kn + 256ull * (uint64_t)kp + (batch ? (1ull << 30) : 0ull);
 }
 
-// Time every compiled organisation on this system (second of two runs, with
+// Time every compiled organisation on this system (the fastest of up to
+// three runs after a first one, with
 // the invariant partials when the call computes them, since they change the
 // ranking: at 1 per cell the 7x7x5 tile is 5% faster than 6x6x6 without
 // them and 5% slower with them) and return the fastest; the outputs and
@@ -1744,14 +1745,20 @@ int time_candidates(pi_ctx *ctx, const SweepArgs &a0, int prec, int first, bool 
     for (int i = -1; i <= kMaxOrgId; ++i) {
         const int cand = i < 0 ? first : i;
         if (i >= 0 && (cand == first || !worth_timing(cand, ppc))) continue;
+        // one untimed run, then the fastest of up to three timed ones (one
+        // if that is already 1.5x the best: single runs vary by a few
+        // percent, which near-ties between tilings would otherwise follow)
         unsigned nblk = 0;
         float ms = 0.f;
         bool ok = true;
-        for (int rep = 0; rep < 2 && ok; ++rep) {
+        for (int rep = 0; rep < 4 && ok; ++rep) {
+            float t = 0.f;
             ok = hipEventRecord(e0, s) == hipSuccess;
             launch_sweep_prec<false>(ctx, prec, inv, cand, a, s, nblk);
             ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
-                 hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                 hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+            if (rep == 1 || (rep > 1 && t < ms)) ms = t;
+            if (rep == 1 && best >= 0 && ms > 1.5f * best_ms) break;
         }
         if (ok && (best < 0 || ms < 0.95f * best_ms)) {
             best = cand;
