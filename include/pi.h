@@ -135,7 +135,7 @@ typedef struct pi_cells_view {
 pi_status pi_cells_get_view(pi_cells *cells, pi_cells_view *out);
 
 /* Accumulation precision of the sweep. */
-#define PI_PREC_COMPENSATED 0 /* FP32 terms with h^2 - r^2 formed in FP64 for
+#define PI_PREC_COMPENSATED 0 /* FP32 terms with an error-free h^2 - r^2 for
                                  q > 1/2, FP32 Kahan-compensated sums */
 #define PI_PREC_PLAIN       1 /* FP32 terms (1 - q from q), plain FP32 sums */
 #define PI_PREC_FP64ACC     2 /* compensated FP32 terms, FP64 sums */

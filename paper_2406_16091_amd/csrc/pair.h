@@ -9,7 +9,7 @@ struct KernelConst {
     float lo, hi;       // filter on fl(r^2): < lo surely inside, >= hi surely outside
     float reach2;       // rc^2 (1 + 16 u) rounded up: a cell whose nearest face is at
                         // fl(distance^2) >= reach2 surely holds no pair inside the cutoff
-    float hh;           // h*h rounded to float
+    float hh, eh;       // h*h rounded to float, and its residual: h^2 = hh + eh exactly
     float hh_quarter;   // hh / 4 (exact): r^2 <= hh/4  <=>  q <= 1/2
     float h, inv_h;
     float sigma;        // 8 / (pi h^3)
@@ -19,19 +19,31 @@ struct KernelConst {
     float w;            // cell width
 };
 
-// h^2 - (dx^2 + dy^2 + dz^2) in FP64 (full rate on the vector units, as
-// FP32): the square of a float is exact in double (48 significant bits), and
-// so is h^2, so the only roundings are the two of the FMA chain that sums
-// the squares (relative error of r^2 below 2^-52) and the last one.  The
-// sign is exact whenever |h^2 - r^2| exceeds 2^-51 h^2, which holds for every
-// pair of points on a power-of-two lattice of spacing >= 2^-25 h (h on the
-// lattice); the value is h^2 - r^2 to within about 2^-52 h^2 (its sign is
-// tested in double, so a tiny difference cannot underflow to zero).
-__device__ __forceinline__ double h2_minus_d2(float dx, float dy, float dz, const KernelConst &k)
+// Error of a + b = s (Knuth's TwoSum, branch-free): a + b == s + err exactly.
+__device__ __forceinline__ float two_sum_err(float a, float b, float s)
 {
-    const double x = (double)dx, y = (double)dy, z = (double)dz, h = (double)k.h;
-    const double d = __builtin_fma(z, z, __builtin_fma(y, y, x * x));
-    return __builtin_fma(h, h, -d);
+    const float bb = s - a;
+    return (a - (s - bb)) + (b - bb);
+}
+
+// h^2 - (dx^2 + dy^2 + dz^2) with error-free transforms: the squares are
+// split into float + exact FMA residual, their sum into float + TwoSum
+// errors, and the large part is subtracted from hh exactly (Sterbenz, since
+// the sum is within a factor of two of hh wherever this matters).  The sign
+// is exact whenever |h^2 - r^2| exceeds about 6 * 2^-48 h^2, which holds for
+// every pair of points on a power-of-two lattice of spacing >= 2^-22 h.
+__device__ __forceinline__ float h2_minus_d2(float dx, float dy, float dz, const KernelConst &k)
+{
+    const float p1 = dx * dx, e1 = __builtin_fmaf(dx, dx, -p1);
+    const float p2 = dy * dy, e2 = __builtin_fmaf(dy, dy, -p2);
+    const float p3 = dz * dz, e3 = __builtin_fmaf(dz, dz, -p3);
+    const float a = p1 + p2;
+    const float t1 = two_sum_err(p1, p2, a);
+    const float s = a + p3;
+    const float t2 = two_sum_err(a, p3, s);
+    const float tail = ((t1 + t2) + (e1 + e2)) + e3; // r^2 = s + tail
+    const float head = k.hh - s;
+    return head + (k.eh - tail);
 }
 
 // Filtered exact predicate r < rc from the FP32 value t = fl(r^2) computed as
@@ -40,7 +52,7 @@ __device__ __forceinline__ bool inside_cutoff(float dx, float dy, float dz, floa
 {
     if (t < k.lo) return true;
     if (t >= k.hi) return false;
-    return h2_minus_d2(dx, dy, dz, k) > 0.0;
+    return h2_minus_d2(dx, dy, dz, k) > 0.0f;
 }
 
 __device__ __forceinline__ float sq_dist(float dx, float dy, float dz)
@@ -67,7 +79,7 @@ __device__ __forceinline__ void bspline_terms(float dx, float dy, float dz, floa
         if (PREC == PI_PREC_PLAIN) {
             omq = fmaxf(1.0f - r * k.inv_h, 0.0f);
         } else {
-            const float D = (float)h2_minus_d2(dx, dy, dz, k);
+            const float D = h2_minus_d2(dx, dy, dz, k);
             omq = D * __builtin_amdgcn_rcpf(k.h * (k.h + r));
         }
         const float omq2 = omq * omq;
@@ -88,7 +100,7 @@ __device__ __forceinline__ void bspline_terms(float dx, float dy, float dz, floa
             omq = fmaxf(1.0f - r * k.inv_h, 0.0f);
         } else {
             // 1 - q = (h^2 - r^2) / (h (h + r)), with h^2 - r^2 free of cancellation
-            const float D = (float)h2_minus_d2(dx, dy, dz, k);
+            const float D = h2_minus_d2(dx, dy, dz, k);
             omq = D * __builtin_amdgcn_rcpf(k.h * (k.h + r));
         }
         const float omq2 = omq * omq;

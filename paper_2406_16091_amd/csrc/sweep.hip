@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_stream(SweepArgs a)
                         const float ddx = sel(dxc, xm, xi, xp) - s.x, ddy = ty - s.y, ddz = tz - s.z;
                         const float t = sq_dist(ddx, ddy, ddz);
                         bool acc = t < a.k.lo;
-                        if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0;
+                        if (t >= a.k.lo && t < a.k.hi) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
                         if (acc && j != k) {
                             myq[((qh + qc) & (Q - 1)) * 64] = make_float4(ddx, ddy, ddz, s.w);
                             ++qc;
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tile(SweepArgs a, int32_t ntx,
                 // exact test (inside_cutoff, unrolled to keep the step short)
                 bool acc = t < a.k.lo;
                 const bool below_hi = t < a.k.hi;
-                if (below_hi && !acc) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0;
+                if (below_hi && !acc) acc = h2_minus_d2(ddx, ddy, ddz, a.k) > 0.0f;
                 // the slot after the queue's tail is free (the queue is
                 // never full at this point), so it is written always and
                 // kept if accepted
@@ -1341,6 +1341,7 @@ KernelConst pi_make_kernel_const(float rc, float cell_w)
     k.hi = nextafterf((float)(r2 * (1.0 + 4.0 * u)), INFINITY);
     k.reach2 = nextafterf((float)(r2 * (1.0 + 16.0 * u)), INFINITY);
     k.hh = h * h;
+    k.eh = fmaf(h, h, -k.hh);
     k.hh_quarter = k.hh * 0.25f;
     k.h = h;
     k.inv_h = (float)(1.0 / hd);
