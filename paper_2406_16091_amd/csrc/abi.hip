@@ -295,10 +295,9 @@ static int list_buffers(pi_cells *c, BufRef *out)
         add((void **)&c->ggz, BUF_N, 4);
         add((void **)&c->offsets2, BUF_CELLS1, 4);
         add((void **)&c->ncnt, BUF_CELLS, 4);
-        add((void **)&c->nstart, BUF_CELLS, 4);
+        add((void **)&c->nstart, BUF_CELLS1, 4);
         add((void **)&c->midx, BUF_N, 4);
         add((void **)&c->nlist, BUF_N, 8);
-        add((void **)&c->rlist, BUF_N, 4);
         add((void **)&c->scan, BUF_SCAN, 4);
     }
     return k;

@@ -115,10 +115,9 @@ struct pi_cells {
     float *grho, *ggx, *ggy, *ggz; // [cap_n] sorted sweep outputs of the last step
     int32_t *offsets2;   // [cap_cells + 1]
     int32_t *ncnt;       // [cap_cells] newcomers per cell during a step, zero between steps
-    int32_t *nstart;     // [cap_cells] start of each cell's newcomer list
+    int32_t *nstart;     // [cap_cells + 1] start of each cell's newcomer list
     int32_t *midx;       // [cap_n] a mover's place in its new cell's newcomer list
     uint2 *nlist;        // [cap_n] newcomer lists (original index, slot)
-    int32_t *rlist;      // [cap_n] cells that received a particle in the last step
     int32_t *scan;       // block partials of the offsets scan (4 x (cap_cells / 1024 + 2))
 };
 

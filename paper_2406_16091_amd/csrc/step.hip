@@ -13,12 +13,16 @@
 //      its rank among the cell's stayers; a particle that changes cell takes
 //      a place in its new cell's newcomer list (a per-cell counter); the
 //      offsets come from one scan over the cells, which also places every
-//      newcomer list and lists the cells that receive anybody; then each
-//      such cell merges its stayers (already in order) with its newcomers
-//      sorted by original index.  The result is the stable counting sort of
-//      the new positions -- ascending original index inside each cell --
-//      exactly as pi_bin would produce it, written into the other half of a
-//      double buffer whose halves then swap.
+//      newcomer list; then every particle finds its slot in the new order by
+//      counting: the stayers of its cell before it, and in a cell that
+//      receives anybody the members (stayers and newcomers) with a smaller
+//      original index.  The result is the stable counting sort of the new
+//      positions -- ascending original index inside each cell -- exactly as
+//      pi_bin would produce it, written into the other half of a double
+//      buffer whose halves then swap.  The updated state is never stored in
+//      the old order: the placement recomputes each particle's update from
+//      the old state (the same operations on the same operands, so the same
+//      bits) and writes it straight to its new slot.
 #include <math.h>
 #include <string.h>
 
@@ -40,17 +44,15 @@ struct StepArgs {
     const int32_t *off;  // offsets of the binning before the step
     const int32_t *cell; // cell of each sorted slot before the step
     const int32_t *perm;
-    float4 *xyzw;        // records, rewritten in place with the new ones
-    float4 *vel;         // velocities, rewritten in place
+    const float4 *xyzw;  // records before the step
+    const float4 *vel;   // velocities before the step
     const float *gx, *gy, *gz;
     int32_t *counts;     // stayers after the update; the new counts after the scan
     int32_t *ncnt;       // newcomers per cell (zero outside a step)
-    int32_t *nstart;     // start of each cell's newcomer list
+    int32_t *nstart;     // start of each cell's newcomer list (n_cells + 1 entries)
     int32_t *midx;       // a mover's place in its new cell's newcomer list
     uint2 *nlist;        // newcomer lists: (original index, slot before the step)
     int32_t *newcell;
-    int32_t *rlist;      // cells that receive a particle, in cell order
-    uint32_t *rcount;    // their number
     uint32_t *err;
     float dk;            // dt * kappa
     float dt;
@@ -99,16 +101,19 @@ __device__ __forceinline__ bool advance(float &u, float &v, float gacc, const St
     return cut;
 }
 
-// 1. Update every particle in place and find its new cell; the counts follow
-// the particles that change cell.
-__global__ __launch_bounds__(kBlock) void k_step_move(StepArgs a)
+// The update of the particle in sorted slot k (old state), its new record
+// relative to its new cell, and that cell.
+struct Moved {
+    float4 rec, vel;
+    int32_t cell;
+    bool cut;
+};
+
+__device__ __forceinline__ Moved move_particle(const StepArgs &a, int32_t k)
 {
-    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (k >= a.n) return;
     const GridDev &g = a.g;
-    const int32_t c = a.cell[k];
     int32_t ix, iy, iz;
-    decode(g, c, ix, iy, iz);
+    decode(g, a.cell[k], ix, iy, iz);
     const float4 r = a.xyzw[k];
     float4 v = a.vel[k];
     // box-relative coordinates, as the binning measured them
@@ -125,23 +130,37 @@ __global__ __launch_bounds__(kBlock) void k_step_move(StepArgs a)
     axis_index(x, g.ox, g.w, g.nx, jx);
     axis_index(y, g.oy, g.w, g.ny, jy);
     axis_index(z, g.oz, g.w, g.nz, jz);
-    const int32_t c2 = jx + g.nx * (jy + g.ny * jz);
-    a.xyzw[k] = make_float4(__builtin_fmaf(-(float)jx, g.w, x - g.ox), __builtin_fmaf(-(float)jy, g.w, y - g.oy),
-                            __builtin_fmaf(-(float)jz, g.w, z - g.oz), r.w);
-    a.vel[k] = make_float4(v.x, v.y, v.z, 0.0f);
-    a.newcell[k] = c2;
-    if (c2 != c) {
+    Moved m;
+    m.cell = jx + g.nx * (jy + g.ny * jz);
+    m.rec = make_float4(__builtin_fmaf(-(float)jx, g.w, x - g.ox), __builtin_fmaf(-(float)jy, g.w, y - g.oy),
+                        __builtin_fmaf(-(float)jz, g.w, z - g.oz), r.w);
+    m.vel = make_float4(v.x, v.y, v.z, 0.0f);
+    m.cut = cut;
+    return m;
+}
+
+// 1. The new cell of every particle; the counts follow the particles that
+// change cell.
+__global__ __launch_bounds__(kBlock) void k_step_move(StepArgs a)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= a.n) return;
+    const int32_t c = a.cell[k];
+    const Moved m = move_particle(a, k);
+    a.newcell[k] = m.cell;
+    if (m.cell != c) {
         atomicSub(a.counts + c, 1);
-        a.midx[k] = atomicAdd(a.ncnt + c2, 1);
+        a.midx[k] = atomicAdd(a.ncnt + m.cell, 1);
     }
-    if (cut) atomicOr(a.err, PI_DERR_STEP);
+    if (m.cut) atomicOr(a.err, PI_DERR_STEP);
 }
 
 // 2. One scan over the cells, in three passes (block totals, one
 // workgroup scanning them, each block's own scan plus its prefix), of the
 // new counts (stayers + newcomers) into the new offsets and of the
-// newcomers into the start of each cell's newcomer list; it also lists the
-// cells that receive anybody, in cell order, and finds M_C.
+// newcomers into the start of each cell's newcomer list (n_cells + 1
+// entries); it also finds M_C and leaves the newcomer counters at zero for
+// the next step.
 template <int NT>
 __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int32_t &total)
 {
@@ -159,74 +178,89 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t v, int32_t *wsum, int
     return before + inc - v;
 }
 
-// Block b's totals: sums of new counts, newcomers and receiving cells at
-// tot[0 * ns + b], tot[1 * ns + b], tot[2 * ns + b]; the largest new count
-// at tot[3 * ns + b].
+// The new counts (stayers + newcomers) and the newcomers of the kScanPer
+// cells from `base` (16-byte loads where all four are inside; zero past nc).
+static_assert(kScanPer == 4, "the scan loads four cells at once");
+__device__ __forceinline__ void load_cells(const int32_t *__restrict__ cnt, const int32_t *__restrict__ ncnt,
+                                           int64_t nc, int64_t base, int32_t *v, int32_t *nw)
+{
+    if (base + kScanPer <= nc) {
+        const int4 c4 = *reinterpret_cast<const int4 *>(cnt + base);
+        const int4 n4 = *reinterpret_cast<const int4 *>(ncnt + base);
+        nw[0] = n4.x; nw[1] = n4.y; nw[2] = n4.z; nw[3] = n4.w;
+        v[0] = c4.x + n4.x; v[1] = c4.y + n4.y; v[2] = c4.z + n4.z; v[3] = c4.w + n4.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const bool in = base + q < nc;
+            nw[q] = in ? ncnt[base + q] : 0;
+            v[q] = in ? cnt[base + q] + nw[q] : 0;
+        }
+    }
+}
+
+// Block b's totals: sums of new counts and of newcomers at tot[0 * ns + b]
+// and tot[1 * ns + b]; the largest new count at tot[2 * ns + b].
 __global__ __launch_bounds__(kScanThreads) void k_scan_totals(const int32_t *__restrict__ cnt,
                                                               const int32_t *__restrict__ ncnt, int64_t nc,
                                                               int32_t *__restrict__ tot, int32_t ns)
 {
-    __shared__ int32_t part[4][kScanThreads / 64];
+    __shared__ int32_t part[3][kScanThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
-    int32_t sc = 0, sn = 0, sr = 0, m = 0;
+    int32_t v[kScanPer], nw[kScanPer];
+    load_cells(cnt, ncnt, nc, base, v, nw);
+    int32_t sc = 0, sn = 0, m = 0;
+#pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
-        if (base + q >= nc) break;
-        const int32_t nw = ncnt[base + q];
-        const int32_t v = cnt[base + q] + nw;
-        sc += v;
-        sn += nw;
-        sr += nw > 0 ? 1 : 0;
-        m = max(m, v);
+        sc += v[q];
+        sn += nw[q];
+        m = max(m, v[q]);
     }
     sc = wave_sum(sc);
     sn = wave_sum(sn);
-    sr = wave_sum(sr);
     m = wave_max(m);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         part[0][w] = sc;
         part[1][w] = sn;
-        part[2][w] = sr;
-        part[3][w] = m;
+        part[2][w] = m;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        int32_t t0 = 0, t1 = 0, t2 = 0;
         for (int q = 0; q < kScanThreads / 64; ++q) {
             t0 += part[0][q];
             t1 += part[1][q];
-            t2 += part[2][q];
-            t3 = max(t3, part[3][q]);
+            t2 = max(t2, part[2][q]);
         }
         tot[blockIdx.x] = t0;
         tot[ns + blockIdx.x] = t1;
         tot[2 * ns + blockIdx.x] = t2;
-        tot[3 * ns + blockIdx.x] = t3;
     }
 }
 
-// One workgroup: the exclusive prefixes of the three block sums (in place),
-// the largest count into *max_per_cell, the receiving-cell total into
-// *rcount.
+// One workgroup: the exclusive prefixes of the two block sums (in place),
+// the largest count into *max_per_cell, the newcomer total into nstart[nc].
 __global__ __launch_bounds__(kBlock) void k_scan_top(int32_t *__restrict__ tot, int32_t nb, int32_t ns,
-                                                     int32_t *__restrict__ max_per_cell, uint32_t *__restrict__ rcount)
+                                                     int32_t *__restrict__ max_per_cell,
+                                                     int32_t *__restrict__ nstart, int64_t nc)
 {
     __shared__ int32_t wsum[kBlock / 64];
     __shared__ int32_t wmax[kBlock / 64];
     int32_t m = 0;
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 2; ++q) {
         int32_t *t = tot + q * ns;
         int32_t carry = 0;
         for (int32_t b0 = 0; b0 < nb; b0 += kBlock) {
             const int32_t b = b0 + (int32_t)threadIdx.x;
             const int32_t v = b < nb ? t[b] : 0;
-            if (q == 0) m = max(m, b < nb ? tot[3 * ns + b] : 0);
+            if (q == 0) m = max(m, b < nb ? tot[2 * ns + b] : 0);
             int32_t total;
             const int32_t ex = block_excl_scan<kBlock>(v, wsum, total);
             if (b < nb) t[b] = carry + ex;
             carry += total;
         }
-        if (q == 2 && threadIdx.x == 0) *rcount = (uint32_t)carry;
+        if (q == 1 && threadIdx.x == 0) nstart[nc] = carry;
     }
     m = wave_max(m);
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
@@ -238,137 +272,104 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(int32_t *__restrict__ tot, 
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t *__restrict__ cnt,
-                                                             const int32_t *__restrict__ ncnt, int64_t nc,
-                                                             const int32_t *__restrict__ tot, int32_t ns,
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int32_t *__restrict__ cnt, int32_t *__restrict__ ncnt,
+                                                             int64_t nc, const int32_t *__restrict__ tot, int32_t ns,
                                                              int32_t *__restrict__ off, int32_t *__restrict__ nstart,
-                                                             int32_t *__restrict__ rlist, int32_t n)
+                                                             int32_t n)
 {
     __shared__ int32_t wsum[kScanThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
-    int32_t v[kScanPer], nw[kScanPer], sc = 0, sn = 0, sr = 0;
+    int32_t v[kScanPer], nw[kScanPer], sc = 0, sn = 0;
+    load_cells(cnt, ncnt, nc, base, v, nw);
+#pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
-        const bool in = base + q < nc;
-        nw[q] = in ? ncnt[base + q] : 0;
-        v[q] = in ? cnt[base + q] + nw[q] : 0;
         sc += v[q];
         sn += nw[q];
-        sr += nw[q] > 0 ? 1 : 0;
     }
     int32_t total;
     int32_t ec = tot[blockIdx.x] + block_excl_scan<kScanThreads>(sc, wsum, total);
     int32_t en = tot[ns + blockIdx.x] + block_excl_scan<kScanThreads>(sn, wsum, total);
-    int32_t er = tot[2 * ns + blockIdx.x] + block_excl_scan<kScanThreads>(sr, wsum, total);
+    int32_t eo[kScanPer], es[kScanPer];
+#pragma unroll
     for (int q = 0; q < kScanPer; ++q) {
-        const int64_t c = base + q;
-        if (c < nc) {
-            off[c] = ec;
-            nstart[c] = en;
-            cnt[c] = v[q];
-            if (nw[q] > 0) rlist[er++] = (int32_t)c;
-        }
+        eo[q] = ec;
+        es[q] = en;
         ec += v[q];
         en += nw[q];
     }
+    if (base + kScanPer <= nc) {
+        *reinterpret_cast<int4 *>(off + base) = make_int4(eo[0], eo[1], eo[2], eo[3]);
+        *reinterpret_cast<int4 *>(nstart + base) = make_int4(es[0], es[1], es[2], es[3]);
+        *reinterpret_cast<int4 *>(cnt + base) = make_int4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            if (base + q < nc) {
+                off[base + q] = eo[q];
+                nstart[base + q] = es[q];
+                cnt[base + q] = v[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q)
+        if (nw[q] != 0) ncnt[base + q] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) off[nc] = n;
 }
 
-__device__ __forceinline__ void place(const StepArgs &a, int32_t c, int32_t s, int32_t from)
+// The particle in old slot k, whose update is m, to slot s of cell c in the
+// new order.
+__device__ __forceinline__ void place_moved(const StepArgs &a, int32_t c, int32_t s, int32_t k, const Moved &m)
 {
     if (s >= a.off2[c + 1]) { // cannot happen: the counts add up
         atomicOr(a.err, PI_DERR_INTERNAL);
         return;
     }
-    a.perm2[s] = a.perm[from];
+    a.perm2[s] = a.perm[k];
     a.cell2[s] = c;
-    a.xyzw2[s] = a.xyzw[from];
-    a.vel2[s] = a.vel[from];
+    a.xyzw2[s] = m.rec;
+    a.vel2[s] = m.vel;
 }
 
-// 3a. One thread per slot: a particle that changed cell enters its new
-// cell's newcomer list; a particle that stays in a cell nobody enters keeps
-// its rank among the cell's stayers (a short loop over the cell's earlier
-// slots) and is placed at once.
-__global__ __launch_bounds__(kBlock) void k_step_place_stayers(StepArgs a)
+// Stayers of cell c in old slots before k (old slots of a cell are in
+// ascending original index).
+__device__ __forceinline__ int32_t stayers_before(const StepArgs &a, int32_t c, int32_t k)
+{
+    int32_t r = 0;
+    for (int32_t j = a.off[c]; j < k; ++j) r += a.newcell[j] == c ? 1 : 0;
+    return r;
+}
+
+// 3a. The newcomer lists: one thread per old slot, a particle that changed
+// cell writes (original index, old slot) at its place in its new cell's list.
+__global__ __launch_bounds__(kBlock) void k_step_list(StepArgs a)
+{
+    const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (k >= a.n) return;
+    const int32_t c2 = a.newcell[k];
+    if (c2 != a.cell[k]) a.nlist[a.nstart[c2] + a.midx[k]] = make_uint2((uint32_t)a.perm[k], (uint32_t)k);
+}
+
+// 3b. One thread per old slot (coalesced reads of the particle's own state):
+// its slot in its new cell is the number of the cell's members with a
+// smaller original index -- stayers (old slots of the cell still in it; for
+// a stayer, those before it) and newcomers (the cell's newcomer list, empty
+// for most cells).
+__global__ __launch_bounds__(kBlock) void k_step_place(StepArgs a)
 {
     const int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (k >= a.n) return;
     const int32_t c = a.cell[k], c2 = a.newcell[k];
-    if (c2 != c) {
-        a.nlist[a.nstart[c2] + a.midx[k]] = make_uint2((uint32_t)a.perm[k], (uint32_t)k);
-        return;
-    }
-    if (a.ncnt[c] > 0) return;
+    const Moved m = move_particle(a, k);
+    const int32_t o = a.perm[k];
     int32_t r = 0;
-    for (int32_t j = a.off[c]; j < k; ++j) r += a.newcell[j] == c ? 1 : 0;
-    place(a, c, a.off2[c] + r, k);
-}
-
-// 3b. One thread per receiving cell: its newcomers sorted by original index
-// (up to kNew in LDS by insertion; more are ranked by counting within the
-// list), merged with the cell's stayers, which are in that order already;
-// then the cell's newcomer counter goes back to zero.
-constexpr int kPlaceBlock = 128;
-constexpr int kNew = 32;
-
-__global__ __launch_bounds__(kPlaceBlock) void k_step_place_cells(StepArgs a)
-{
-    __shared__ int32_t norig[kNew][kPlaceBlock];
-    __shared__ int32_t nslot[kNew][kPlaceBlock];
-    const int t = threadIdx.x;
-    const uint32_t m = *a.rcount;
-    for (uint32_t e = blockIdx.x * kPlaceBlock + t; e < m; e += gridDim.x * kPlaceBlock) {
-        const int32_t c = a.rlist[e];
-        const int32_t nn = a.ncnt[c], nb0 = a.nstart[c];
-        const int32_t i0 = a.off[c], i1 = a.off[c + 1];
-        const int32_t s = a.off2[c];
-        if (nn <= kNew) {
-            for (int32_t q0 = 0; q0 < nn; ++q0) {
-                const uint2 e2 = a.nlist[nb0 + q0];
-                const int32_t o = (int32_t)e2.x;
-                int q = q0;
-                while (q > 0 && norig[q - 1][t] > o) {
-                    norig[q][t] = norig[q - 1][t];
-                    nslot[q][t] = nslot[q - 1][t];
-                    --q;
-                }
-                norig[q][t] = o;
-                nslot[q][t] = (int32_t)e2.y;
-            }
-            // merge the stayers (old slots of c still in c) with the newcomers
-            int32_t i = i0, q = 0, d = s;
-            while (i < i1 && a.newcell[i] != c) ++i;
-            while (i < i1 || q < nn) {
-                if (q == nn || (i < i1 && a.perm[i] < norig[q][t])) {
-                    place(a, c, d++, i);
-                    ++i;
-                    while (i < i1 && a.newcell[i] != c) ++i;
-                } else {
-                    place(a, c, d++, nslot[q][t]);
-                    ++q;
-                }
-            }
-        } else {
-            // many newcomers: rank each particle by counting
-            int32_t rank = 0;
-            for (int32_t i = i0; i < i1; ++i) {
-                if (a.newcell[i] != c) continue;
-                const int32_t o = a.perm[i];
-                int32_t r = rank++;
-                for (int32_t q = 0; q < nn; ++q) r += (int32_t)a.nlist[nb0 + q].x < o ? 1 : 0;
-                place(a, c, s + r, i);
-            }
-            for (int32_t q0 = 0; q0 < nn; ++q0) {
-                const uint2 e2 = a.nlist[nb0 + q0];
-                const int32_t o = (int32_t)e2.x;
-                int32_t r = 0;
-                for (int32_t q = 0; q < nn; ++q) r += (int32_t)a.nlist[nb0 + q].x < o ? 1 : 0;
-                for (int32_t i = i0; i < i1; ++i) r += (a.newcell[i] == c && a.perm[i] < o) ? 1 : 0;
-                place(a, c, s + r, (int32_t)e2.y);
-            }
-        }
-        a.ncnt[c] = 0;
+    if (c2 == c) {
+        r = stayers_before(a, c, k);
+    } else {
+        for (int32_t j = a.off[c2]; j < a.off[c2 + 1]; ++j) r += (a.newcell[j] == c2 && a.perm[j] < o) ? 1 : 0;
     }
+    for (int32_t q = a.nstart[c2]; q < a.nstart[c2 + 1]; ++q) r += (int32_t)a.nlist[q].x < o ? 1 : 0;
+    place_moved(a, c2, a.off2[c2] + r, k, m);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather_velocity(int32_t n, const int32_t *__restrict__ perm,
@@ -493,7 +494,7 @@ extern "C" pi_status pi_step(pi_ctx *ctx, pi_cells *cells, const pi_step_opts *o
     a.gz = cells->ggz;
     a.counts = cells->counts;
     // the newcomer counters are zero between steps: zeroed once after an
-    // allocation, and back to zero at the end of every step
+    // allocation, and back to zero in every step's scan
     if (!cells->ncnt_zeroed) {
         PI_CHECK_HIP(hipMemsetAsync(cells->ncnt, 0, (size_t)std::max<int64_t>(nc, 1) * sizeof(int32_t), s));
         cells->ncnt_zeroed = true;
@@ -503,8 +504,6 @@ extern "C" pi_status pi_step(pi_ctx *ctx, pi_cells *cells, const pi_step_opts *o
     a.midx = cells->midx;
     a.nlist = cells->nlist;
     a.newcell = cells->newcell;
-    a.rlist = cells->rlist;
-    a.rcount = cells->d_err + 40;
     a.err = cells->d_err;
     a.dt = o.dt;
     a.dk = o.dt * o.kappa;
@@ -516,20 +515,19 @@ extern "C" pi_status pi_step(pi_ctx *ctx, pi_cells *cells, const pi_step_opts *o
     a.xyzw2 = cells->xyzw2;
     a.vel2 = cells->vel2;
     PI_LAUNCH(ctx, "k_step_move", k_step_move, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
-    // 3. new offsets, newcomer lists, receiving cells and M_C
+    // 3. new offsets, newcomer list starts and M_C
     const int32_t nb = (int32_t)((nc + kScanBlock - 1) / kScanBlock);
     const int32_t ns = (int32_t)(nc / kScanBlock + 2);
     int32_t *tot = cells->scan;
     PI_LAUNCH(ctx, "k_scan_totals", k_scan_totals, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cells->counts,
               cells->ncnt, nc, tot, ns);
-    PI_LAUNCH(ctx, "k_scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, tot, nb, ns, cells->max_per_cell, a.rcount);
+    PI_LAUNCH(ctx, "k_scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, tot, nb, ns, cells->max_per_cell,
+              cells->nstart, nc);
     PI_LAUNCH(ctx, "k_scan_apply", k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cells->counts,
-              cells->ncnt, nc, tot, ns, cells->offsets2, cells->nstart, cells->rlist, (int32_t)n);
-    // 4. the new stable order: stayers of cells nobody enters, then every
-    //    cell that receives a particle (a persistent grid over their list)
-    PI_LAUNCH(ctx, "k_step_place_stayers", k_step_place_stayers, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
-    const unsigned pcb = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (n + kPlaceBlock - 1) / kPlaceBlock));
-    PI_LAUNCH(ctx, "k_step_place_cells", k_step_place_cells, dim3(pcb), dim3(kPlaceBlock), 0, s, a);
+              cells->ncnt, nc, tot, ns, cells->offsets2, cells->nstart, (int32_t)n);
+    // 4. the newcomer lists, then the new stable order
+    PI_LAUNCH(ctx, "k_step_list", k_step_list, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
+    PI_LAUNCH(ctx, "k_step_place", k_step_place, dim3(nblocks(n, kBlock)), dim3(kBlock), 0, s, a);
     PI_CHECK_HIP(hipGetLastError());
     std::swap(cells->perm, cells->perm2);
     std::swap(cells->cell, cells->cell2);
