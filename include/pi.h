@@ -335,8 +335,8 @@ pi_status pi_interact_pairfn(pi_ctx *ctx, const pi_cells *cells, const pi_pairfn
  * which are the stepped values whenever they lie on a common power-of-two
  * lattice with the origin and cell width.  With rho .. gz (all or none) it
  * also writes the sweep outputs of the last step (at the positions before
- * it; PI_ESTATE before the first step).  The first call allocates about 80
- * bytes per particle and 12 per cell of stepping buffers on the object.
+ * it; PI_ESTATE before the first step).  The first call allocates 88 bytes
+ * per particle and 12 per cell of stepping buffers on the object.
  */
 typedef struct pi_step_opts {
     float dt;         /* time step (>= 0) */
