@@ -107,6 +107,9 @@ CASES = {
     # clustered, unit cells, 2^-18 lattice: dense cells receive and lose many
     "clustered": (lambda: synth.box_system(30_000, 14, seed=903, lattice_log2=18, clustered_blobs=3), 0.3,
                   0.001, 2.0 ** -18),
+    # 15^3 cells: a cell count that is not a multiple of four (the scan's
+    # last cells take its element-wise path)
+    "odd_grid": (lambda: synth.box_system(8_000, 15, seed=904, lattice_log2=18), 0.2, 0.001, 2.0 ** -18),
 }
 
 
