@@ -254,7 +254,10 @@ pi_status pi_batch_run_orgs(pi_ctx *ctx, pi_batch *b, int32_t nsys, const pi_sys
         int t = pi_pick_tile(o, ppc);
         if (t < 0) return PI_EINVAL;
         if (o.sweep == PI_SWEEP_AUTO) t = pi_auto_tile(ctx, o.precision, sys[s].n, ppc);
-        if (org && org[s] >= 0) t = org[s];
+        if (org && org[s] >= 0) {
+            if (!pi_org_valid(org[s])) return PI_EINVAL;
+            t = org[s];
+        }
         b->tile_of[s] = pi_batch_org(t);
     }
     // sweep table: systems grouped by organisation (caller's order within a

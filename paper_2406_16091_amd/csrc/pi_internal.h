@@ -272,6 +272,7 @@ void pi_tile_opts(int tile_id, pi_interact_opts *out);
 int pi_auto_tile(pi_ctx *ctx, int precision, int64_t n, double ppc);
 int64_t pi_batch_layout(int tile_id, SysDev *h_sys, int32_t nsys);
 int pi_batch_org(int tile_id);
+bool pi_org_valid(int id);
 // A batch object that launches its sequence directly on every call instead
 // of capturing it into a graph (for layouts used a few times only); the
 // tables are rebuilt only when the layout changes.

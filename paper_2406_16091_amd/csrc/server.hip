@@ -692,7 +692,11 @@ extern "C" pi_status pi_submit(pi_server *s, const pi_request *r, uint64_t *tick
         memcpy(h + 3 * r->n, r->w, b);
     }
     Ticket *t = new (std::nothrow) Ticket();
-    if (!t) return PI_ENOMEM;
+    if (!t) {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->pool.emplace_back(bytes, pin);
+        return PI_ENOMEM;
+    }
     t->req = *r;
     t->req.x = t->req.y = t->req.z = t->req.w = nullptr;
     t->footprint = fp;

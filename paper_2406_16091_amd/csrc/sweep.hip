@@ -1580,6 +1580,14 @@ bool pi_tile_shape(int tile_id, int *tx, int *ty, int *tz)
     return false;
 }
 
+// Whether id names an organisation: 0 (no LDS), the stream sweep, or an
+// entry of the tile table.
+bool pi_org_valid(int id)
+{
+    int tx, ty, tz;
+    return id == 0 || id == kStreamId || pi_tile_shape(id, &tx, &ty, &tz);
+}
+
 // The explicit options (organisation and tile shape) that run organisation
 // `tile`; precision and order are left as they are.
 void pi_tile_opts(int tile, pi_interact_opts *out)
