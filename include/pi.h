@@ -370,7 +370,9 @@ pi_status pi_sync(pi_ctx *ctx, pi_cells *cells, pi_stream stream);
  * 16 on) once per size and occupancy class -- buckets
  * of log2(n) and of the mean particles per cell -- on the caller's stream,
  * and reuses the fastest for that class afterwards (per context).  Tuning
- * runs the sweep once per candidate and waits for the stream.  In
+ * runs each candidate once untimed, then keeps the fastest of up to three
+ * timed runs (a candidate already 1.5x slower than the best so far stops
+ * after one), and waits for the stream.  In
  * PI_TUNE_STATIC mode (or with PI_AUTOTUNE=off in the environment) AUTO uses
  * a fixed rule on the mean occupancy instead: the 6x6x6 sub-box while its
  * staged halo is expected to fit in LDS (mean + 6 standard deviations of a
