@@ -103,19 +103,19 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, inv: bool = True):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summaries (profiles/traffic_*.md), or None if none matches the current
-    kernel sources.  Among the template instances that match, the one with
-    the invariant reduction on (and not the batch form) is preferred when
-    `inv` is set, since that is the instance the timed step launches."""
+def _profile_value(tag: str, pattern: str, kernel: str, inv: bool):
+    """Value of the `tag` line for `kernel` in the committed summaries
+    profiles/`pattern`, or None if none matches the current kernel sources.
+    Among the template instances that match, the one with the invariant
+    reduction on (and not the batch form) is preferred when `inv` is set,
+    since that is the instance the timed step launches."""
     import glob
     want, cur = kernel_key(kernel), source_hash()
     found = []
-    for p in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+    for p in sorted(glob.glob(os.path.join(ROOT, "profiles", pattern))):
         with open(p) as f:
             for line in f:
-                if line.startswith("TRAFFIC "):
+                if line.startswith(tag + " "):
                     parts = line.split()
                     name, val, h = " ".join(parts[1:-2]), parts[-2], parts[-1]
                     key = kernel_key(name)
@@ -130,6 +130,20 @@ def measured_traffic(kernel: str, inv: bool = True):
             if name.replace(" ", "").endswith(",true,false>"):
                 return val
     return found[0][1]
+
+
+def measured_traffic(kernel: str, inv: bool = True):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries (profiles/traffic_*.md: FETCH_SIZE and WRITE_SIZE scaled by a
+    copy kernel's), or None if none matches the current kernel sources."""
+    return _profile_value("TRAFFIC", "traffic_*.md", kernel, inv)
+
+
+def measured_valu_issue(kernel: str, inv: bool = True):
+    """Microseconds of VALU issue per launch of `kernel` (SQ_INSTS_VALU x 4
+    cycles over the 1024 SIMDs at 2.4 GHz) from the committed counter
+    summaries (profiles/sqcounters_*.md), or None."""
+    return _profile_value("VALUISSUE", "sqcounters_*.md", kernel, inv)
 
 
 def candidates_from_counts(counts: np.ndarray, dims) -> int:
@@ -611,6 +625,11 @@ def main():
         roof["traffic_over_algorithmic_bytes"] = round(traffic / by, 3) if traffic and by else None
         if flops:
             roof["fp32_frac_of_157TF"] = round(flops / avg_s / 1e12 / FP32_PEAK_TFLOPS, 4)
+        # the VALU issue time the committed instruction counters give for the
+        # kernel, against its measured time: near 1 means bound by VALU issue
+        issue = measured_valu_issue(name)
+        roof["valu_issue_us"] = round(issue, 1) if issue else None
+        roof["valu_issue_over_time"] = round(issue / (avg_s * 1e6), 3) if issue else None
         bin_us = sum(v[1] for k, v in kt.items() if not k.startswith(("k_sweep", "k_inv"))) * 1e3 / nbreak
         sw = [(k, v) for k, v in kt.items() if k.startswith("k_sweep")]
         sweep_us = sum(v[1] for _, v in sw) * 1e3 / nbreak
