@@ -16,6 +16,28 @@ def test_kernel_key_matches_library_and_profiler_names():
     assert bench.kernel_key("k_cell_ranges") == "k_cell_ranges"
 
 
+def test_profile_lines_match_only_the_current_sources(tmp_path, monkeypatch):
+    """Traffic and VALU-issue figures come from the committed summaries only
+    while the kernel sources are those they were taken on; a timing name
+    without template arguments matches its instances, the instance with the
+    invariants on and not the batch form first."""
+    h = bench.source_hash()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "traffic_x.md").write_text(
+        f"TRAFFIC k_sweep_tile<6, 6, 6, 768, 4, 0, false, false> 1.0e8 {h}\n"
+        f"TRAFFIC k_sweep_tile<6, 6, 6, 768, 4, 0, true, false> 2.0e8 {h}\n"
+        f"TRAFFIC k_sweep_nolds<0, true, false> 3.0e8 0000000000000000\n")
+    (prof / "sqcounters_x.md").write_text(f"VALUISSUE k_sweep_tile<6, 6, 6, 768, 4, 0, true, false> 1052.5 {h}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: h)
+    assert bench.measured_traffic("k_sweep_tile<6,6,6>") == 2.0e8
+    assert bench.measured_traffic("k_sweep_tile<6,6,6>", inv=False) == 1.0e8
+    assert bench.measured_traffic("k_sweep_nolds") is None  # taken on other sources
+    assert bench.measured_valu_issue("k_sweep_tile<6,6,6>") == 1052.5
+    assert bench.measured_valu_issue("k_sweep_stream") is None
+
+
 def test_candidate_count_is_the_clipped_stencil_sum():
     # brute force on a small occupancy field: sum over cells of
     # count * (sources in the clipped 27-cell block) minus the targets themselves
