@@ -232,3 +232,22 @@ def test_full_size_step_rebinning(dev):
     st = ds.state()
     _check_binning(ds, st["x"], st["y"], st["z"], s)
     ds.close()
+
+
+def test_full_size_clustered_step_rebinning(dev):
+    """The clustered set at full size (2^23 particles, 64 blobs, cells of
+    sixty and more particles): one step, and the incremental re-binning
+    (many newcomers per dense cell, ranked by counting) against the
+    oracle's full binning of the new positions."""
+    s = synth.clustered()
+    rng = np.random.default_rng(961)
+    vel = [rng.normal(0, 0.05 * s.cell_w, s.n).astype(np.float32) for _ in range(3)]
+    ds = dev.DeviceSystem(s)
+    ds.bin()
+    ds.set_velocity(*vel)
+    ds.step(0.25, 0.001 * s.rc ** 5, 2.0 ** -24)
+    ds.sync()
+    st = ds.state()
+    b = _check_binning(ds, st["x"], st["y"], st["z"], s)
+    _say(f"[step] clustered full size: M_C {b.max_per_cell}")
+    ds.close()
